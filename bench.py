@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark of Fourier-accelerated steepest-descent Landau gauge fixing.
+
+Workload: one 32^4 SU(3) lattice (V = 2^20 sites) from the seeded generator
+(U = g exp(i eps H) g^dag(x+mu), eps for mean plaquette 0.6), alpha 0.08,
+FP64, links stored as two rows (12 reals).  A "step" is one iteration of
+Algorithm 1 (filter, g, gauge transform, Delta/F/theta), on links resident in
+HBM.  Printed as one JSON line:
+
+  value          iterations per second (K timed iterations, no profiling)
+  roofline       the dominant kernel (fused transform + Delta + (x,y) FFT):
+                 algorithmic bytes per launch / its mean duration from HIP
+                 events on the library's stream in a second, profiled pass
+  time_to_theta  wall time of lgf_fix to theta < 1e-15 for FP64 (12- and
+                 18-real) and mixed FP32/FP64, from freshly loaded links
+  cpu_baseline   the FP64 oracle on this host's cores, a bounded sample
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+PAPER_C2070_ITERS_PER_S = 16.35    # 32^4, DP, 12-real, texture, ECC off (Table 3)
+
+
+def alg_bytes(V, s, R):
+    """Algorithmic HBM bytes: per iteration and per launch of each kernel.
+
+    Per site and iteration: links read and written once (8R reals), g written
+    and read once (2R), the packed Delta (8 reals) written once, read and
+    written once by the (z, t) pass, and read once for g (32 reals).
+    """
+    return {
+        "iteration": V * s * (8 * R + 2 * R + 32),
+        "transform_measure": V * s * (4 * R + 4 * R + R + 8),
+        "zt_fft_scale": V * s * 16,
+        "gauge": V * s * (8 + R),
+    }
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("su3.hpp", "fft.hpp", "kernels.hpp", "lgf.hip"):
+        with open(os.path.join(ROOT, "paper_1206_0675_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, dims, storage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    key = f"{kernel}@{'x'.join(map(str, dims))}/{storage}"
+    e = rec.get(key)
+    if not e or e.get("source_digest") != source_digest():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dims", type=int, nargs=4, default=[32, 32, 32, 32])
+    ap.add_argument("--storage", type=int, default=12, choices=[12, 18])
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the time-to-theta runs")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported. "
+              "A multi-GPU layout is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1206_0675_amd import lgf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    L = lgf.load_library()
+    dims = tuple(args.dims)
+    V = synth.volume(dims)
+    t = time.time()
+    U = synth.random_links(dims, args.seed)
+    print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    R = args.storage
+    ab = alg_bytes(V, 8, R)
+
+    # ---- timed iterations (no profiling) -----------------------------------
+    with lgf.Context(dims, lib=L, storage=R) as ctx:
+        ctx.load(U)
+        ctx.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(args.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    dt = t1 - t0
+    iters_per_s = args.steps / dt
+    print(f"# {args.steps} iterations in {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    # ---- profiled pass: per-kernel durations from HIP events ----------------
+    with lgf.Context(dims, lib=L, storage=R, profile=1) as ctx:
+        ctx.load(U)
+        ctx.step(args.warmup)
+        ctx.profile_reset()
+        ctx.step(args.steps)
+        prof = ctx.profile()
+    kernels = {}
+    for name in ("transform_measure", "zt_fft_scale", "gauge", "reduce"):
+        n, ms = prof.get(name, (0, 0.0))
+        if n:
+            avg_s = ms / n / 1e3
+            k = {"launches": n, "avg_us": round(avg_s * 1e6, 2)}
+            if name in ab:
+                k["alg_bytes"] = ab[name]
+                k["gbps"] = round(ab[name] / avg_s / 1e9, 1)
+                k["frac"] = round(ab[name] / avg_s / 1e9 / HBM_PEAK_GBPS, 4)
+            kernels[name] = k
+    dom = kernels["transform_measure"]
+    achieved = dom["gbps"]
+    traffic = measured_traffic("transform_measure", dims, R)
+
+    # ---- time to theta < 1e-15 ---------------------------------------------
+    extras = {}
+    if not args.no_extras:
+        for label, kw in (("fp64_12real", dict(storage=12)), ("fp64_18real", dict(storage=18)),
+                          ("mixed_12real", dict(storage=12, precision=lgf.MIXED)),
+                          ("mixed_18real", dict(storage=18, precision=lgf.MIXED))):
+            with lgf.Context(dims, lib=L, poll_every=8, **kw) as ctx:
+                ctx.load(U)
+                ctx.measure()
+                torch.cuda.synchronize()
+                s = ctx.fix()
+            extras[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "iters_fp32": s.iter_fp32,
+                             "F": s.F, "theta": s.theta}
+
+    # ---- CPU baseline: the FP64 oracle on this host -------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.opts(store12=(R == 12))
+        t = time.perf_counter()
+        oracle.step(dims, U, 1, o)
+        t_a = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.step(dims, U, 7, o)
+        t_b = time.perf_counter() - t
+        cpu = {"value": round(6 / (t_b - t_a), 4), "unit": "iters/s", "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"FP64 oracle (plain C, OpenMP) on the same {'x'.join(map(str, dims))} lattice: "
+                         f"rate = 6 / (t(7 updates) - t(1 update)), {t_a + t_b:.1f}s of CPU work"}
+
+    it_bytes = ab["iteration"]
+    line = {
+        "metric": "FA-SD iters/s and time to theta<1e-15 on 32^4 SU(3); HBM GB/s; learned vs plain",
+        "value": round(iters_per_s, 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) FA-SD iteration, FP64, {R}-real links, alpha 0.08",
+                   "dims": list(dims), "storage": R, "seed": args.seed, "generator": "g exp(i eps H) g^dag, plaquette 0.6"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "kernel": "transform_measure", "alg_bytes_per_launch": ab["transform_measure"]},
+        "iteration_alg_gbps": round(it_bytes * iters_per_s / 1e9, 1),
+        "iteration_frac": round(it_bytes * iters_per_s / 1e9 / HBM_PEAK_GBPS, 4),
+        "kernels": kernels,
+        "time_to_theta": extras,
+        "cpu_baseline": cpu,
+        "context": {"paper_c2070_iters_per_s": PAPER_C2070_ITERS_PER_S,
+                    "device": torch.cuda.get_device_name(0), "source_digest": source_digest()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * lgf.h -- C ABI of the MI355X (gfx950) library for Landau gauge fixing of
+ * SU(3) lattice gauge fields by Fourier-accelerated steepest descent
+ * (N. Cardoso, P. J. Silva, P. Bicudo, O. Oliveira, "Landau Gauge Fixing on
+ * GPUs", Comput. Phys. Commun., arXiv:1206.0675).
+ *
+ * The method (Section 2 of the paper): maximise over the gauge orbit
+ *     F_U[g] = 1/(4 N_c V) sum_x sum_mu Re Tr g(x) U_mu(x) g^dag(x + mu)
+ * by iterating (Algorithm 1)
+ *     Delta(x) = sum_nu [U_nu(x - nu) - U_nu(x) - h.c. - trace]
+ *     g(x)     = exp[ FFT^-1 (alpha/2) (p2max/p2) FFT Delta ](x)     (eq. gx)
+ *                (to first order in alpha, then projected to SU(3))
+ *     U_mu(x) -> g(x) U_mu(x) g^dag(x + mu)
+ * until theta = 1/(N_c V) sum_x Tr Delta(x) Delta^dag(x) < 1e-15.
+ *
+ * Conventions for every call
+ *   - Return value: LGF_OK (0) or a negative LGF_E_* code.  No C++ exception
+ *     crosses this boundary.  lgf_last_error() describes the last failure of
+ *     a context; lgf_strerror() names a code.
+ *   - The library never keeps a caller's pointer after a call returns: data
+ *     is copied in and out.  A context owns all the device memory it uses.
+ *   - Pointers tagged `where` are host memory (LGF_HOST) or device memory of
+ *     the current HIP device (LGF_DEVICE, e.g. torch.Tensor.data_ptr()).
+ *     Device pointers are used in stream order on the context's stream.
+ *   - Canonical link layout (host or device): FP64, 72 doubles per site,
+ *     double index ((((t*Lz + z)*Ly + y)*Lx + x)*4 + mu)*18 + (3*i + j)*2 + c,
+ *     mu = 0..3 for x, y, z, t, c = 0 (real) / 1 (imaginary): x fastest, as
+ *     the lexicographic (x, y, z, t) order of Section 3.  Per-site matrix
+ *     fields (the gauge transformation G) use 18 doubles per site, same order.
+ *   - Periodic boundary conditions in all four directions.
+ *   - Shapes: each extent a power of two in [4, 128]; in addition the (x, y)
+ *     plane and the (z, t) plane must fit the LDS of one workgroup
+ *     (FP64: Lx*Ly <= 2048 and Lz*Lt <= 8192).  Otherwise
+ *     LGF_E_UNSUPPORTED_SHAPE, returned before any device call.
+ *   - A context is used by one host thread at a time; distinct contexts are
+ *     independent.
+ */
+#ifndef LGF_H
+#define LGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LGF_OK 0
+#define LGF_E_INVALID_ARG (-1)       /* NULL pointer, bad enum, alpha <= 0, ...            */
+#define LGF_E_UNSUPPORTED_SHAPE (-2) /* extent not a power of two in [4,128], plane too big */
+#define LGF_E_OUT_OF_MEMORY (-3)     /* device allocation failed                            */
+#define LGF_E_DEVICE (-4)            /* a HIP runtime call failed                           */
+#define LGF_E_NOT_UNITARY (-5)       /* input link with |UU^dag-1| or |det U-1| > tolerance */
+#define LGF_E_NONFINITE (-6)         /* NaN/Inf in the input, or theta became non-finite    */
+#define LGF_E_NOT_CONVERGED (-7)     /* max_iter reached with theta >= theta_stop           */
+#define LGF_E_STATE (-8)             /* call not valid now (e.g. step before load)          */
+
+/* where a caller's buffer lives */
+#define LGF_HOST 0
+#define LGF_DEVICE 1
+
+/* arithmetic precision of the iteration */
+#define LGF_FP64 0   /* every iteration in FP64                                          */
+#define LGF_FP32 1   /* every iteration in FP32 (F, theta sums and g projection in FP64) */
+#define LGF_MIXED 2  /* FP32 until theta < theta_switch, then the links are rebuilt in
+                        FP64 as G U0 G^dag(x+mu) and FP64 iterations finish the run       */
+
+/* link storage (Section 3.2): full matrix, or the first two rows with the
+ * third rebuilt as (a x b)^* when read */
+#define LGF_STORE18 18
+#define LGF_STORE12 12
+
+/* step kind */
+#define LGF_STEP_PLAIN 0  /* eq. gx: (alpha/2) p2max/p2 */
+
+/* acceleration kernel */
+#define LGF_ACCEL_FOURIER 1  /* K(p) = p2max/p2, K(0) = 0 (eq. gx)                       */
+#define LGF_ACCEL_NONE 0     /* K(p) = 1: plain steepest descent (the same update without
+                                Fourier acceleration, Section 2)                          */
+
+typedef struct lgf_params {
+    int32_t dims[4];        /* Lx, Ly, Lz, Lt                                           */
+    int32_t precision;      /* LGF_FP64 | LGF_FP32 | LGF_MIXED                           */
+    int32_t storage;        /* LGF_STORE18 | LGF_STORE12                                 */
+    int32_t step;           /* LGF_STEP_PLAIN                                            */
+    int32_t accel;          /* LGF_ACCEL_FOURIER | LGF_ACCEL_NONE                        */
+    int32_t track_gauge;    /* 1: accumulate G = ... g2 g1 so that U = G U0 G^dag(x+mu)
+                               (always on in LGF_MIXED); needed by lgf_store_gauge      */
+    int32_t profile;        /* 1: time every kernel launch with HIP events               */
+    double alpha;           /* step size, paper: 0.08                                    */
+    double theta_stop;      /* stop when theta < theta_stop, paper: 1e-15                */
+    double theta_switch;    /* LGF_MIXED: leave FP32 when theta < theta_switch (1e-6)    */
+    double unit_tol;        /* lgf_load_links rejects links beyond this (1e-12); <= 0
+                               skips the check                                           */
+    int64_t max_iter;       /* lgf_fix gives up after this many gauge transformations    */
+    int32_t poll_every;     /* lgf_fix reads theta back after this many iterations       */
+    int32_t reserved;
+    void *stream;           /* hipStream_t to run on; NULL: the context creates its own */
+} lgf_params;
+
+typedef struct lgf_stats {
+    int64_t iter;           /* gauge transformations applied since the last load         */
+    int64_t iter_fp32;      /* ... of which in FP32                                      */
+    int64_t iter_fp64;      /* ... of which in FP64                                      */
+    int64_t reserved;
+    double F;               /* functional of the current links                           */
+    double theta;           /* convergence measure of the current links                  */
+    double seconds;         /* wall time of the call                                     */
+    int32_t phase;          /* 0: FP32 arithmetic, 1: FP64 arithmetic                    */
+    int32_t status;         /* the call's return code                                    */
+} lgf_stats;
+
+typedef struct lgf_context *lgf_ctx;
+
+/* Defaults: dims 0, LGF_FP64, LGF_STORE18, LGF_STEP_PLAIN, LGF_ACCEL_FOURIER,
+ * alpha 0.08, theta_stop 1e-15 (Section 2), theta_switch 1e-6, unit_tol 1e-12,
+ * max_iter 100000, poll_every 16, stream NULL.  Host only. */
+int32_t lgf_default_params(lgf_params *p);
+
+/* Check canonical FP64 links on the host, without a context or a GPU: every
+ * entry finite, |U U^dag - 1|_max <= tol and |det U - 1| <= tol.  first_bad
+ * (may be NULL) receives the index of the first failing link (site*4 + mu) or
+ * -1.  Returns LGF_OK, LGF_E_NONFINITE or LGF_E_NOT_UNITARY. */
+int32_t lgf_validate_links(const int32_t dims[4], const double *links, double tol, int64_t *first_bad);
+
+/* Validate params (host only: LGF_E_INVALID_ARG / LGF_E_UNSUPPORTED_SHAPE),
+ * then allocate the context's device buffers on the current device. */
+int32_t lgf_create(const lgf_params *p, lgf_ctx *out);
+
+/* Free everything; NULL is accepted. */
+int32_t lgf_destroy(lgf_ctx ctx);
+
+/* Copy in canonical FP64 links (where = LGF_HOST or LGF_DEVICE), check them
+ * against unit_tol, lay them out on the device, reset G = 1 and the
+ * iteration count.  On error the previous state is invalid (LGF_E_STATE
+ * until the next successful load). */
+int32_t lgf_load_links(lgf_ctx ctx, const void *links, int32_t where);
+
+/* Copy the current links out in canonical FP64. */
+int32_t lgf_store_links(lgf_ctx ctx, void *links, int32_t where);
+
+/* Accumulated gauge transformation G (18 doubles per site), such that the
+ * current links are G(x) U0(x) G^dag(x+mu) for the loaded links U0.  Needs
+ * track_gauge or LGF_MIXED.  lgf_load_gauge replaces G (checkpoint resume). */
+int32_t lgf_store_gauge(lgf_ctx ctx, void *G, int32_t where);
+int32_t lgf_load_gauge(lgf_ctx ctx, const void *G, int32_t where);
+
+/* F and theta of the current links (Section 2); no update. */
+int32_t lgf_measure(lgf_ctx ctx, lgf_stats *out);
+
+/* Exactly n iterations of Algorithm 1 with no stop test, in the current
+ * precision phase.  trace (n + 1 entries, or NULL) receives F and theta of
+ * the links before the first update and after each update. */
+int32_t lgf_step(lgf_ctx ctx, int64_t n, lgf_stats *trace);
+
+/* Algorithm 1: iterate until theta < theta_stop (LGF_OK) or max_iter
+ * (LGF_E_NOT_CONVERGED).  theta is read back every poll_every iterations;
+ * iterations queued after convergence do nothing.  In LGF_MIXED the FP32
+ * phase ends at theta < theta_switch and the run finishes in FP64. */
+int32_t lgf_fix(lgf_ctx ctx, lgf_stats *out);
+
+/* Per-kernel timing collected when params.profile = 1: for kernel k < n
+ * (names from lgf_kernel_name), the number of launches and their summed
+ * duration in milliseconds measured with HIP events on the context's stream.
+ * count receives the number of kernels known.  lgf_profile_reset clears. */
+int32_t lgf_profile_read(lgf_ctx ctx, int64_t *launches, double *total_ms, int32_t n, int32_t *count);
+int32_t lgf_profile_reset(lgf_ctx ctx);
+const char *lgf_kernel_name(int32_t k);
+
+/* Bytes of device memory the context holds. */
+int32_t lgf_device_bytes(lgf_ctx ctx, int64_t *bytes);
+
+const char *lgf_strerror(int32_t code);
+const char *lgf_last_error(lgf_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,448 @@
+// HIP kernels of one Fourier-accelerated steepest-descent iteration
+// (Algorithm 1 of Cardoso, Silva, Bicudo, Oliveira, arXiv:1206.0675) on a
+// 4D periodic lattice, for gfx950.
+//
+// One iteration is three launches plus a one-block reduction:
+//   k_measure<APPLY_G>  U' = g U g^dag(x+mu) (Section 2), Delta(x) of U'
+//                       packed to 8 reals, per-site F and theta terms, and
+//                       the forward 2D FFT over each (x, y) plane in LDS.
+//   k_zt                forward 2D FFT over (z, t), multiply by
+//                       (alpha/2) p2max / (p^2 V) (eq. gx), inverse (z, t).
+//   k_gauge             inverse 2D FFT over (x, y) and
+//                       g = reunit(1 + (alpha/2) dtilde), stored for the
+//                       next k_measure (optionally G <- g G).
+//   k_reduce            F and theta from per-plane partial sums, in a fixed
+//                       order; sets the convergence flag.
+// Every kernel returns at once when the device flag `done` is set, so
+// iterations queued past convergence cost only their launches.
+//
+// Site index s = q * NP + p with p = y * Lx + x (plane offset) and
+// q = t * Lz + z (plane index).  Delta after the (x, y) transform is kept in
+// a tiled layout: element (field c, plane position p, plane q) at
+//   D[((p / W) * 4 + c) * NQ + q) * W + p % W]
+// so the (x, y) kernels read and write runs of W consecutive complex values
+// and the (z, t) kernel reads one contiguous block of NQ * W values.
+#pragma once
+#include "fft.hpp"
+#include "su3.hpp"
+
+namespace lgf {
+
+struct Geo {
+    int L[4];       // Lx, Ly, Lz, Lt
+    int logL[4];
+    int NP, logNP;  // Lx * Ly
+    int NQ, logNQ;  // Lz * Lt
+    int W, logW;    // tile width of the Delta layout
+    int64_t V;
+};
+
+struct DevState {
+    int64_t iter;        // gauge transformations applied so far
+    double F, theta;     // of the current links
+    double theta_stop;   // done once theta < theta_stop
+    int32_t done;
+    int32_t nonfinite;
+};
+
+// plane index handled by this block: consecutive planes stay on one XCD
+// (blocks are dealt to the 8 XCDs round robin), so the z neighbours a
+// block reads are in the same L2.
+__device__ __forceinline__ int plane_of_block(int b, int nq)
+{
+    if ((nq & 7) != 0) return b;
+    return (b & 7) * (nq >> 3) + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// block-wide sum of two doubles through LDS, fixed order
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_sum2(double a, double b, double* red, int tid, int nth,
+                                           double* out_a, double* out_b)
+{
+    red[2 * tid] = a;
+    red[2 * tid + 1] = b;
+    __syncthreads();
+    for (int h = nth >> 1; h > 0; h >>= 1) {
+        if (tid < h) {
+            red[2 * tid] += red[2 * (tid + h)];
+            red[2 * tid + 1] += red[2 * (tid + h) + 1];
+        }
+        __syncthreads();
+    }
+    *out_a = red[0];
+    *out_b = red[1];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// a0: canonical FP64 [s][mu][3][3] -> SoA links of type T; validation
+// ---------------------------------------------------------------------------
+// dev[0], dev[1]: max |U U^dag - 1| and |det U - 1| as double bit patterns
+// (non-negative doubles order like their bit patterns); dev[2]: number of
+// links with a non-finite entry.
+template <typename T, int NE>
+__global__ void __launch_bounds__(256) k_load(int64_t V, const double* __restrict__ src,
+                                              C2<T>* __restrict__ U, unsigned long long* __restrict__ dev)
+{
+    __shared__ double red[2 * 256];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    const int64_t li = (int64_t)blockIdx.x * blockDim.x + tid;
+    double du = 0.0, dd = 0.0;
+    if (li < 4 * V) {
+        const int64_t s = li >> 2;
+        const int mu = (int)(li & 3);
+        M3<double> m;
+        const C2<double>* p = reinterpret_cast<const C2<double>*>(src) + li * 9;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) m.e[e] = p[e];
+        bool finite = true;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) finite = finite && isfinite(m.e[e].x) && isfinite(m.e[e].y);
+        if (!finite) {
+            atomicAdd(&bad, 1);
+        } else {
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    C2<double> acc = mk<double>(i == j ? -1.0 : 0.0, 0.0);
+                    for (int k = 0; k < 3; ++k) acc = acc + cmulc(m.e[3 * i + k], m.e[3 * j + k]);
+                    du = fmax(du, sqrt(acc.x * acc.x + acc.y * acc.y));
+                }
+            C2<double> det = cmul(m.e[0], cmul(m.e[4], m.e[8]) - cmul(m.e[5], m.e[7]));
+            det = det - cmul(m.e[1], cmul(m.e[3], m.e[8]) - cmul(m.e[5], m.e[6]));
+            det = det + cmul(m.e[2], cmul(m.e[3], m.e[7]) - cmul(m.e[4], m.e[6]));
+            dd = sqrt((det.x - 1.0) * (det.x - 1.0) + det.y * det.y);
+        }
+#pragma unroll
+        for (int e = 0; e < NE; ++e) U[(mu * NE + e) * V + s] = mk<T>((T)m.e[e].x, (T)m.e[e].y);
+    }
+    // block max
+    red[2 * tid] = du;
+    red[2 * tid + 1] = dd;
+    __syncthreads();
+    for (int h = blockDim.x >> 1; h > 0; h >>= 1) {
+        if (tid < h) {
+            red[2 * tid] = fmax(red[2 * tid], red[2 * (tid + h)]);
+            red[2 * tid + 1] = fmax(red[2 * tid + 1], red[2 * (tid + h) + 1]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        atomicMax(&dev[0], (unsigned long long)__double_as_longlong(red[0]));
+        atomicMax(&dev[1], (unsigned long long)__double_as_longlong(red[1]));
+        if (bad) atomicAdd(&dev[2], (unsigned long long)bad);
+    }
+}
+
+// SoA links of type T -> canonical FP64, third row rebuilt when NE = 6.
+template <typename T, int NE>
+__global__ void __launch_bounds__(256) k_store(int64_t V, const C2<T>* __restrict__ U, double* __restrict__ dst)
+{
+    const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (li >= 4 * V) return;
+    const int64_t s = li >> 2;
+    const int mu = (int)(li & 3);
+    M3<T> m;
+    load_mat<T, NE>(m, U + (int64_t)mu * NE * V, V, s);
+    C2<double>* p = reinterpret_cast<C2<double>*>(dst) + li * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) p[e] = mk<double>((double)m.e[e].x, (double)m.e[e].y);
+}
+
+// per-site matrix field (g or G): canonical FP64 [s][3][3] <-> SoA
+template <typename T, int NE>
+__global__ void __launch_bounds__(256) k_field_store(int64_t V, const C2<T>* __restrict__ f, double* __restrict__ dst)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    M3<T> m;
+    load_mat<T, NE>(m, f, V, s);
+    C2<double>* p = reinterpret_cast<C2<double>*>(dst) + s * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) p[e] = mk<double>((double)m.e[e].x, (double)m.e[e].y);
+}
+
+template <typename T, int NE>
+__global__ void __launch_bounds__(256) k_field_load(int64_t V, const double* __restrict__ src, C2<T>* __restrict__ f)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const C2<double>* p = reinterpret_cast<const C2<double>*>(src) + s * 9;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) f[e * V + s] = mk<T>((T)p[e].x, (T)p[e].y);
+}
+
+template <typename T, int NE>
+__global__ void __launch_bounds__(256) k_field_identity(int64_t V, C2<T>* __restrict__ f)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) f[e * V + s] = mk<T>((e == 0 || e == 4 || e == 8) ? T(1) : T(0), T(0));
+}
+
+// ---------------------------------------------------------------------------
+// a1 + a2 + a3(x, y):  gauge transform, Delta, F and theta terms, forward
+// (x, y) FFT of the packed Delta.  One block per (z, t) plane.
+// ---------------------------------------------------------------------------
+template <typename T, int NE, bool APPLY_G>
+__global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restrict__ Uin, C2<T>* __restrict__ Uout,
+                                                 const C2<T>* __restrict__ g, C2<T>* __restrict__ D,
+                                                 double* __restrict__ partial, const C2<T>* __restrict__ twx,
+                                                 const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    double* red = lds_raw;                                   // 2 * blockDim doubles
+    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x);   // 4 fields x NP
+
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int q = plane_of_block(blockIdx.x, geo.NQ);
+    const int Lx = geo.L[0], Ly = geo.L[1], Lz = geo.L[2], Lt = geo.L[3];
+    const int NP = geo.NP;
+    const int64_t V = geo.V;
+    const int z = q & (Lz - 1), t = q >> geo.logL[2];
+    const int64_t qzp = (int64_t)(t * Lz + ((z + 1) & (Lz - 1))) * NP;
+    const int64_t qzm = (int64_t)(t * Lz + ((z - 1) & (Lz - 1))) * NP;
+    const int64_t qtp = (int64_t)(((t + 1) & (Lt - 1)) * Lz + z) * NP;
+    const int64_t qtm = (int64_t)(((t - 1) & (Lt - 1)) * Lz + z) * NP;
+    const int64_t q0 = (int64_t)q * NP;
+
+    double fsum = 0.0, tsum = 0.0;
+    for (int p = tid; p < NP; p += nth) {
+        const int x = p & (Lx - 1), y = p >> geo.logL[0];
+        const int64_t s = q0 + p;
+        const int64_t fwd[4] = {q0 + y * Lx + ((x + 1) & (Lx - 1)), q0 + (((y + 1) & (Ly - 1)) * Lx + x),
+                                qzp + p, qtp + p};
+        const int64_t bwd[4] = {q0 + y * Lx + ((x - 1) & (Lx - 1)), q0 + (((y - 1) & (Ly - 1)) * Lx + x),
+                                qzm + p, qtm + p};
+        Alg8<T> acc;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc.c[c] = mk<T>(T(0), T(0));
+        M3<T> gx;
+        if (APPLY_G) load_mat<T, NE>(gx, g, V, s);
+        double f = 0.0;
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            M3<T> u;
+            load_mat<T, NE>(u, Uin + (int64_t)mu * NE * V, V, s);
+            if (APPLY_G) {
+                M3<T> gn, r;
+                load_mat<T, NE>(gn, g, V, fwd[mu]);
+                a_u_bdag(gx, u, gn, r);
+                store_mat<T, NE>(r, Uout + (int64_t)mu * NE * V, V, s);
+                u = r;
+            }
+            f += (double)u.e[0].x + (double)u.e[4].x + (double)u.e[8].x;
+            alg_accumulate(acc, u, T(-1));
+        }
+#pragma unroll 1
+        for (int nu = 0; nu < 4; ++nu) {
+            M3<T> u;
+            load_mat<T, NE>(u, Uin + (int64_t)nu * NE * V, V, bwd[nu]);
+            if (APPLY_G) {
+                M3<T> gb, r;
+                load_mat<T, NE>(gb, g, V, bwd[nu]);
+                a_u_bdag(gb, u, gx, r);
+                u = r;
+            }
+            alg_accumulate(acc, u, T(1));
+        }
+        fsum += f;
+        tsum += alg_norm2(acc);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) buf[c * NP + p] = acc.c[c];
+    }
+    double fb, tb;
+    block_sum2(fsum, tsum, red, tid, nth, &fb, &tb);
+    if (tid == 0) {
+        partial[2 * q] = fb;
+        partial[2 * q + 1] = tb;
+    }
+    // forward FFT along x, then y, of the four fields
+    fft_dif(buf, Lines{geo.logL[0], geo.logL[1], 2, Lx, NP, 1}, twx, tid, nth);
+    fft_dif(buf, Lines{geo.logL[1], geo.logL[0], 2, 1, NP, Lx}, twy, tid, nth);
+    const int W = geo.W;
+    for (int i = tid; i < 4 * NP; i += nth) {
+        const int c = i >> geo.logNP, p = i & (NP - 1);
+        D[((int64_t)((p >> geo.logW) * 4 + c) * geo.NQ + q) * W + (p & (W - 1))] = buf[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a3(z, t) + a4 + a5(z, t): one block per (tile of W plane positions, field)
+// ---------------------------------------------------------------------------
+// ptab: four tables 4 sin^2(pi n / L_mu) indexed by the bit-reversed
+// position (x table first), so ptab[off_mu + pos] belongs to mode n = bitrev(pos).
+// accel = 1: factor c0 / p^2 with c0 = (alpha/2) p2max / V, zero at p = 0;
+// accel = 0 (plain steepest descent): the constant c0 = (alpha/2) / V.
+template <typename T>
+__global__ void __launch_bounds__(256) k_zt(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
+                                            const C2<T>* __restrict__ twt, const double* __restrict__ ptab,
+                                            double c0, int accel, const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
+    const int W = geo.W, NQ = geo.NQ, n = NQ * W;
+    C2<T>* src = D + (int64_t)(j * 4 + c) * NQ * W;
+    for (int i = tid; i < n; i += nth) buf[i] = src[i];
+    __syncthreads();
+    const int Lz = geo.L[2];
+    fft_dif(buf, Lines{geo.logL[2], geo.logW, geo.logL[3], 1, Lz * W, W}, twz, tid, nth);
+    fft_dif(buf, Lines{geo.logL[3], geo.logL[2] + geo.logW, 0, 1, 0, Lz * W}, twt, tid, nth);
+    const double* tx = ptab;
+    const double* ty = tx + geo.L[0];
+    const double* tz = ty + geo.L[1];
+    const double* tt = tz + geo.L[2];
+    for (int i = tid; i < n; i += nth) {
+        const int w = i & (W - 1), qq = i >> geo.logW;
+        const int p = j * W + w;
+        const double p2 = tx[p & (geo.L[0] - 1)] + ty[p >> geo.logL[0]] + tz[qq & (Lz - 1)] + tt[qq >> geo.logL[2]];
+        const T f = (T)(accel ? (p2 > 0.0 ? c0 / p2 : 0.0) : c0);
+        buf[i] = scale(buf[i], f);
+    }
+    __syncthreads();
+    fft_dit(buf, Lines{geo.logL[3], geo.logL[2] + geo.logW, 0, 1, 0, Lz * W}, twt, tid, nth);
+    fft_dit(buf, Lines{geo.logL[2], geo.logW, geo.logL[3], 1, Lz * W, W}, twz, tid, nth);
+    for (int i = tid; i < n; i += nth) src[i] = buf[i];
+}
+
+// ---------------------------------------------------------------------------
+// a5(x, y) + a6 (+ a8): inverse (x, y) FFT, g = reunit(1 + dtilde) in FP64,
+// and optionally G <- reunit(g G).  One block per (z, t) plane.
+// ---------------------------------------------------------------------------
+template <typename T, int NE, bool ACC_G>
+__global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict__ D, C2<T>* __restrict__ g,
+                                               C2<T>* __restrict__ G, const C2<T>* __restrict__ twx,
+                                               const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int q = plane_of_block(blockIdx.x, geo.NQ);
+    const int NP = geo.NP, W = geo.W;
+    const int64_t V = geo.V;
+    for (int i = tid; i < 4 * NP; i += nth) {
+        const int c = i >> geo.logNP, p = i & (NP - 1);
+        buf[i] = D[((int64_t)((p >> geo.logW) * 4 + c) * geo.NQ + q) * W + (p & (W - 1))];
+    }
+    __syncthreads();
+    fft_dit(buf, Lines{geo.logL[1], geo.logL[0], 2, 1, NP, geo.L[0]}, twy, tid, nth);
+    fft_dit(buf, Lines{geo.logL[0], geo.logL[1], 2, geo.L[0], NP, 1}, twx, tid, nth);
+    const int64_t q0 = (int64_t)q * NP;
+    for (int p = tid; p < NP; p += nth) {
+        C2<double> c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = mk<double>((double)buf[k * NP + p].x, (double)buf[k * NP + p].y);
+        M3<double> m;
+        one_plus_alg_reunit(c, m);
+        const int64_t s = q0 + p;
+        store_mat<T, NE>(cast_mat<T>(m), g, V, s);
+        if (ACC_G) {
+            M3<T> Gt;
+            load_mat<T, NE>(Gt, G, V, s);
+            M3<double> Gd = cast_mat<double>(Gt), r;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    C2<double> acc = cmul(m.e[3 * i], Gd.e[k]);
+                    acc = acc + cmul(m.e[3 * i + 1], Gd.e[3 + k]);
+                    acc = acc + cmul(m.e[3 * i + 2], Gd.e[6 + k]);
+                    r.e[3 * i + k] = acc;
+                }
+            reunit(r);
+            store_mat<T, NE>(cast_mat<T>(r), G, V, s);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a7: F = sum/(12V), theta = sum/(3V) over the per-plane partials, in plane
+// order; counts the update, records (F, theta), sets the stop flag.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partial, int nq, int64_t V,
+                                                DevState* __restrict__ st, double* __restrict__ trace,
+                                                int counts_update)
+{
+    if (st->done) return;
+    __shared__ double red[2 * 256];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    double a = 0.0, b = 0.0;
+    for (int i = tid; i < nq; i += nth) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    double fs, ts;
+    block_sum2(a, b, red, tid, nth, &fs, &ts);
+    if (tid == 0) {
+        const double F = fs / (12.0 * (double)V), th = ts / (3.0 * (double)V);
+        if (counts_update) st->iter += 1;
+        st->F = F;
+        st->theta = th;
+        if (trace) {
+            trace[0] = F;
+            trace[1] = th;
+        }
+        if (!(th == th) || th > 1e300) {
+            st->nonfinite = 1;
+            st->done = 1;
+        } else if (th < st->theta_stop) {
+            st->done = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a9: precision switch.  U_mu(x) = G(x) U0_mu(x) G^dag(x + mu) in FP64 from
+// the FP64 links as loaded and the FP32-accumulated gauge, reunitarised in
+// FP64 (so the result lies exactly on the gauge orbit of the input); the
+// promoted gauge is stored as G64.
+// ---------------------------------------------------------------------------
+template <int NE>
+__global__ void __launch_bounds__(256) k_promote_gauge(int64_t V, const C2<float>* __restrict__ G32,
+                                                       C2<double>* __restrict__ G64)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    M3<float> a;
+    load_mat<float, NE>(a, G32, V, s);
+    M3<double> m = cast_mat<double>(a);
+    reunit(m);
+    store_mat<double, NE>(m, G64, V, s);
+}
+
+template <int NE>
+__global__ void __launch_bounds__(256) k_switch(Geo geo, const C2<double>* __restrict__ U0, const C2<double>* __restrict__ G,
+                                                C2<double>* __restrict__ U)
+{
+    const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t V = geo.V;
+    if (li >= 4 * V) return;
+    const int mu = (int)(li / V);
+    const int64_t s = li - (int64_t)mu * V;
+    int64_t rem = s;
+    int c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k] = (int)(rem & (geo.L[k] - 1));
+        rem >>= geo.logL[k];
+    }
+    c[mu] = (c[mu] + 1) & (geo.L[mu] - 1);
+    const int64_t sn = (((int64_t)c[3] * geo.L[2] + c[2]) * geo.L[1] + c[1]) * geo.L[0] + c[0];
+    M3<double> a, u, b, r;
+    load_mat<double, NE>(a, G, V, s);
+    load_mat<double, NE>(u, U0 + (int64_t)mu * NE * V, V, s);
+    load_mat<double, NE>(b, G, V, sn);
+    a_u_bdag(a, u, b, r);
+    store_mat<double, NE>(r, U + (int64_t)mu * NE * V, V, s);
+}
+
+}  // namespace lgf

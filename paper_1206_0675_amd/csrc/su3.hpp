@@ -1,0 +1,191 @@
+// Device-side complex and SU(3) arithmetic for the gauge-fixing kernels.
+//
+// Storage conventions (one complex per element, structure of arrays):
+//   link field  U[(mu * NE + e) * V + s]   mu = 0..3, e = 0..NE-1
+//   gauge field g[e * V + s]
+// NE = 9 stores the full 3x3 matrix; NE = 6 stores its first two rows and
+// rebuilds the third as (a x b)^*, exact for SU(3) (the 12-real
+// parameterisation of Section 3.2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lgf {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) C2 {
+    T x, y;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> mk(T a, T b) { C2<T> r; r.x = a; r.y = b; return r; }
+template <typename T>
+__device__ __forceinline__ C2<T> operator+(C2<T> a, C2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ C2<T> operator-(C2<T> a, C2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) { return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) { return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+template <typename T>
+__device__ __forceinline__ C2<T> conjg(C2<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ C2<T> scale(C2<T> a, T f) { return mk<T>(a.x * f, a.y * f); }
+// i * a and -i * a
+template <typename T>
+__device__ __forceinline__ C2<T> mul_i(C2<T> a) { return mk<T>(-a.y, a.x); }
+template <typename T>
+__device__ __forceinline__ C2<T> mul_mi(C2<T> a) { return mk<T>(a.y, -a.x); }
+
+template <typename T>
+struct M3 {
+    C2<T> e[9];
+};
+
+// third row = (first row x second row)^*
+template <typename T>
+__device__ __forceinline__ void rebuild_row3(M3<T>& m)
+{
+    m.e[6] = conjg(cmul(m.e[1], m.e[5]) - cmul(m.e[2], m.e[4]));
+    m.e[7] = conjg(cmul(m.e[2], m.e[3]) - cmul(m.e[0], m.e[5]));
+    m.e[8] = conjg(cmul(m.e[0], m.e[4]) - cmul(m.e[1], m.e[3]));
+}
+
+template <typename T, int NE>
+__device__ __forceinline__ void load_mat(M3<T>& m, const C2<T>* __restrict__ base, int64_t stride, int64_t s)
+{
+#pragma unroll
+    for (int e = 0; e < NE; ++e) m.e[e] = base[e * stride + s];
+    if (NE == 6) rebuild_row3(m);
+}
+
+template <typename T, int NE>
+__device__ __forceinline__ void store_mat(const M3<T>& m, C2<T>* __restrict__ base, int64_t stride, int64_t s)
+{
+#pragma unroll
+    for (int e = 0; e < NE; ++e) base[e * stride + s] = m.e[e];
+}
+
+// r = a * u * b^dagger
+template <typename T>
+__device__ __forceinline__ void a_u_bdag(const M3<T>& a, const M3<T>& u, const M3<T>& b, M3<T>& r)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        C2<T> au[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            C2<T> s = cmul(a.e[3 * i], u.e[k]);
+            s = s + cmul(a.e[3 * i + 1], u.e[3 + k]);
+            s = s + cmul(a.e[3 * i + 2], u.e[6 + k]);
+            au[k] = s;
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            C2<T> s = cmulc(au[0], b.e[3 * l]);
+            s = s + cmulc(au[1], b.e[3 * l + 1]);
+            s = s + cmulc(au[2], b.e[3 * l + 2]);
+            r.e[3 * i + l] = s;
+        }
+    }
+}
+
+// The eight real degrees of freedom of u - u^dagger - (1/3) Tr(u - u^dagger):
+// p[0] = (.)_01, p[1] = (.)_02, p[2] = (.)_12 (complex), and
+// p[3] = Im(.)_00 + i Im(.)_11.  The rest follow from anti-Hermiticity and
+// tracelessness.
+template <typename T>
+struct Alg8 {
+    C2<T> c[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void alg_accumulate(Alg8<T>& acc, const M3<T>& u, T sign)
+{
+    const T third = T(2) / T(3);
+    C2<T> p0 = u.e[1] - conjg(u.e[3]);
+    C2<T> p1 = u.e[2] - conjg(u.e[6]);
+    C2<T> p2 = u.e[5] - conjg(u.e[7]);
+    T tr = third * (u.e[0].y + u.e[4].y + u.e[8].y);
+    C2<T> p3 = mk<T>(T(2) * u.e[0].y - tr, T(2) * u.e[4].y - tr);
+    acc.c[0] = acc.c[0] + scale(p0, sign);
+    acc.c[1] = acc.c[1] + scale(p1, sign);
+    acc.c[2] = acc.c[2] + scale(p2, sign);
+    acc.c[3] = acc.c[3] + scale(p3, sign);
+}
+
+// |Delta|^2 = sum_ij |Delta_ij|^2 from the packed form (Delta_22 = -i(a + b)).
+template <typename T>
+__device__ __forceinline__ double alg_norm2(const Alg8<T>& d)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s += 2.0 * ((double)d.c[c].x * d.c[c].x + (double)d.c[c].y * d.c[c].y);
+    double a = d.c[3].x, b = d.c[3].y;
+    return s + a * a + b * b + (a + b) * (a + b);
+}
+
+// 1 + D for a packed anti-Hermitian traceless D, projected to SU(3) by row
+// Gram-Schmidt (row 3 = (row 1 x row 2)^*), in double precision.
+__device__ __forceinline__ void one_plus_alg_reunit(const C2<double> c[4], M3<double>& m)
+{
+    const double a = c[3].x, b = c[3].y;
+    C2<double> r0[3] = {mk<double>(1.0, a), c[0], c[1]};
+    C2<double> r1[3] = {mk<double>(-c[0].x, c[0].y), mk<double>(1.0, b), c[2]};
+    double n0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n0 += r0[j].x * r0[j].x + r0[j].y * r0[j].y;
+    n0 = 1.0 / sqrt(n0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r0[j] = scale(r0[j], n0);
+    // <r0, r1> = sum_j conj(r0_j) r1_j
+    C2<double> ip = mk<double>(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) ip = ip + cmul(conjg(r0[j]), r1[j]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r1[j] = r1[j] - cmul(ip, r0[j]);
+    double n1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n1 += r1[j].x * r1[j].x + r1[j].y * r1[j].y;
+    n1 = 1.0 / sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r1[j] = scale(r1[j], n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { m.e[j] = r0[j]; m.e[3 + j] = r1[j]; }
+    rebuild_row3(m);
+}
+
+// Row Gram-Schmidt projection of a general 3x3 matrix to SU(3), in double.
+__device__ __forceinline__ void reunit(M3<double>& m)
+{
+    double n0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n0 += m.e[j].x * m.e[j].x + m.e[j].y * m.e[j].y;
+    n0 = 1.0 / sqrt(n0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[j] = scale(m.e[j], n0);
+    C2<double> ip = mk<double>(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) ip = ip + cmul(conjg(m.e[j]), m.e[3 + j]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[3 + j] = m.e[3 + j] - cmul(ip, m.e[j]);
+    double n1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n1 += m.e[3 + j].x * m.e[3 + j].x + m.e[3 + j].y * m.e[3 + j].y;
+    n1 = 1.0 / sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[3 + j] = scale(m.e[3 + j], n1);
+    rebuild_row3(m);
+}
+
+template <typename TO, typename TI>
+__device__ __forceinline__ M3<TO> cast_mat(const M3<TI>& a)
+{
+    M3<TO> r;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) r.e[e] = mk<TO>((TO)a.e[e].x, (TO)a.e[e].y);
+    return r;
+}
+
+}  // namespace lgf

@@ -1,0 +1,234 @@
+"""Python binding of the C ABI in include/lgf.h (argument marshalling only).
+
+Every step of the iteration runs in the HIP library liblgf.so built from
+csrc/ for gfx950; this module only converts arguments.  If the library is
+missing, loading fails with an error that says how to build it: there is no
+fallback.
+
+Arrays: links are complex128 (or float64 views) in the canonical layout
+(Lt, Lz, Ly, Lx, 4, 3, 3); the gauge field G is (Lt, Lz, Ly, Lx, 3, 3);
+dims are (Lx, Ly, Lz, Lt).  A torch tensor on the GPU is passed as a device
+pointer (LGF_DEVICE); numpy arrays as host memory (LGF_HOST).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_LIB = os.path.join(_HERE, "liblgf.so")
+
+OK = 0
+E_INVALID_ARG, E_UNSUPPORTED_SHAPE, E_OUT_OF_MEMORY, E_DEVICE = -1, -2, -3, -4
+E_NOT_UNITARY, E_NONFINITE, E_NOT_CONVERGED, E_STATE = -5, -6, -7, -8
+HOST, DEVICE = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
+STORE18, STORE12 = 18, 12
+STEP_PLAIN = 0
+ACCEL_NONE, ACCEL_FOURIER = 0, 1
+
+
+class Params(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 4), ("precision", C.c_int32), ("storage", C.c_int32),
+                ("step", C.c_int32), ("accel", C.c_int32), ("track_gauge", C.c_int32),
+                ("profile", C.c_int32), ("alpha", C.c_double), ("theta_stop", C.c_double),
+                ("theta_switch", C.c_double), ("unit_tol", C.c_double), ("max_iter", C.c_int64),
+                ("poll_every", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iter", C.c_int64), ("iter_fp32", C.c_int64), ("iter_fp64", C.c_int64),
+                ("reserved", C.c_int64), ("F", C.c_double), ("theta", C.c_double),
+                ("seconds", C.c_double), ("phase", C.c_int32), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class LgfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_libs = {}
+
+
+def load_library(path: str | None = None):
+    """Load the C ABI library (default: the gfx950 build next to this file)."""
+    path = os.path.abspath(path or os.environ.get("LGF_LIBRARY", DEFAULT_LIB))
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1206_0675_amd.build` "
+                          "(hipcc --offload-arch=gfx950); there is no fallback implementation")
+    L = C.CDLL(path)
+    P, S, V, I32, I64 = C.POINTER(Params), C.POINTER(Stats), C.c_void_p, C.c_int32, C.c_int64
+    ctx_p = C.POINTER(C.c_void_p)
+    sig = {
+        "lgf_default_params": ([P], I32),
+        "lgf_validate_links": ([C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_double, C.POINTER(I64)], I32),
+        "lgf_create": ([P, ctx_p], I32),
+        "lgf_destroy": ([V], I32),
+        "lgf_load_links": ([V, V, I32], I32),
+        "lgf_store_links": ([V, V, I32], I32),
+        "lgf_store_gauge": ([V, V, I32], I32),
+        "lgf_load_gauge": ([V, V, I32], I32),
+        "lgf_measure": ([V, S], I32),
+        "lgf_step": ([V, I64, S], I32),
+        "lgf_fix": ([V, S], I32),
+        "lgf_profile_read": ([V, C.POINTER(I64), C.POINTER(C.c_double), I32, C.POINTER(I32)], I32),
+        "lgf_profile_reset": ([V], I32),
+        "lgf_kernel_name": ([I32], C.c_char_p),
+        "lgf_device_bytes": ([V, C.POINTER(I64)], I32),
+        "lgf_strerror": ([I32], C.c_char_p),
+        "lgf_last_error": ([V], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes, fn.restype = args, res
+    _libs[path] = L
+    return L
+
+
+def default_params(dims, lib=None, **kw) -> Params:
+    L = lib or load_library()
+    p = Params()
+    L.lgf_default_params(C.byref(p))
+    p.dims[:] = [int(d) for d in dims]
+    for k, v in kw.items():
+        if k == "stream":
+            v = v if v is None or isinstance(v, int) else int(v)
+        setattr(p, k, v)
+    return p
+
+
+def validate_links(dims, links, tol=1e-12, lib=None):
+    """(status, first_bad) from the host-only check of canonical FP64 links."""
+    L = lib or load_library()
+    a = np.ascontiguousarray(links).view(np.float64)
+    d = (C.c_int32 * 4)(*[int(x) for x in dims])
+    bad = C.c_int64()
+    rc = L.lgf_validate_links(d, a.ctypes.data_as(C.POINTER(C.c_double)), float(tol), C.byref(bad))
+    return rc, bad.value
+
+
+def _buffer(x):
+    """(pointer, where, keepalive) for a numpy array or a torch tensor."""
+    if isinstance(x, np.ndarray):
+        if not x.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data, HOST, x
+    if hasattr(x, "data_ptr") and hasattr(x, "is_cuda"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr(), (DEVICE if x.is_cuda else HOST), x
+    raise TypeError("expected a numpy array or a torch tensor")
+
+
+class Context:
+    """One lattice configuration on the GPU (lgf_create ... lgf_destroy)."""
+
+    def __init__(self, dims, lib=None, params: Params | None = None, **kw):
+        self.lib = lib or load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.params = params if params is not None else default_params(self.dims, self.lib, **kw)
+        h = C.c_void_p()
+        rc = self.lib.lgf_create(C.byref(self.params), C.byref(h))
+        if rc != OK:
+            raise LgfError(rc, self.lib.lgf_last_error(None).decode())
+        self.h = h
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lgf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LgfError(rc, self.lib.lgf_last_error(self.h).decode())
+        return rc
+
+    @property
+    def shape(self):
+        lx, ly, lz, lt = self.dims
+        return (lt, lz, ly, lx)
+
+    # -- data --------------------------------------------------------------
+    def load(self, links):
+        ptr, where, _keep = _buffer(links)
+        self._check(self.lib.lgf_load_links(self.h, C.c_void_p(ptr), where))
+
+    def store(self, out=None):
+        if out is None:
+            out = np.empty(self.shape + (4, 3, 3), dtype=np.complex128)
+        ptr, where, _keep = _buffer(out)
+        self._check(self.lib.lgf_store_links(self.h, C.c_void_p(ptr), where))
+        return out
+
+    def store_gauge(self, out=None):
+        if out is None:
+            out = np.empty(self.shape + (3, 3), dtype=np.complex128)
+        ptr, where, _keep = _buffer(out)
+        self._check(self.lib.lgf_store_gauge(self.h, C.c_void_p(ptr), where))
+        return out
+
+    def load_gauge(self, G):
+        ptr, where, _keep = _buffer(G)
+        self._check(self.lib.lgf_load_gauge(self.h, C.c_void_p(ptr), where))
+
+    # -- iteration ---------------------------------------------------------
+    def measure(self) -> Stats:
+        s = Stats()
+        self._check(self.lib.lgf_measure(self.h, C.byref(s)))
+        return s
+
+    def step(self, n: int, trace: bool = False):
+        """n updates; with trace, arrays (F[n+1], theta[n+1])."""
+        if not trace:
+            self._check(self.lib.lgf_step(self.h, int(n), None))
+            return None
+        tr = (Stats * (n + 1))()
+        self._check(self.lib.lgf_step(self.h, int(n), tr))
+        return np.array([t.F for t in tr]), np.array([t.theta for t in tr])
+
+    def fix(self, raise_on_error=True) -> Stats:
+        s = Stats()
+        rc = self.lib.lgf_fix(self.h, C.byref(s))
+        if raise_on_error:
+            self._check(rc)
+        return s
+
+    # -- profiling -----------------------------------------------------------
+    def profile(self):
+        n = 32
+        launches, ms, cnt = (C.c_int64 * n)(), (C.c_double * n)(), C.c_int32()
+        self._check(self.lib.lgf_profile_read(self.h, launches, ms, n, C.byref(cnt)))
+        out = {}
+        for k in range(min(cnt.value, n)):
+            if launches[k]:
+                out[self.lib.lgf_kernel_name(k).decode()] = (int(launches[k]), float(ms[k]))
+        return out
+
+    def profile_reset(self):
+        self._check(self.lib.lgf_profile_reset(self.h))
+
+    def device_bytes(self):
+        b = C.c_int64()
+        self._check(self.lib.lgf_device_bytes(self.h, C.byref(b)))
+        return b.value

@@ -1,0 +1,150 @@
+// CPU stand-in for the small part of the HIP API the gauge-fixing library
+// uses.  TEST INFRASTRUCTURE: it lets the unmodified HIP sources be compiled
+// by g++ and run on the host (one std::thread per GPU thread, a std::barrier
+// per __syncthreads, blocks one after another) so that index arithmetic,
+// bounds and barrier placement can be checked on a machine without a GPU,
+// with AddressSanitizer.  It is never part of the library that runs on the GPU.
+#pragma once
+#include <algorithm>
+#include <atomic>
+#include <barrier>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __restrict__ __restrict
+// one block runs at a time, so a function-static array is exactly the
+// block's shared memory
+#define __shared__ static
+
+struct dim3 {
+    unsigned x, y, z;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+
+namespace emu {
+inline thread_local dim3 tidx;
+inline dim3 bidx, bdim, gdim;
+inline std::barrier<>* bar = nullptr;
+inline std::vector<unsigned char> dyn_lds;
+}  // namespace emu
+
+#define threadIdx (emu::tidx)
+#define blockIdx (emu::bidx)
+#define blockDim (emu::bdim)
+#define gridDim (emu::gdim)
+#define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(emu::dyn_lds.data());
+
+inline void __syncthreads() { emu::bar->arrive_and_wait(); }
+
+inline long long __double_as_longlong(double d)
+{
+    long long r;
+    std::memcpy(&r, &d, sizeof r);
+    return r;
+}
+using std::isfinite;
+using std::fmax;
+using std::sqrt;
+
+template <typename T>
+inline T atomicAdd(T* p, T v)
+{
+    return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+}
+inline unsigned long long atomicMax(unsigned long long* p, unsigned long long v)
+{
+    unsigned long long old = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (old < v && !__atomic_compare_exchange_n(p, &old, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return old;
+}
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 };
+typedef void* hipStream_t;
+typedef struct emu_event* hipEvent_t;
+struct emu_event {
+    double t;
+};
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyHostToHost };
+enum { hipStreamNonBlocking = 1, hipHostMallocDefault = 0 };
+enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
+
+// Fill value for fresh "device" memory: NaN-like bytes, so reads of
+// never-written memory show up in results.
+inline hipError_t hipMalloc(void** p, size_t n)
+{
+    *p = std::malloc(n ? n : 1);
+    if (!*p) return hipErrorOutOfMemory;
+    std::memset(*p, 0xff, n);
+    return hipSuccess;
+}
+template <typename T>
+inline hipError_t hipMalloc(T** p, size_t n) { return hipMalloc(reinterpret_cast<void**>(p), n); }
+inline hipError_t hipFree(void* p) { std::free(p); return hipSuccess; }
+inline hipError_t hipHostMalloc(void** p, size_t n, unsigned) { return hipMalloc(p, n); }
+template <typename T>
+inline hipError_t hipHostMalloc(T** p, size_t n, unsigned f) { return hipHostMalloc(reinterpret_cast<void**>(p), n, f); }
+inline hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
+inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { std::memmove(d, s, n); return hipSuccess; }
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { std::memmove(d, s, n); return hipSuccess; }
+inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) { std::memset(d, v, n); return hipSuccess; }
+inline hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = reinterpret_cast<hipStream_t>(0x1); return hipSuccess; }
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventCreate(hipEvent_t* e) { *e = new emu_event{0.0}; return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t)
+{
+    e->t = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    return hipSuccess;
+}
+inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) { *ms = (float)((b->t - a->t) * 1e3); return hipSuccess; }
+inline hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
+inline hipError_t hipGetLastError() { return hipSuccess; }
+inline const char* hipGetErrorString(hipError_t) { return "emulated HIP error"; }
+
+namespace emu {
+// One team of host threads per launch walks the blocks in order.  The LDS is
+// refilled with 0xff before each block, as a GPU gives no guarantee about it.
+template <typename K, typename... Args>
+void launch(K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
+{
+    const unsigned nth = block.x * block.y * block.z;
+    const unsigned nblk = grid.x * grid.y * grid.z;
+    gdim = grid;
+    bdim = block;
+    dyn_lds.assign(lds ? lds : 1, 0xff);
+    std::barrier<> b((std::ptrdiff_t)nth);
+    bar = &b;
+    std::vector<std::thread> th;
+    th.reserve(nth);
+    for (unsigned t = 0; t < nth; ++t)
+        th.emplace_back([&, t] {
+            tidx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+            for (unsigned k = 0; k < nblk; ++k) {
+                if (t == 0) {
+                    bidx = dim3(k % grid.x, (k / grid.x) % grid.y, k / (grid.x * grid.y));
+                    std::memset(dyn_lds.data(), 0xff, dyn_lds.size());
+                }
+                b.arrive_and_wait();
+                kernel(args...);
+                b.arrive_and_wait();
+            }
+        });
+    for (auto& x : th) x.join();
+    bar = nullptr;
+}
+}  // namespace emu
+
+#define hipLaunchKernelGGL(kernel, grid, block, lds, stream, ...) emu::launch(kernel, grid, block, lds, __VA_ARGS__)

@@ -1,0 +1,142 @@
+"""The library's HIP sources, compiled for the CPU against a stand-in
+hip_runtime.h (tests/emu), checked against the FP64 oracle on small lattices.
+
+This runs every kernel's index arithmetic, LDS FFT stages and the runtime's
+launch sequencing without a GPU, so layout and bounds mistakes are caught
+before a GPU run; the GPU parity tests repeat the comparison on the MI355X.
+One case also runs under AddressSanitizer.
+"""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1206_0675_amd import lgf
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "emu"))
+
+
+@pytest.fixture(scope="module")
+def E():
+    import build_emu
+    return lgf.load_library(build_emu.build())
+
+
+CASES = [((4, 4, 4, 4), {}), ((8, 4, 4, 4), {}), ((4, 8, 4, 8), {}), ((4, 4, 16, 4), {}),
+         ((16, 16, 4, 4), {}), ((32, 16, 4, 4), {}), ((4, 4, 8, 16), {}),
+         ((8, 8, 4, 4), {"storage": 12}), ((4, 4, 4, 8), {"accel": 0})]
+
+
+@pytest.mark.parametrize("dims, kw", CASES)
+def test_emulated_steps_match_oracle(E, oracle_lib, dims, kw):
+    U = synth.random_links(dims, 2)
+    ctx = lgf.Context(dims, lib=E, **kw)
+    ctx.load(U)
+    tf, tt = ctx.step(3, trace=True)
+    Ug = ctx.store()
+    o = oracle.opts(accel=kw.get("accel", 1) == 1, store12=kw.get("storage", 18) == 12)
+    Uo, of, ot, _ = oracle.step(dims, U, 3, o)
+    assert np.max(np.abs(Ug - Uo)) <= 1e-13
+    assert np.max(np.abs(tf - of)) <= 1e-13 * np.max(np.abs(of))
+    assert np.max(np.abs(tt / ot - 1)) <= 1e-12
+
+
+def test_emulated_fp32_error_is_single_precision(E, oracle_lib):
+    dims = (8, 4, 8, 4)
+    U = synth.random_links(dims, 2)
+    ctx = lgf.Context(dims, lib=E, precision=lgf.FP32)
+    ctx.load(U)
+    tf, tt = ctx.step(3, trace=True)
+    Uo, of, ot, _ = oracle.step(dims, U, 3)
+    d = np.max(np.abs(ctx.store() - Uo))
+    assert 1e-9 < d < 1e-5
+
+
+def test_emulated_fix_and_mixed(E, oracle_lib):
+    dims = (4, 4, 8, 4)
+    U = synth.random_links(dims, 3)
+    _, it, F, th, ok, _ = oracle.fix(dims, U)
+    ctx = lgf.Context(dims, lib=E, poll_every=8)
+    ctx.load(U)
+    s = ctx.fix()
+    assert abs(s.iter - it) <= 1 and abs(s.F - F) <= 1e-12 and s.theta < 1e-15
+    m = lgf.Context(dims, lib=E, precision=lgf.MIXED, poll_every=8)
+    m.load(U)
+    s = m.fix()
+    assert s.iter_fp32 > 0 and s.iter_fp64 > 0 and s.iter == s.iter_fp32 + s.iter_fp64
+    assert abs(s.F - F) <= 1e-9 and s.theta < 1e-15
+    G = m.store_gauge()
+    assert np.max(np.abs(oracle.transform(dims, U, G) - m.store())) < 1e-12
+
+
+def test_emulated_checkpoint_resume(E, oracle_lib):
+    dims = (4, 8, 4, 4)
+    U = synth.random_links(dims, 4)
+    a = lgf.Context(dims, lib=E, track_gauge=1)
+    a.load(U)
+    a.step(4)
+    U4, G4 = a.store(), a.store_gauge()
+    a.step(3)
+    ref = a.store()
+    b = lgf.Context(dims, lib=E, track_gauge=1)
+    b.load(U4)
+    b.load_gauge(G4)
+    b.step(3)
+    assert np.array_equal(b.store(), ref)
+    assert np.max(np.abs(b.store_gauge() - a.store_gauge())) == 0.0
+
+
+def test_emulated_load_rejects_bad_links(E):
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 1)
+    ctx = lgf.Context(dims, lib=E)
+    bad = U.copy()
+    bad[0, 0, 0, 0, 0] *= 1.001
+    with pytest.raises(lgf.LgfError) as e:
+        ctx.load(bad)
+    assert e.value.code == lgf.E_NOT_UNITARY
+    with pytest.raises(lgf.LgfError) as e:
+        ctx.step(1)
+    assert e.value.code == lgf.E_STATE
+    bad[0, 0, 0, 0, 0, 0, 0] = np.inf
+    with pytest.raises(lgf.LgfError) as e:
+        ctx.load(bad)
+    assert e.value.code == lgf.E_NONFINITE
+
+
+_ASAN_SCRIPT = r"""
+import sys
+sys.path.insert(0, {root!r})
+import synth
+from paper_1206_0675_amd import lgf
+L = lgf.load_library({lib!r})
+for dims, kw in [((4, 4, 4, 4), {{"max_iter": 4}}), ((8, 4, 4, 8), {{"storage": 12, "max_iter": 4}}),
+                 ((4, 8, 4, 4), {{"precision": 2, "poll_every": 4, "theta_switch": 1.0, "max_iter": 8}}),
+                 ((4, 4, 8, 4), {{"precision": 1, "track_gauge": 1, "max_iter": 4}})]:
+    ctx = lgf.Context(dims, lib=L, **kw)
+    ctx.load(synth.random_links(dims, 5))
+    ctx.step(2, trace=True)
+    ctx.fix(raise_on_error=False)
+    ctx.store()
+    if kw.get("precision") or kw.get("track_gauge"):
+        ctx.load_gauge(ctx.store_gauge())
+    ctx.close()
+print("ASAN-CLEAN")
+"""
+
+
+@pytest.mark.slow
+def test_emulated_under_address_sanitizer():
+    import build_emu
+    lib = build_emu.build(asan=True)
+    asan = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True, text=True).stdout.strip()
+    env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0")
+    root = os.path.dirname(HERE)
+    r = subprocess.run([sys.executable, "-c", _ASAN_SCRIPT.format(root=root, lib=lib)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and "ASAN-CLEAN" in r.stdout, r.stderr[-3000:]

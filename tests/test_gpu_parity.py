@@ -1,0 +1,264 @@
+"""GPU parity: the gfx950 library through its C ABI against the FP64 oracle.
+
+Gates (FP64): after one update the links agree to 1e-13; over ten updates
+links, F and theta agree to 1e-12 (relative, every iteration); a full run to
+theta < 1e-15 ends at an F within 1e-9 of the oracle's, with iteration
+counts within one.  Mixed precision must end within 1e-9 of the oracle's F.
+Also checked on the GPU: gauge invariance of the plaquette, unitarity of the
+links and of the accumulated gauge, ascent of F, run-to-run bitwise
+determinism, checkpoint/resume, device-pointer I/O, input validation, and
+the smallest and largest supported planes.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1206_0675_amd import lgf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lgf.load_library()       # the gfx950 build; raises if it is missing
+
+
+def announce(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+_links_cache = {}
+
+
+def links(dims, seed=1, **kw):
+    key = (tuple(dims), seed, tuple(sorted(kw.items())))
+    if key not in _links_cache:
+        _links_cache[key] = synth.random_links(dims, seed, **kw)
+    return _links_cache[key]
+
+
+def gpu_steps(L, dims, U, n, **kw):
+    announce(f"steps dims={dims} n={n} {kw}")
+    with lgf.Context(dims, lib=L, **kw) as ctx:
+        ctx.load(U)
+        tf, tt = ctx.step(n, trace=True)
+        return ctx.store(), tf, tt
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 8, 8, 8), (16, 8, 4, 8), (8, 4, 16, 32)])
+def test_measure(L, oracle_lib, dims):
+    U = links(dims)
+    announce(f"measure {dims}")
+    with lgf.Context(dims, lib=L) as ctx:
+        ctx.load(U)
+        s = ctx.measure()
+    F, th, _ = oracle.measure(dims, U)
+    assert abs(s.F - F) <= 1e-13 * abs(F) + 1e-16
+    assert abs(s.theta - th) <= 1e-13 * th
+
+
+@pytest.mark.parametrize("dims, kw", [((8, 8, 8, 8), {}), ((16, 16, 16, 16), {}), ((8, 16, 4, 32), {}),
+                                      ((16, 16, 16, 16), {"storage": 12}), ((8, 8, 8, 8), {"accel": 0})])
+def test_one_and_ten_steps(L, oracle_lib, dims, kw):
+    U = links(dims)
+    o = oracle.opts(accel=kw.get("accel", 1) == 1, store12=kw.get("storage", 18) == 12)
+    U1, _, _ = gpu_steps(L, dims, U, 1, **kw)
+    Uo1, _, _, _ = oracle.step(dims, U, 1, o)
+    assert rel(U1, Uo1) <= 1e-13
+    U10, tf, tt = gpu_steps(L, dims, U, 10, **kw)
+    Uo10, of, ot, _ = oracle.step(dims, U, 10, o)
+    assert rel(U10, Uo10) <= 1e-12
+    assert np.max(np.abs(tf - of) / np.abs(of)) <= 1e-12
+    assert np.max(np.abs(tt - ot) / ot) <= 1e-12
+
+
+@pytest.mark.parametrize("dims, seed", [((8, 8, 8, 8), 1), ((8, 8, 8, 8), 2), ((16, 16, 16, 16), 1),
+                                        ((16, 16, 8, 32), 3)])
+def test_fix_final_F(L, oracle_lib, dims, seed):
+    U = links(dims, seed)
+    announce(f"fix {dims} seed {seed}")
+    with lgf.Context(dims, lib=L, track_gauge=1, poll_every=8) as ctx:
+        ctx.load(U)
+        s = ctx.fix()
+        Ug, G = ctx.store(), ctx.store_gauge()
+    _, it, F, th, ok, _ = oracle.fix(dims, U)
+    assert ok and s.theta < 1e-15
+    assert abs(s.F - F) <= 1e-9
+    assert abs(s.iter - it) <= 1
+    assert abs(oracle.plaquette(dims, Ug) - oracle.plaquette(dims, U)) <= 1e-12
+    for m in (Ug, G):
+        mu, md = oracle.unitarity(m)
+        assert mu <= 1e-12 and md <= 1e-12
+    assert rel(oracle.transform(dims, U, G), Ug) <= 1e-12
+
+
+def test_monotone_F_and_determinism(L, oracle_lib):
+    dims = (16, 16, 16, 16)
+    U = links(dims, 2)
+    a, tf, tt = gpu_steps(L, dims, U, 30)
+    b, tf2, tt2 = gpu_steps(L, dims, U, 30)
+    assert np.all(np.diff(tf) >= -1e-14)
+    assert np.array_equal(a, b) and np.array_equal(tf, tf2) and np.array_equal(tt, tt2)
+
+
+def test_identity_and_pure_gauge(L, oracle_lib):
+    dims = (8, 8, 8, 8)
+    announce("identity and pure gauge")
+    with lgf.Context(dims, lib=L) as ctx:
+        ctx.load(synth.identity_links(dims))
+        s = ctx.fix()
+        assert s.iter == 0 and s.F == 1.0 and s.theta == 0.0
+        ctx.step(3)
+        assert np.array_equal(ctx.store(), synth.identity_links(dims))
+        ctx.load(synth.pure_gauge(dims, 4))
+        s = ctx.fix()
+        assert s.theta < 1e-15 and abs(s.F - 1.0) <= 1e-12
+
+
+def test_step_zero_is_measure(L, oracle_lib):
+    dims = (8, 8, 4, 4)
+    U = links(dims)
+    Ug, tf, tt = gpu_steps(L, dims, U, 0)
+    F, th, _ = oracle.measure(dims, U)
+    assert len(tf) == 1 and abs(tf[0] - F) <= 1e-13 and abs(tt[0] / th - 1) <= 1e-13
+    assert np.array_equal(Ug, U)
+
+
+# ---------------------------------------------------------------------------
+# precision
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dims, seed", [((16, 16, 16, 16), 1), ((16, 16, 16, 16), 4)])
+def test_mixed_precision_final_F(L, oracle_lib, dims, seed):
+    U = links(dims, seed)
+    announce(f"mixed {dims} seed {seed}")
+    with lgf.Context(dims, lib=L, precision=lgf.MIXED, storage=12, poll_every=4) as ctx:
+        ctx.load(U)
+        s = ctx.fix()
+        Ug, G = ctx.store(), ctx.store_gauge()
+    _, it, F, th, ok, _ = oracle.fix(dims, U)
+    assert s.theta < 1e-15 and s.iter_fp32 > 0 and s.iter_fp64 > 0
+    assert abs(s.F - F) <= 1e-9
+    assert abs(oracle.plaquette(dims, Ug) - oracle.plaquette(dims, U)) <= 1e-12
+    assert rel(oracle.transform(dims, U, G), Ug) <= 1e-12
+
+
+def test_fp32_error_bound(L, oracle_lib):
+    dims = (16, 16, 16, 16)
+    U = links(dims)
+    Ug, tf, tt = gpu_steps(L, dims, U, 10, precision=lgf.FP32)
+    Uo, of, ot, _ = oracle.step(dims, U, 10)
+    assert 1e-9 < rel(Ug, Uo) <= 1e-5
+    assert np.max(np.abs(tf - of)) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# full size: the 32^4 lattice in the bench configuration
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", [18, 12])
+def test_full_size_32x4_ten_steps(L, oracle_lib, storage):
+    dims = (32, 32, 32, 32)
+    U = links(dims)
+    Ug, tf, tt = gpu_steps(L, dims, U, 10, storage=storage)
+    Uo, of, ot, _ = oracle.step(dims, U, 10, oracle.opts(store12=storage == 12))
+    assert rel(Ug, Uo) <= 1e-12
+    assert np.max(np.abs(tf - of) / np.abs(of)) <= 1e-12
+    assert np.max(np.abs(tt - ot) / ot) <= 1e-12
+
+
+def test_full_size_32x4_fix_properties(L, oracle_lib):
+    dims = (32, 32, 32, 32)
+    U = links(dims)
+    announce("fix 32^4 12-real")
+    with lgf.Context(dims, lib=L, storage=12) as ctx:
+        ctx.load(U)
+        s = ctx.fix()
+        Ug = ctx.store()
+        F, th, _ = oracle.measure(dims, Ug)
+    assert s.theta < 1e-15 and 30 < s.iter < 80
+    assert abs(F - s.F) <= 1e-12 and abs(th - s.theta) <= 1e-10 * th
+    assert abs(oracle.plaquette(dims, Ug) - oracle.plaquette(dims, U)) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# I/O, state and edges
+# ---------------------------------------------------------------------------
+def test_device_pointer_io(L, oracle_lib):
+    import torch
+    dims = (8, 8, 8, 8)
+    U = links(dims)
+    announce("device pointers")
+    stream = torch.cuda.current_stream()
+    with lgf.Context(dims, lib=L, stream=stream.cuda_stream) as ctx:
+        t = torch.from_numpy(U.view(np.float64).copy()).cuda()
+        ctx.load(t)
+        ctx.step(5)
+        out = torch.empty_like(t)
+        ctx.store(out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.complex128).reshape(U.shape)
+    Uo, _, _, _ = oracle.step(dims, U, 5)
+    assert rel(got, Uo) <= 1e-12
+
+
+def test_checkpoint_resume_bitwise(L):
+    dims = (16, 8, 8, 16)
+    U = links(dims, 5)
+    announce("checkpoint")
+    with lgf.Context(dims, lib=L, track_gauge=1) as a, lgf.Context(dims, lib=L, track_gauge=1) as b:
+        a.load(U)
+        a.step(7)
+        U7, G7 = a.store(), a.store_gauge()
+        a.step(6)
+        b.load(U7)
+        b.load_gauge(G7)
+        b.step(6)
+        assert np.array_equal(a.store(), b.store())
+        assert np.array_equal(a.store_gauge(), b.store_gauge())
+
+
+def test_load_validation(L):
+    dims = (8, 8, 8, 8)
+    U = links(dims).copy()
+    announce("validation")
+    with lgf.Context(dims, lib=L) as ctx:
+        U[3, 2, 1, 0, 1] *= 1.0 + 1e-9
+        with pytest.raises(lgf.LgfError) as e:
+            ctx.load(U)
+        assert e.value.code == lgf.E_NOT_UNITARY
+        with pytest.raises(lgf.LgfError) as e:
+            ctx.step(1)
+        assert e.value.code == lgf.E_STATE
+        U[0, 0, 0, 0, 0, 0, 0] = np.nan
+        with pytest.raises(lgf.LgfError) as e:
+            ctx.load(U)
+        assert e.value.code == lgf.E_NONFINITE
+
+
+def test_not_converged_status(L):
+    dims = (8, 8, 8, 8)
+    announce("max_iter")
+    with lgf.Context(dims, lib=L, max_iter=5, poll_every=2) as ctx:
+        ctx.load(links(dims))
+        s = ctx.fix(raise_on_error=False)
+        assert s.status == lgf.E_NOT_CONVERGED and s.iter == 5
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (64, 32, 4, 4), (4, 4, 128, 64)])
+def test_smallest_and_largest_planes(L, oracle_lib, dims):
+    U = links(dims)
+    Ug, tf, tt = gpu_steps(L, dims, U, 3)
+    Uo, of, ot, _ = oracle.step(dims, U, 3)
+    assert rel(Ug, Uo) <= 1e-12
+    assert np.max(np.abs(tt - ot) / ot) <= 1e-12
