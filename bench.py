@@ -79,6 +79,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the time-to-theta runs")
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="for hardware counters: a few iterations, then one plain device copy of "
+                         "--copy-mib MiB (a kernel of known traffic that scales FETCH_SIZE/WRITE_SIZE); no JSON")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -103,6 +107,18 @@ def main():
     print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     R = args.storage
     ab = alg_bytes(V, 8, R)
+
+    if args.pmc_sample:
+        with lgf.Context(dims, lib=L, storage=R) as ctx:
+            ctx.load(U)
+            ctx.step(5)
+        n = args.copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# pmc sample: 5 iterations, then one copy of {args.copy_mib} MiB", file=sys.stderr, flush=True)
+        return
 
     # ---- timed iterations (no profiling) -----------------------------------
     with lgf.Context(dims, lib=L, storage=R) as ctx:
@@ -158,15 +174,18 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         o = oracle.opts(store12=(R == 12))
+        n_a, n_b = 2, 32
         t = time.perf_counter()
-        oracle.step(dims, U, 1, o)
+        oracle.step(dims, U, n_a, o)
         t_a = time.perf_counter() - t
         t = time.perf_counter()
-        oracle.step(dims, U, 7, o)
+        oracle.step(dims, U, n_b, o)
         t_b = time.perf_counter() - t
-        cpu = {"value": round(6 / (t_b - t_a), 4), "unit": "iters/s", "cores": oracle.threads(), "kind": "oracle",
-               "sample": f"FP64 oracle (plain C, OpenMP) on the same {'x'.join(map(str, dims))} lattice: "
-                         f"rate = 6 / (t(7 updates) - t(1 update)), {t_a + t_b:.1f}s of CPU work"}
+        cpu = {"value": round((n_b - n_a) / (t_b - t_a), 4), "unit": "iters/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"FP64 oracle (plain C, OpenMP) on the same {'x'.join(map(str, dims))} lattice, "
+                         f"{R}-real: rate = {n_b - n_a} / (t({n_b} updates) - t({n_a} updates)), "
+                         f"{t_a + t_b:.1f}s of CPU work"}
 
     it_bytes = ab["iteration"]
     line = {

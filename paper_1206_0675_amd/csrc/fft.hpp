@@ -1,134 +1,229 @@
 // Power-of-two complex FFTs over lines held in LDS, for the 2D+2D split of
-// the 4D transform (Section 3.2: a batch of 2D (x, y) transforms, then a
-// batch of 2D (z, t) transforms; here without any data reordering pass).
+// the 4D transform (Section 3.2: a batch of 2D (x, y) transforms and a batch
+// of 2D (z, t) transforms; here with no separate data-reordering pass).
 //
-// Forward transforms are decimation-in-frequency (natural order in,
-// bit-reversed order out); inverse transforms are decimation-in-time
-// (bit-reversed in, natural out).  The spectral multiply sits between them
-// and indexes modes through the bit reversal, so no permutation is ever
-// performed.  Radix-4 butterflies (each equal to two radix-2 stages) with one
-// radix-2 stage when log2(L) is odd.  Twiddles W_L^k = exp(-2 pi i k / L)
-// come from a host-computed table of L entries.
+// A line of length L = R1 * R2 is transformed in at most two register-blocked
+// passes (the "four-step" factorisation of the DFT):
+//   pass A: for each k2 < R2, the R1-point DFT of x[k2 + R2 m] over m, times
+//           the twiddle W_L^(k2 j1), written back to position k2 + R2 j1;
+//   pass B: for each j1 < R1, the R2-point DFT of the R2 contiguous values at
+//           R2 j1 + k2, written back in place.
+// Mode n = j1 + R1 j2 then sits at position p = j2 + R2 j1 (a digit
+// transposition; mode_of_position() below).  The spectral multiply works in
+// that order and the inverse undoes the passes in reverse (B^-1 then A^-1),
+// so no permutation pass is ever made.  The R-point DFTs (R <= 16) run in
+// registers with compile-time twiddles.  W_L^k = exp(-2 pi i k / L); inverse
+// transforms are unnormalised.
 //
-// A set of lines is described by Lines: line l = l_hi * 2^lo_log + l_lo holds
-// element j at buf[l_lo * s_lo + l_hi * s_hi + j * es].  All threads of the
-// block call these routines; they end with a barrier.
+// A set of lines: line l = l_hi * 2^lo_log + l_lo holds element j at
+// buf[l_lo * s_lo + l_hi * s_hi + j * es].  All threads of the block call the
+// pass routines; each ends with a barrier.
 #pragma once
 #include "su3.hpp"
 
 namespace lgf {
 
 struct Lines {
-    int logL;     // log2 of the line length
     int lo_log;   // log2 of the number of low line indices
     int hi_log;   // log2 of the number of high line indices
     int s_lo, s_hi, es;
 };
 
+// (R1, R2) used for a line of length L; the host builds its mode tables from
+// the same function.
+__host__ __device__ constexpr int fft_r2(int L) { return L <= 8 ? 1 : (L <= 32 ? 4 : 8); }
+__host__ __device__ constexpr int fft_r1(int L) { return L / fft_r2(L); }
+__host__ __device__ constexpr int mode_of_position(int L, int p)
+{
+    return p / fft_r2(L) + fft_r1(L) * (p % fft_r2(L));
+}
+
+// cos(i pi / 8), i = 0..8
+__device__ __forceinline__ constexpr double cos_pi8(int i)
+{
+    constexpr double c1 = 0.92387953251128675612818318939678828682;   // cos(pi/8)
+    constexpr double c2 = 0.70710678118654752440084436210484903928;   // cos(pi/4)
+    constexpr double c3 = 0.38268343236508977172845998403039886676;   // cos(3pi/8)
+    return i == 0 ? 1.0 : i == 1 ? c1 : i == 2 ? c2 : i == 3 ? c3 : i == 4 ? 0.0
+         : i == 5 ? -c3 : i == 6 ? -c2 : i == 7 ? -c1 : -1.0;
+}
+
+// v *= exp(-+ 2 pi i k / span), forward sign unless INV; k < span / 2, span <= 16
+template <typename T, int SPAN, int K, bool INV>
+__device__ __forceinline__ C2<T> twiddle_const(C2<T> v)
+{
+    constexpr int i = K * (16 / SPAN);            // angle = i * pi / 8, 0 <= i < 8
+    if constexpr (i == 0) return v;
+    else if constexpr (i == 4) return INV ? mul_i(v) : mul_mi(v);
+    else {
+        const T c = (T)cos_pi8(i);
+        const T s = (T)cos_pi8(i <= 4 ? 4 - i : i - 4);   // sin(i pi / 8)
+        const T sn = INV ? s : -s;
+        return mk<T>(v.x * c - v.y * sn, v.x * sn + v.y * c);
+    }
+}
+
+template <int N, int B>
+__host__ __device__ constexpr int bitrev_c(int v)
+{
+    int r = 0;
+    for (int i = 0; i < B; ++i) r |= ((v >> i) & 1) << (B - 1 - i);
+    return r;
+}
+
+template <int R>
+constexpr int log2_c() { return R <= 1 ? 0 : 1 + log2_c<R / 2>(); }
+
+template <typename T, int R, int SPAN, int BLK, int K, bool INV>
+__device__ __forceinline__ void dft_bfly(C2<T>* v)
+{
+    constexpr int h = SPAN / 2;
+    const C2<T> a = v[BLK * SPAN + K], b = v[BLK * SPAN + K + h];
+    v[BLK * SPAN + K] = a + b;
+    v[BLK * SPAN + K + h] = twiddle_const<T, SPAN, K, INV>(a - b);
+    if constexpr (K + 1 < h) dft_bfly<T, R, SPAN, BLK, K + 1, INV>(v);
+    else if constexpr (BLK + 1 < R / SPAN) dft_bfly<T, R, SPAN, BLK + 1, 0, INV>(v);
+}
+
+template <typename T, int R, int SPAN, bool INV>
+__device__ __forceinline__ void dft_stages(C2<T>* v)
+{
+    dft_bfly<T, R, SPAN, 0, 0, INV>(v);
+    if constexpr (SPAN > 2) dft_stages<T, R, SPAN / 2, INV>(v);
+}
+
+// In-register R-point DFT, natural order in and out (radix-2 decimation in
+// frequency; the final bit reversal is a renaming of registers).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(C2<T>* v)
+{
+    if constexpr (R > 1) {
+        dft_stages<T, R, R, INV>(v);
+        C2<T> w[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) w[j] = v[bitrev_c<R, log2_c<R>()>(j)];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = w[j];
+    }
+}
+
+__device__ __forceinline__ void task_split(int t, int R, const Lines& a, int& kk, int& line)
+{
+    // unit-stride element axis: k fastest; otherwise the unit-stride line
+    // index fastest, so neighbouring lanes touch neighbouring LDS words
+    if (a.es == 1) {
+        kk = t & (R - 1);
+        line = t / R;
+    } else {
+        const int lo = t & ((1 << a.lo_log) - 1), rest = t >> a.lo_log;
+        kk = rest & (R - 1);
+        line = ((rest / R) << a.lo_log) | lo;
+    }
+}
+
 template <typename T>
-__device__ __forceinline__ C2<T>* line_ptr(C2<T>* buf, const Lines& a, int line)
+__device__ __forceinline__ C2<T>* line_base(C2<T>* buf, const Lines& a, int line)
 {
     const int l_lo = line & ((1 << a.lo_log) - 1);
     const int l_hi = line >> a.lo_log;
     return buf + l_lo * a.s_lo + l_hi * a.s_hi;
 }
 
-// Forward (sign -1) transform of every line; output in bit-reversed order.
-template <typename T>
-__device__ void fft_dif(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
+// pass A (forward) or A^-1 (inverse); tw = W_L^k, k < L
+template <typename T, int R1, int R2, bool INV>
+__device__ void fft_pass_a(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
 {
-    const int L = 1 << a.logL;
-    const int es = a.es;
-    int logspan = a.logL;
-    while (logspan >= 2) {
-        const int logq = logspan - 2, q = 1 << logq;
-        const int twstep = 1 << (a.logL - logspan);
-        const int nbf = 1 << (a.lo_log + a.hi_log + a.logL - 2);
-        for (int b = tid; b < nbf; b += nth) {
-            const int j = b & ((L >> 2) - 1);
-            C2<T>* p = line_ptr(buf, a, b >> (a.logL - 2));
-            const int k = j & (q - 1);
-            const int p0 = ((j >> logq) << logspan) + k;
-            C2<T> x0 = p[p0 * es], x1 = p[(p0 + q) * es], x2 = p[(p0 + 2 * q) * es], x3 = p[(p0 + 3 * q) * es];
-            C2<T> s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3;
-            C2<T> y0 = s02 + s13;
-            C2<T> y2 = s02 - s13;
-            C2<T> y1 = d02 + mul_mi(d13);   // x0 - i x1 - x2 + i x3
-            C2<T> y3 = d02 + mul_i(d13);    // x0 + i x1 - x2 - i x3
-            if (k != 0) {
-                y1 = cmul(y1, tw[k * twstep]);
-                y2 = cmul(y2, tw[2 * k * twstep]);
-                y3 = cmul(y3, tw[3 * k * twstep]);
+    const int ntask = R2 << (a.lo_log + a.hi_log);
+    const int es = a.es, st = R2 * es;
+    for (int t = tid; t < ntask; t += nth) {
+        int k2, line;
+        task_split(t, R2, a, k2, line);
+        C2<T>* p = line_base(buf, a, line) + k2 * es;
+        C2<T> v[R1];
+#pragma unroll
+        for (int m = 0; m < R1; ++m) v[m] = p[m * st];
+        if (!INV) {
+            dft<T, R1, false>(v);
+            if (R2 > 1 && k2 != 0) {
+#pragma unroll
+                for (int j = 1; j < R1; ++j) v[j] = cmul(v[j], tw[k2 * j]);
             }
-            p[p0 * es] = y0;
-            p[(p0 + q) * es] = y2;
-            p[(p0 + 2 * q) * es] = y1;
-            p[(p0 + 3 * q) * es] = y3;
+        } else {
+            if (R2 > 1 && k2 != 0) {
+#pragma unroll
+                for (int j = 1; j < R1; ++j) v[j] = cmulc(v[j], tw[k2 * j]);
+            }
+            dft<T, R1, true>(v);
         }
-        __syncthreads();
-        logspan -= 2;
+#pragma unroll
+        for (int m = 0; m < R1; ++m) p[m * st] = v[m];
     }
-    if (logspan == 1) {
-        const int nbf = 1 << (a.lo_log + a.hi_log + a.logL - 1);
-        for (int b = tid; b < nbf; b += nth) {
-            const int j = b & ((L >> 1) - 1);
-            C2<T>* p = line_ptr(buf, a, b >> (a.logL - 1));
-            C2<T> x0 = p[(2 * j) * es], x1 = p[(2 * j + 1) * es];
-            p[(2 * j) * es] = x0 + x1;
-            p[(2 * j + 1) * es] = x0 - x1;
+    __syncthreads();
+}
+
+// pass B (forward) or B^-1 (inverse): R2-point DFTs of contiguous groups
+template <typename T, int R1, int R2, bool INV>
+__device__ void fft_pass_b(C2<T>* buf, const Lines a, int tid, int nth)
+{
+    if constexpr (R2 > 1) {
+        const int ntask = R1 << (a.lo_log + a.hi_log);
+        const int es = a.es;
+        for (int t = tid; t < ntask; t += nth) {
+            int j1, line;
+            task_split(t, R1, a, j1, line);
+            C2<T>* p = line_base(buf, a, line) + j1 * R2 * es;
+            C2<T> u[R2];
+#pragma unroll
+            for (int k = 0; k < R2; ++k) u[k] = p[k * es];
+            dft<T, R2, INV>(u);
+#pragma unroll
+            for (int k = 0; k < R2; ++k) p[k * es] = u[k];
         }
         __syncthreads();
     }
 }
 
-// Inverse (sign +1, unnormalised) transform of every line; input in
-// bit-reversed order, output natural.  Undoes fft_dif up to a factor L.
-template <typename T>
-__device__ void fft_dit(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
+template <typename T, int L>
+__device__ __forceinline__ void fft_fwd_L(C2<T>* buf, const Lines& a, const C2<T>* tw, int tid, int nth)
 {
-    const int L = 1 << a.logL;
-    const int es = a.es;
-    int logspan = (a.logL & 1) ? 1 : 2;
-    if (logspan == 1) {
-        const int nbf = 1 << (a.lo_log + a.hi_log + a.logL - 1);
-        for (int b = tid; b < nbf; b += nth) {
-            const int j = b & ((L >> 1) - 1);
-            C2<T>* p = line_ptr(buf, a, b >> (a.logL - 1));
-            C2<T> x0 = p[(2 * j) * es], x1 = p[(2 * j + 1) * es];
-            p[(2 * j) * es] = x0 + x1;
-            p[(2 * j + 1) * es] = x0 - x1;
-        }
-        __syncthreads();
-        logspan = 3;
+    fft_pass_a<T, fft_r1(L), fft_r2(L), false>(buf, a, tw, tid, nth);
+    fft_pass_b<T, fft_r1(L), fft_r2(L), false>(buf, a, tid, nth);
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void fft_inv_L(C2<T>* buf, const Lines& a, const C2<T>* tw, int tid, int nth)
+{
+    fft_pass_b<T, fft_r1(L), fft_r2(L), true>(buf, a, tid, nth);
+    fft_pass_a<T, fft_r1(L), fft_r2(L), true>(buf, a, tw, tid, nth);
+}
+
+// Forward transform of every line (output in mode_of_position order).  L is
+// a power of two in [4, LMAX]; kernels built for LMAX = 64 carry no code (and
+// no register demand) for longer lines.
+template <typename T, int LMAX>
+__device__ void fft_fwd(C2<T>* buf, int L, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
+{
+    switch (L) {
+    case 4: fft_fwd_L<T, 4>(buf, a, tw, tid, nth); break;
+    case 8: fft_fwd_L<T, 8>(buf, a, tw, tid, nth); break;
+    case 16: fft_fwd_L<T, 16>(buf, a, tw, tid, nth); break;
+    case 32: fft_fwd_L<T, 32>(buf, a, tw, tid, nth); break;
+    case 64: fft_fwd_L<T, 64>(buf, a, tw, tid, nth); break;
+    default: if constexpr (LMAX >= 128) fft_fwd_L<T, 128>(buf, a, tw, tid, nth); break;
     }
-    for (; logspan <= a.logL; logspan += 2) {
-        const int logq = logspan - 2, q = 1 << logq;
-        const int twstep = 1 << (a.logL - logspan);
-        const int nbf = 1 << (a.lo_log + a.hi_log + a.logL - 2);
-        for (int b = tid; b < nbf; b += nth) {
-            const int j = b & ((L >> 2) - 1);
-            C2<T>* p = line_ptr(buf, a, b >> (a.logL - 2));
-            const int k = j & (q - 1);
-            const int p0 = ((j >> logq) << logspan) + k;
-            C2<T> z0 = p[p0 * es], z1 = p[(p0 + q) * es], z2 = p[(p0 + 2 * q) * es], z3 = p[(p0 + 3 * q) * es];
-            if (k != 0) {
-                const C2<T> w2 = tw[2 * k * twstep];
-                z1 = cmulc(z1, w2);
-                z3 = cmulc(z3, w2);
-            }
-            C2<T> a0 = z0 + z1, a1 = z0 - z1, b0 = z2 + z3, b1 = z2 - z3;
-            if (k != 0) {
-                const C2<T> w1 = tw[k * twstep];
-                b0 = cmulc(b0, w1);
-                b1 = cmulc(b1, w1);
-            }
-            b1 = mul_i(b1);
-            p[p0 * es] = a0 + b0;
-            p[(p0 + 2 * q) * es] = a0 - b0;
-            p[(p0 + q) * es] = a1 + b1;
-            p[(p0 + 3 * q) * es] = a1 - b1;
-        }
-        __syncthreads();
+}
+
+// Inverse (unnormalised) transform of every line; undoes fft_fwd up to L.
+template <typename T, int LMAX>
+__device__ void fft_inv(C2<T>* buf, int L, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
+{
+    switch (L) {
+    case 4: fft_inv_L<T, 4>(buf, a, tw, tid, nth); break;
+    case 8: fft_inv_L<T, 8>(buf, a, tw, tid, nth); break;
+    case 16: fft_inv_L<T, 16>(buf, a, tw, tid, nth); break;
+    case 32: fft_inv_L<T, 32>(buf, a, tw, tid, nth); break;
+    case 64: fft_inv_L<T, 64>(buf, a, tw, tid, nth); break;
+    default: if constexpr (LMAX >= 128) fft_inv_L<T, 128>(buf, a, tw, tid, nth); break;
     }
 }
 

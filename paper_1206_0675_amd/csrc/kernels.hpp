@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_field_identity(int64_t V, C2<T>* __rest
 // a1 + a2 + a3(x, y):  gauge transform, Delta, F and theta terms, forward
 // (x, y) FFT of the packed Delta.  One block per (z, t) plane.
 // ---------------------------------------------------------------------------
-template <typename T, int NE, bool APPLY_G>
+template <typename T, int NE, bool APPLY_G, int LMAX>
 __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restrict__ Uin, C2<T>* __restrict__ Uout,
                                                  const C2<T>* __restrict__ g, C2<T>* __restrict__ D,
                                                  double* __restrict__ partial, const C2<T>* __restrict__ twx,
@@ -215,10 +215,8 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restric
     for (int p = tid; p < NP; p += nth) {
         const int x = p & (Lx - 1), y = p >> geo.logL[0];
         const int64_t s = q0 + p;
-        const int64_t fwd[4] = {q0 + y * Lx + ((x + 1) & (Lx - 1)), q0 + (((y + 1) & (Ly - 1)) * Lx + x),
-                                qzp + p, qtp + p};
-        const int64_t bwd[4] = {q0 + y * Lx + ((x - 1) & (Lx - 1)), q0 + (((y - 1) & (Ly - 1)) * Lx + x),
-                                qzm + p, qtm + p};
+        const int64_t xp = q0 + y * Lx + ((x + 1) & (Lx - 1)), xm = q0 + y * Lx + ((x - 1) & (Lx - 1));
+        const int64_t yp = q0 + (((y + 1) & (Ly - 1)) * Lx + x), ym = q0 + (((y - 1) & (Ly - 1)) * Lx + x);
         Alg8<T> acc;
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc.c[c] = mk<T>(T(0), T(0));
@@ -231,22 +229,23 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restric
             load_mat<T, NE>(u, Uin + (int64_t)mu * NE * V, V, s);
             if (APPLY_G) {
                 M3<T> gn, r;
-                load_mat<T, NE>(gn, g, V, fwd[mu]);
-                a_u_bdag(gx, u, gn, r);
+                load_mat<T, NE>(gn, g, V, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
+                a_u_bdag<T, (NE == 6 ? 2 : 3)>(gx, u, gn, r);
                 store_mat<T, NE>(r, Uout + (int64_t)mu * NE * V, V, s);
                 u = r;
             }
-            f += (double)u.e[0].x + (double)u.e[4].x + (double)u.e[8].x;
+            f += re_trace(u);
             alg_accumulate(acc, u, T(-1));
         }
 #pragma unroll 1
         for (int nu = 0; nu < 4; ++nu) {
             M3<T> u;
-            load_mat<T, NE>(u, Uin + (int64_t)nu * NE * V, V, bwd[nu]);
+            const int64_t sb = nu == 0 ? xm : nu == 1 ? ym : nu == 2 ? qzm + p : qtm + p;
+            load_mat<T, NE>(u, Uin + (int64_t)nu * NE * V, V, sb);
             if (APPLY_G) {
                 M3<T> gb, r;
-                load_mat<T, NE>(gb, g, V, bwd[nu]);
-                a_u_bdag(gb, u, gx, r);
+                load_mat<T, NE>(gb, g, V, sb);
+                a_u_bdag<T, (NE == 6 ? 2 : 3)>(gb, u, gx, r);
                 u = r;
             }
             alg_accumulate(acc, u, T(1));
@@ -263,8 +262,8 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restric
         partial[2 * q + 1] = tb;
     }
     // forward FFT along x, then y, of the four fields
-    fft_dif(buf, Lines{geo.logL[0], geo.logL[1], 2, Lx, NP, 1}, twx, tid, nth);
-    fft_dif(buf, Lines{geo.logL[1], geo.logL[0], 2, 1, NP, Lx}, twy, tid, nth);
+    fft_fwd<T, LMAX>(buf, Lx, Lines{geo.logL[1], 2, Lx, NP, 1}, twx, tid, nth);
+    fft_fwd<T, LMAX>(buf, Ly, Lines{geo.logL[0], 2, 1, NP, Lx}, twy, tid, nth);
     const int W = geo.W;
     for (int i = tid; i < 4 * NP; i += nth) {
         const int c = i >> geo.logNP, p = i & (NP - 1);
@@ -275,12 +274,58 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restric
 // ---------------------------------------------------------------------------
 // a3(z, t) + a4 + a5(z, t): one block per (tile of W plane positions, field)
 // ---------------------------------------------------------------------------
-// ptab: four tables 4 sin^2(pi n / L_mu) indexed by the bit-reversed
-// position (x table first), so ptab[off_mu + pos] belongs to mode n = bitrev(pos).
+// ptab: four tables 4 sin^2(pi n / L_mu), indexed by position along the axis
+// after the forward transforms (x table first), i.e. for the mode
+// n = mode_of_position(L_mu, pos).
 // accel = 1: factor c0 / p^2 with c0 = (alpha/2) p2max / V, zero at p = 0;
 // accel = 0 (plain steepest descent): the constant c0 = (alpha/2) / V.
-template <typename T>
-__global__ void __launch_bounds__(256) k_zt(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
+struct SpectralScale {
+    const double* tx;
+    const double* ty;
+    const double* tz;
+    const double* tt;
+    double c0;
+    int accel;
+    __device__ __forceinline__ double factor(double p2) const
+    {
+        return accel ? (p2 > 0.0 ? c0 / p2 : 0.0) : c0;
+    }
+};
+
+// The t axis of the (z, t) block: forward DFT, spectral factor and inverse
+// DFT of each contiguous group in registers, between the two A passes.
+template <typename T, int LT>
+__device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth,
+                          const SpectralScale& sc, const Geo& geo, int j)
+{
+    constexpr int R1 = fft_r1(LT), R2 = fft_r2(LT);
+    constexpr int G = R2 > 1 ? R2 : R1;            // values per register group
+    if (R2 > 1) fft_pass_a<T, R1, R2, false>(buf, a, tw, tid, nth);
+    const int ntask = (R2 > 1 ? R1 : 1) << a.lo_log;
+    const int es = a.es;
+    for (int t = tid; t < ntask; t += nth) {
+        const int lo = t & ((1 << a.lo_log) - 1);          // (z, w) line
+        const int j1 = R2 > 1 ? (t >> a.lo_log) : 0;
+        const int w = lo & (geo.W - 1), zp = lo >> geo.logW;
+        const int pxy = j * geo.W + w;
+        const double base = sc.tx[pxy & (geo.L[0] - 1)] + sc.ty[pxy >> geo.logL[0]] + sc.tz[zp];
+        C2<T>* p = buf + lo + j1 * R2 * es;
+        C2<T> u[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) u[k] = p[k * es];
+        dft<T, G, false>(u);
+#pragma unroll
+        for (int k = 0; k < G; ++k) u[k] = scale(u[k], (T)sc.factor(base + sc.tt[j1 * R2 + k]));
+        dft<T, G, true>(u);
+#pragma unroll
+        for (int k = 0; k < G; ++k) p[k * es] = u[k];
+    }
+    __syncthreads();
+    if (R2 > 1) fft_pass_a<T, R1, R2, true>(buf, a, tw, tid, nth);
+}
+
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
                                             const C2<T>* __restrict__ twt, const double* __restrict__ ptab,
                                             double c0, int accel, const DevState* __restrict__ st)
 {
@@ -294,22 +339,20 @@ __global__ void __launch_bounds__(256) k_zt(Geo geo, C2<T>* __restrict__ D, cons
     for (int i = tid; i < n; i += nth) buf[i] = src[i];
     __syncthreads();
     const int Lz = geo.L[2];
-    fft_dif(buf, Lines{geo.logL[2], geo.logW, geo.logL[3], 1, Lz * W, W}, twz, tid, nth);
-    fft_dif(buf, Lines{geo.logL[3], geo.logL[2] + geo.logW, 0, 1, 0, Lz * W}, twt, tid, nth);
-    const double* tx = ptab;
-    const double* ty = tx + geo.L[0];
-    const double* tz = ty + geo.L[1];
-    const double* tt = tz + geo.L[2];
-    for (int i = tid; i < n; i += nth) {
-        const int w = i & (W - 1), qq = i >> geo.logW;
-        const int p = j * W + w;
-        const double p2 = tx[p & (geo.L[0] - 1)] + ty[p >> geo.logL[0]] + tz[qq & (Lz - 1)] + tt[qq >> geo.logL[2]];
-        const T f = (T)(accel ? (p2 > 0.0 ? c0 / p2 : 0.0) : c0);
-        buf[i] = scale(buf[i], f);
+    const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
+    const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
+    const SpectralScale sc{ptab, ptab + geo.L[0], ptab + geo.L[0] + geo.L[1], ptab + geo.L[0] + geo.L[1] + Lz,
+                           c0, accel};
+    fft_fwd<T, LMAX>(buf, Lz, zl, twz, tid, nth);
+    switch (geo.L[3]) {
+    case 4: zt_t_axis<T, 4>(buf, tl, twt, tid, nth, sc, geo, j); break;
+    case 8: zt_t_axis<T, 8>(buf, tl, twt, tid, nth, sc, geo, j); break;
+    case 16: zt_t_axis<T, 16>(buf, tl, twt, tid, nth, sc, geo, j); break;
+    case 32: zt_t_axis<T, 32>(buf, tl, twt, tid, nth, sc, geo, j); break;
+    case 64: zt_t_axis<T, 64>(buf, tl, twt, tid, nth, sc, geo, j); break;
+    default: if constexpr (LMAX >= 128) zt_t_axis<T, 128>(buf, tl, twt, tid, nth, sc, geo, j); break;
     }
-    __syncthreads();
-    fft_dit(buf, Lines{geo.logL[3], geo.logL[2] + geo.logW, 0, 1, 0, Lz * W}, twt, tid, nth);
-    fft_dit(buf, Lines{geo.logL[2], geo.logW, geo.logL[3], 1, Lz * W, W}, twz, tid, nth);
+    fft_inv<T, LMAX>(buf, Lz, zl, twz, tid, nth);
     for (int i = tid; i < n; i += nth) src[i] = buf[i];
 }
 
@@ -317,7 +360,7 @@ __global__ void __launch_bounds__(256) k_zt(Geo geo, C2<T>* __restrict__ D, cons
 // a5(x, y) + a6 (+ a8): inverse (x, y) FFT, g = reunit(1 + dtilde) in FP64,
 // and optionally G <- reunit(g G).  One block per (z, t) plane.
 // ---------------------------------------------------------------------------
-template <typename T, int NE, bool ACC_G>
+template <typename T, int NE, bool ACC_G, int LMAX>
 __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict__ D, C2<T>* __restrict__ g,
                                                C2<T>* __restrict__ G, const C2<T>* __restrict__ twx,
                                                const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
@@ -334,8 +377,8 @@ __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict_
         buf[i] = D[((int64_t)((p >> geo.logW) * 4 + c) * geo.NQ + q) * W + (p & (W - 1))];
     }
     __syncthreads();
-    fft_dit(buf, Lines{geo.logL[1], geo.logL[0], 2, 1, NP, geo.L[0]}, twy, tid, nth);
-    fft_dit(buf, Lines{geo.logL[0], geo.logL[1], 2, geo.L[0], NP, 1}, twx, tid, nth);
+    fft_inv<T, LMAX>(buf, geo.L[1], Lines{geo.logL[0], 2, 1, NP, geo.L[0]}, twy, tid, nth);
+    fft_inv<T, LMAX>(buf, geo.L[0], Lines{geo.logL[1], 2, geo.L[0], NP, 1}, twx, tid, nth);
     const int64_t q0 = (int64_t)q * NP;
     for (int p = tid; p < NP; p += nth) {
         C2<double> c[4];

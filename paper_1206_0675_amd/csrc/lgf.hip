@@ -106,6 +106,7 @@ struct lgf_context {
     int64_t bytes = 0;
     double c0 = 0.0;          // (alpha/2) p2max / V
     int nth_plane = 256;
+    int lmax = 64;            // longest axis rounded up to 64 or 128 (kernel variant)
     std::string err;
     std::vector<hipEvent_t> ev_pool;
     std::vector<Pending> pending;
@@ -237,13 +238,6 @@ bool shape_fits(const int32_t* dims, int nth)
     return true;
 }
 
-int bitrev(int v, int bits)
-{
-    int r = 0;
-    for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
-    return r;
-}
-
 template <typename T>
 int32_t alloc_bufs(lgf_context* c, Bufs<T>& b)
 {
@@ -286,22 +280,22 @@ void free_bufs(Bufs<T>& b)
     b = Bufs<T>();
 }
 
-template <typename T, int NE>
+template <typename T, int NE, int LMAX>
 int32_t set_lds_attrs(lgf_context* c)
 {
     const Geo& g = bufs<T>(c).geo;
     const int mlds = (int)(4 * g.NP * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double));
     const int glds = (int)(4 * g.NP * sizeof(C2<T>));
     const int zlds = (int)((size_t)g.NQ * g.W * sizeof(C2<T>));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, false>),
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, false, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, mlds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, true>),
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, true, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, mlds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<T, NE, false>),
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<T, NE, false, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, glds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<T, NE, true>),
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<T, NE, true, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, glds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt<T>),
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt<T, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, zlds));
     return LGF_OK;
 }
@@ -310,13 +304,13 @@ int32_t set_lds_attrs(lgf_context* c)
 // one iteration, enqueued
 // ----------------------------------------------------------------------------
 // Delta, F, theta of U[cur] with no update (the first line of Algorithm 1).
-template <typename T, int NE>
+template <typename T, int NE, int LMAX>
 int32_t enqueue_measure(lgf_context* c, double* trace_slot)
 {
     Bufs<T>& b = bufs<T>(c);
     const Geo& g = b.geo;
     const size_t lds = 4 * g.NP * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double);
-    TRY(launch(c, K_MEASURE, k_measure<T, NE, false>, dim3(g.NQ), dim3(c->nth_plane), lds, g,
+    TRY(launch(c, K_MEASURE, k_measure<T, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), lds, g,
                (const C2<T>*)b.U[c->cur], (C2<T>*)nullptr, (const C2<T>*)nullptr, b.D, c->partial,
                (const C2<T>*)(b.tw + b.tw_off[0]), (const C2<T>*)(b.tw + b.tw_off[1]), (const DevState*)c->st));
     TRY(launch(c, K_REDUCE, k_reduce, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
@@ -328,7 +322,7 @@ int32_t enqueue_measure(lgf_context* c, double* trace_slot)
 // filter, g, transform, Delta/F/theta of the new links (the loop body of
 // Algorithm 1).  The update flips cur; when the device stop flag is set the
 // kernels do nothing and the host learns the real parity at the next poll.
-template <typename T, int NE>
+template <typename T, int NE, int LMAX>
 int32_t enqueue_update(lgf_context* c, double* trace_slot)
 {
     Bufs<T>& b = bufs<T>(c);
@@ -338,16 +332,16 @@ int32_t enqueue_update(lgf_context* c, double* trace_slot)
     const size_t mlds = glds + 2 * c->nth_plane * sizeof(double);
     const C2<T>* twx = b.tw + b.tw_off[0];
     const C2<T>* twy = b.tw + b.tw_off[1];
-    TRY(launch(c, K_ZT, k_zt<T>, dim3((g.NP / g.W) * 4), dim3(256), zlds, g, b.D,
+    TRY(launch(c, K_ZT, k_zt<T, LMAX>, dim3((g.NP / g.W) * 4), dim3(512), zlds, g, b.D,
                (const C2<T>*)(b.tw + b.tw_off[2]), (const C2<T>*)(b.tw + b.tw_off[3]), (const double*)c->ptab,
                c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), (const DevState*)c->st));
     if (c->track)
-        TRY(launch(c, K_GAUGE, k_gauge<T, NE, true>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.g,
+        TRY(launch(c, K_GAUGE, k_gauge<T, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.g,
                    b.G, twx, twy, (const DevState*)c->st));
     else
-        TRY(launch(c, K_GAUGE, k_gauge<T, NE, false>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.g,
+        TRY(launch(c, K_GAUGE, k_gauge<T, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.g,
                    b.G, twx, twy, (const DevState*)c->st));
-    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<T, NE, true>, dim3(g.NQ), dim3(c->nth_plane), mlds, g,
+    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<T, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane), mlds, g,
                (const C2<T>*)b.U[c->cur], b.U[1 - c->cur], (const C2<T>*)b.g, b.D, c->partial, twx, twy,
                (const DevState*)c->st));
     TRY(launch(c, K_REDUCE, k_reduce, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
@@ -356,17 +350,30 @@ int32_t enqueue_update(lgf_context* c, double* trace_slot)
     return LGF_OK;
 }
 
-int32_t measure_any(lgf_context* c, double* trace_slot)
+// Kernel variant for the current phase, storage and longest lattice axis.
+template <template <typename, int, int> class OP, typename... A>
+int32_t dispatch(lgf_context* c, A... args)
 {
-    if (c->phase == 1) return c->NE == 9 ? enqueue_measure<double, 9>(c, trace_slot) : enqueue_measure<double, 6>(c, trace_slot);
-    return c->NE == 9 ? enqueue_measure<float, 9>(c, trace_slot) : enqueue_measure<float, 6>(c, trace_slot);
+    const bool big = c->lmax > 64;
+    if (c->phase == 1) {
+        if (c->NE == 9) return big ? OP<double, 9, 128>::run(c, args...) : OP<double, 9, 64>::run(c, args...);
+        return big ? OP<double, 6, 128>::run(c, args...) : OP<double, 6, 64>::run(c, args...);
+    }
+    if (c->NE == 9) return big ? OP<float, 9, 128>::run(c, args...) : OP<float, 9, 64>::run(c, args...);
+    return big ? OP<float, 6, 128>::run(c, args...) : OP<float, 6, 64>::run(c, args...);
 }
 
-int32_t update_any(lgf_context* c, double* trace_slot)
-{
-    if (c->phase == 1) return c->NE == 9 ? enqueue_update<double, 9>(c, trace_slot) : enqueue_update<double, 6>(c, trace_slot);
-    return c->NE == 9 ? enqueue_update<float, 9>(c, trace_slot) : enqueue_update<float, 6>(c, trace_slot);
-}
+template <typename T, int NE, int LMAX>
+struct OpMeasure {
+    static int32_t run(lgf_context* c, double* tr) { return enqueue_measure<T, NE, LMAX>(c, tr); }
+};
+template <typename T, int NE, int LMAX>
+struct OpUpdate {
+    static int32_t run(lgf_context* c, double* tr) { return enqueue_update<T, NE, LMAX>(c, tr); }
+};
+
+int32_t measure_any(lgf_context* c, double* trace_slot) { return dispatch<OpMeasure>(c, trace_slot); }
+int32_t update_any(lgf_context* c, double* trace_slot) { return dispatch<OpUpdate>(c, trace_slot); }
 
 // After a poll: the number of updates that really ran fixes the parity.
 void resync_cur(lgf_context* c, int64_t iter_before, int cur_before)
@@ -584,6 +591,8 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
     c->track = p->track_gauge != 0 || p->precision == LGF_MIXED;
     c->phase = use64 && !use32 ? 1 : 0;
     c->nth_plane = nth;
+    for (int m = 0; m < 4; ++m)
+        if (p->dims[m] > 64) c->lmax = 128;
     int32_t rc = LGF_OK;
     auto bail = [&](int32_t code) {
         std::string msg = c->err;
@@ -609,14 +618,15 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
         if (hipMalloc(&c->U0, link) != hipSuccess) { c->err = "hipMalloc U0"; return bail(LGF_E_OUT_OF_MEMORY); }
         c->bytes += link;
     }
-    // momentum tables, indexed by bit-reversed position: 4 sin^2(pi n / L)
+    // momentum tables, indexed by position after the forward transforms:
+    // 4 sin^2(pi n / L) for n = mode_of_position(L, pos)
     std::vector<double> pt;
     double p2max = 0.0;
     for (int m = 0; m < 4; ++m) {
-        const int L = p->dims[m], bits = ilog2(L);
+        const int L = p->dims[m];
         double best = 0.0;
         for (int pos = 0; pos < L; ++pos) {
-            const double s = std::sin(M_PI * (double)bitrev(pos, bits) / (double)L);
+            const double s = std::sin(M_PI * (double)mode_of_position(L, pos) / (double)L);
             pt.push_back(4.0 * s * s);
             best = std::fmax(best, 4.0 * s * s);
         }
@@ -637,13 +647,17 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
     }
     std::memset(c->st_host, 0, sizeof(DevState));
     if (hipMalloc(&c->check, sizeof(unsigned long long) * 3) != hipSuccess) { c->err = "hipMalloc check"; return bail(LGF_E_OUT_OF_MEMORY); }
-    if (use64) {
-        rc = c->NE == 9 ? set_lds_attrs<double, 9>(c) : set_lds_attrs<double, 6>(c);
-        if (rc != LGF_OK) return bail(rc);
-    }
-    if (use32) {
-        rc = c->NE == 9 ? set_lds_attrs<float, 9>(c) : set_lds_attrs<float, 6>(c);
-        if (rc != LGF_OK) return bail(rc);
+    for (int lm : {64, 128}) {
+        if (use64) {
+            rc = c->NE == 9 ? (lm == 64 ? set_lds_attrs<double, 9, 64>(c) : set_lds_attrs<double, 9, 128>(c))
+                            : (lm == 64 ? set_lds_attrs<double, 6, 64>(c) : set_lds_attrs<double, 6, 128>(c));
+            if (rc != LGF_OK) return bail(rc);
+        }
+        if (use32) {
+            rc = c->NE == 9 ? (lm == 64 ? set_lds_attrs<float, 9, 64>(c) : set_lds_attrs<float, 9, 128>(c))
+                            : (lm == 64 ? set_lds_attrs<float, 6, 64>(c) : set_lds_attrs<float, 6, 128>(c));
+            if (rc != LGF_OK) return bail(rc);
+        }
     }
     if ((rc = launch(c, K_STATE, k_state_init, dim3(1), dim3(1), 0, c->st)) != LGF_OK) return bail(rc);
     if ((rc = sync_state(c)) != LGF_OK) return bail(rc);

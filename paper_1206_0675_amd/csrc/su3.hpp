@@ -23,11 +23,32 @@ template <typename T>
 __device__ __forceinline__ C2<T> operator+(C2<T> a, C2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
 template <typename T>
 __device__ __forceinline__ C2<T> operator-(C2<T> a, C2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+// Complex products with explicit fused multiply-adds in a fixed order, so
+// the same product gives the same bits wherever it is evaluated (the
+// compiler may not re-contract them).
 template <typename T>
-__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) { return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ C2<T> cfma(C2<T> a, C2<T> b, C2<T> acc)      // acc + a b
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cfmac(C2<T> a, C2<T> b, C2<T> acc)     // acc + a conj(b)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.y, b.x, acc.y);
+    acc.y = fma(-a.x, b.y, acc.y);
+    return acc;
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) { return cfma(a, b, mk<T>(T(0), T(0))); }
 // a * conj(b)
 template <typename T>
-__device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) { return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+__device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) { return cfmac(a, b, mk<T>(T(0), T(0))); }
 template <typename T>
 __device__ __forceinline__ C2<T> conjg(C2<T> a) { return mk<T>(a.x, -a.y); }
 template <typename T>
@@ -45,11 +66,14 @@ struct M3 {
 
 // third row = (first row x second row)^*
 template <typename T>
+__device__ __forceinline__ C2<T> neg(C2<T> a) { return mk<T>(-a.x, -a.y); }
+
+template <typename T>
 __device__ __forceinline__ void rebuild_row3(M3<T>& m)
 {
-    m.e[6] = conjg(cmul(m.e[1], m.e[5]) - cmul(m.e[2], m.e[4]));
-    m.e[7] = conjg(cmul(m.e[2], m.e[3]) - cmul(m.e[0], m.e[5]));
-    m.e[8] = conjg(cmul(m.e[0], m.e[4]) - cmul(m.e[1], m.e[3]));
+    m.e[6] = conjg(cfma(neg(m.e[2]), m.e[4], cmul(m.e[1], m.e[5])));
+    m.e[7] = conjg(cfma(neg(m.e[0]), m.e[5], cmul(m.e[2], m.e[3])));
+    m.e[8] = conjg(cfma(neg(m.e[1]), m.e[3], cmul(m.e[0], m.e[4])));
 }
 
 template <typename T, int NE>
@@ -67,28 +91,23 @@ __device__ __forceinline__ void store_mat(const M3<T>& m, C2<T>* __restrict__ ba
     for (int e = 0; e < NE; ++e) base[e * stride + s] = m.e[e];
 }
 
-// r = a * u * b^dagger
-template <typename T>
+// r = a * u * b^dagger.  With ROWS = 2 only the first two rows are formed
+// and the third is rebuilt as (row 1 x row 2)^*, as for a link stored in
+// the 12-real form.
+template <typename T, int ROWS = 3>
 __device__ __forceinline__ void a_u_bdag(const M3<T>& a, const M3<T>& u, const M3<T>& b, M3<T>& r)
 {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < ROWS; ++i) {
         C2<T> au[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            C2<T> s = cmul(a.e[3 * i], u.e[k]);
-            s = s + cmul(a.e[3 * i + 1], u.e[3 + k]);
-            s = s + cmul(a.e[3 * i + 2], u.e[6 + k]);
-            au[k] = s;
-        }
+        for (int k = 0; k < 3; ++k)
+            au[k] = cfma(a.e[3 * i + 2], u.e[6 + k], cfma(a.e[3 * i + 1], u.e[3 + k], cmul(a.e[3 * i], u.e[k])));
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            C2<T> s = cmulc(au[0], b.e[3 * l]);
-            s = s + cmulc(au[1], b.e[3 * l + 1]);
-            s = s + cmulc(au[2], b.e[3 * l + 2]);
-            r.e[3 * i + l] = s;
-        }
+        for (int l = 0; l < 3; ++l)
+            r.e[3 * i + l] = cfmac(au[2], b.e[3 * l + 2], cfmac(au[1], b.e[3 * l + 1], cmulc(au[0], b.e[3 * l])));
     }
+    if (ROWS == 2) rebuild_row3(r);
 }
 
 // The eight real degrees of freedom of u - u^dagger - (1/3) Tr(u - u^dagger):
@@ -100,9 +119,12 @@ struct Alg8 {
     C2<T> c[4];
 };
 
+// Written without contraction, so the result from a link held in registers
+// equals the result from the same link stored and read back.
 template <typename T>
 __device__ __forceinline__ void alg_accumulate(Alg8<T>& acc, const M3<T>& u, T sign)
 {
+#pragma clang fp contract(off)
     const T third = T(2) / T(3);
     C2<T> p0 = u.e[1] - conjg(u.e[3]);
     C2<T> p1 = u.e[2] - conjg(u.e[6]);
@@ -113,6 +135,14 @@ __device__ __forceinline__ void alg_accumulate(Alg8<T>& acc, const M3<T>& u, T s
     acc.c[1] = acc.c[1] + scale(p1, sign);
     acc.c[2] = acc.c[2] + scale(p2, sign);
     acc.c[3] = acc.c[3] + scale(p3, sign);
+}
+
+// Re Tr u in FP64, without contraction (see alg_accumulate).
+template <typename T>
+__device__ __forceinline__ double re_trace(const M3<T>& u)
+{
+#pragma clang fp contract(off)
+    return (double)u.e[0].x + (double)u.e[4].x + (double)u.e[8].x;
 }
 
 // |Delta|^2 = sum_ij |Delta_ij|^2 from the packed form (Delta_22 = -i(a + b)).

@@ -54,6 +54,7 @@ inline long long __double_as_longlong(double d)
 }
 using std::isfinite;
 using std::fmax;
+using std::fma;
 using std::sqrt;
 
 template <typename T>
