@@ -95,8 +95,13 @@ typedef struct lgf_params {
                                skips the check                                           */
     int64_t max_iter;       /* lgf_fix gives up after this many gauge transformations    */
     int32_t poll_every;     /* lgf_fix reads theta back after this many iterations       */
-    int32_t reserved;
+    int32_t no_graph;       /* 1: lgf_fix launches kernel by kernel instead of replaying
+                               a captured graph of poll_every iterations                 */
     void *stream;           /* hipStream_t to run on; NULL: the context creates its own */
+    int32_t autotune;       /* 1: time the candidate launch shapes on this lattice at
+                               create and keep the fastest (cached per shape in the file
+                               named by $LGF_TUNE_CACHE, if set)                         */
+    int32_t reserved;
 } lgf_params;
 
 typedef struct lgf_stats {
@@ -159,6 +164,37 @@ int32_t lgf_step(lgf_ctx ctx, int64_t n, lgf_stats *trace);
  * iterations queued after convergence do nothing.  In LGF_MIXED the FP32
  * phase ends at theta < theta_switch and the run finishes in FP64. */
 int32_t lgf_fix(lgf_ctx ctx, lgf_stats *out);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many configurations of different shapes gauge-fixed together
+ * (each kernel launch of an iteration covers every configuration; iterations
+ * are replayed from a captured graph; converged configurations are skipped;
+ * LGF_MIXED switches each configuration to FP64 on its own).  The common
+ * params apply to all members except dims; the accumulated gauge is always
+ * tracked.
+ * ------------------------------------------------------------------------- */
+typedef struct lgf_batch *lgf_batch_t;
+
+/* dims[i] = {Lx, Ly, Lz, Lt} of member i (each as for lgf_create). */
+int32_t lgf_batch_create(const lgf_params *common, int32_t n, const int32_t (*dims)[4], lgf_batch_t *out);
+int32_t lgf_batch_destroy(lgf_batch_t b);
+/* Copy in member i's canonical FP64 links (validated as by lgf_load_links). */
+int32_t lgf_batch_load(lgf_batch_t b, int32_t i, const void *links, int32_t where);
+/* Iterate every loaded member to theta < theta_stop or max_iter.  out (n
+ * entries, or NULL) receives each member's stats; seconds is the batch wall
+ * time.  Returns LGF_OK if every member converged, else the worst status. */
+int32_t lgf_batch_fix(lgf_batch_t b, lgf_stats *out);
+int32_t lgf_batch_store(lgf_batch_t b, int32_t i, void *links, int32_t where);
+int32_t lgf_batch_store_gauge(lgf_batch_t b, int32_t i, void *G, int32_t where);
+/* The launch shape the batch runs with: threads per plane block and the
+ * width (complex values) of the Delta tiles, after autotuning if requested. */
+int32_t lgf_batch_config(lgf_batch_t b, int32_t *plane_threads, int32_t *tile_bytes);
+const char *lgf_batch_last_error(lgf_batch_t b);
+
+/* One call: create, load host links_in[i], fix, store into links_out[i]
+ * (which may alias links_in[i]), destroy.  Returns the worst member status. */
+int32_t lgf_fix_batch(const lgf_params *common, int32_t n, const int32_t (*dims)[4], const double *const *links_in,
+                      double *const *links_out, lgf_stats *out);
 
 /* Per-kernel timing collected when params.profile = 1: for kernel k < n
  * (names from lgf_kernel_name), the number of launches and their summed

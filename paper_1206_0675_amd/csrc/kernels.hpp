@@ -37,12 +37,24 @@ struct Geo {
     int64_t V;
 };
 
+// Per-configuration state on the device.  The host reads it back only at
+// poll points; kernels of an iteration skip a configuration whose `done` is
+// set, so iterations queued past convergence do nothing.
 struct DevState {
-    int64_t iter;        // gauge transformations applied so far
-    double F, theta;     // of the current links
-    double theta_stop;   // done once theta < theta_stop
+    int64_t iter;          // gauge transformations applied so far
+    int64_t iter_fp32;     // ... of which in FP32 arithmetic
+    int64_t max_iter;      // batched runs: stop (unconverged) at this count
+    double F, theta;       // of the current links
+    double theta_stop;     // done once theta < theta_stop
+    double theta_switch;   // batched mixed runs: leave FP32 once theta < theta_switch
     int32_t done;
     int32_t nonfinite;
+    int32_t cur;           // the current links are in U[cur]; the update writes U[1 - cur]
+    int32_t phase;         // 0: FP32 arithmetic, 1: FP64
+    int32_t needs_measure; // Delta, F, theta of the current links are not computed yet
+    int32_t switch_pending;// batched mixed runs: FP32 phase finished, rebuild in FP64
+    int32_t mixed;         // batched runs: FP32 phase followed by FP64
+    int32_t pad;
 };
 
 // plane index handled by this block: consecutive planes stay on one XCD
@@ -184,23 +196,18 @@ __global__ void __launch_bounds__(256) k_field_identity(int64_t V, C2<T>* __rest
     for (int e = 0; e < NE; ++e) f[e * V + s] = mk<T>((e == 0 || e == 4 || e == 8) ? T(1) : T(0), T(0));
 }
 
+
 // ---------------------------------------------------------------------------
-// a1 + a2 + a3(x, y):  gauge transform, Delta, F and theta terms, forward
-// (x, y) FFT of the packed Delta.  One block per (z, t) plane.
+// a1 + a2 + a3(x, y) for one (z, t) plane q: gauge transform, Delta, F and
+// theta terms, forward (x, y) FFT of the packed Delta into D.
+//   red: 2 * blockDim doubles of LDS; buf: 4 * NP complex of LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int NE, bool APPLY_G, int LMAX>
-__global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restrict__ Uin, C2<T>* __restrict__ Uout,
-                                                 const C2<T>* __restrict__ g, C2<T>* __restrict__ D,
-                                                 double* __restrict__ partial, const C2<T>* __restrict__ twx,
-                                                 const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
+__device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ Uin, C2<T>* __restrict__ Uout,
+                              const C2<T>* __restrict__ g, C2<T>* __restrict__ D, double* __restrict__ partial,
+                              const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy, double* red, C2<T>* buf)
 {
-    if (st->done) return;
-    HIP_DYNAMIC_SHARED(double, lds_raw)
-    double* red = lds_raw;                                   // 2 * blockDim doubles
-    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x);   // 4 fields x NP
-
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int q = plane_of_block(blockIdx.x, geo.NQ);
     const int Lx = geo.L[0], Ly = geo.L[1], Lz = geo.L[2], Lt = geo.L[3];
     const int NP = geo.NP;
     const int64_t V = geo.V;
@@ -272,7 +279,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restric
 }
 
 // ---------------------------------------------------------------------------
-// a3(z, t) + a4 + a5(z, t): one block per (tile of W plane positions, field)
+// a3(z, t) + a4 + a5(z, t) for one (tile j of W plane positions, field c)
 // ---------------------------------------------------------------------------
 // ptab: four tables 4 sin^2(pi n / L_mu), indexed by position along the axis
 // after the forward transforms (x table first), i.e. for the mode
@@ -291,6 +298,12 @@ struct SpectralScale {
         return accel ? (p2 > 0.0 ? c0 / p2 : 0.0) : c0;
     }
 };
+
+__device__ __forceinline__ SpectralScale make_scale(const Geo& geo, const double* ptab, double c0, int accel)
+{
+    return SpectralScale{ptab, ptab + geo.L[0], ptab + geo.L[0] + geo.L[1], ptab + geo.L[0] + geo.L[1] + geo.L[2],
+                         c0, accel};
+}
 
 // The t axis of the (z, t) block: forward DFT, spectral factor and inverse
 // DFT of each contiguous group in registers, between the two A passes.
@@ -325,15 +338,10 @@ __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ t
 }
 
 template <typename T, int LMAX>
-__global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
-                                            const C2<T>* __restrict__ twt, const double* __restrict__ ptab,
-                                            double c0, int accel, const DevState* __restrict__ st)
+__device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
+                         const C2<T>* __restrict__ twt, const SpectralScale& sc, C2<T>* buf)
 {
-    if (st->done) return;
-    HIP_DYNAMIC_SHARED(double, lds_raw)
-    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
     const int W = geo.W, NQ = geo.NQ, n = NQ * W;
     C2<T>* src = D + (int64_t)(j * 4 + c) * NQ * W;
     for (int i = tid; i < n; i += nth) buf[i] = src[i];
@@ -341,8 +349,6 @@ __global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, cons
     const int Lz = geo.L[2];
     const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
     const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
-    const SpectralScale sc{ptab, ptab + geo.L[0], ptab + geo.L[0] + geo.L[1], ptab + geo.L[0] + geo.L[1] + Lz,
-                           c0, accel};
     fft_fwd<T, LMAX>(buf, Lz, zl, twz, tid, nth);
     switch (geo.L[3]) {
     case 4: zt_t_axis<T, 4>(buf, tl, twt, tid, nth, sc, geo, j); break;
@@ -357,19 +363,15 @@ __global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, cons
 }
 
 // ---------------------------------------------------------------------------
-// a5(x, y) + a6 (+ a8): inverse (x, y) FFT, g = reunit(1 + dtilde) in FP64,
-// and optionally G <- reunit(g G).  One block per (z, t) plane.
+// a5(x, y) + a6 (+ a8) for one plane q: inverse (x, y) FFT,
+// g = reunit(1 + dtilde) in FP64, optionally G <- reunit(g G).
 // ---------------------------------------------------------------------------
 template <typename T, int NE, bool ACC_G, int LMAX>
-__global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict__ D, C2<T>* __restrict__ g,
-                                               C2<T>* __restrict__ G, const C2<T>* __restrict__ twx,
-                                               const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
+__device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, C2<T>* __restrict__ g,
+                            C2<T>* __restrict__ G, const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
+                            C2<T>* buf)
 {
-    if (st->done) return;
-    HIP_DYNAMIC_SHARED(double, lds_raw)
-    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int q = plane_of_block(blockIdx.x, geo.NQ);
     const int NP = geo.NP, W = geo.W;
     const int64_t V = geo.V;
     for (int i = tid; i < 4 * NP; i += nth) {
@@ -395,12 +397,9 @@ __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict_
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    C2<double> acc = cmul(m.e[3 * i], Gd.e[k]);
-                    acc = acc + cmul(m.e[3 * i + 1], Gd.e[3 + k]);
-                    acc = acc + cmul(m.e[3 * i + 2], Gd.e[6 + k]);
-                    r.e[3 * i + k] = acc;
-                }
+                for (int k = 0; k < 3; ++k)
+                    r.e[3 * i + k] =
+                        cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
             reunit(r);
             store_mat<T, NE>(cast_mat<T>(r), G, V, s);
         }
@@ -408,15 +407,13 @@ __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// a7: F = sum/(12V), theta = sum/(3V) over the per-plane partials, in plane
-// order; counts the update, records (F, theta), sets the stop flag.
+// a7: F = sum/(12V), theta = sum/(3V) over the per-plane partials in plane
+// order (one block).  counts_update: the partials are of freshly transformed
+// links, so the update is counted and the link buffers swap roles.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partial, int nq, int64_t V,
-                                                DevState* __restrict__ st, double* __restrict__ trace,
-                                                int counts_update)
+__device__ __forceinline__ void reduce_state(const double* __restrict__ partial, int nq, int64_t V, DevState* st,
+                             double* __restrict__ trace, int counts_update, double* red)
 {
-    if (st->done) return;
-    __shared__ double red[2 * 256];
     const int tid = threadIdx.x, nth = blockDim.x;
     double a = 0.0, b = 0.0;
     for (int i = tid; i < nq; i += nth) {
@@ -427,7 +424,12 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
     block_sum2(a, b, red, tid, nth, &fs, &ts);
     if (tid == 0) {
         const double F = fs / (12.0 * (double)V), th = ts / (3.0 * (double)V);
-        if (counts_update) st->iter += 1;
+        if (counts_update) {
+            st->iter += 1;
+            if (st->phase == 0) st->iter_fp32 += 1;
+            st->cur ^= 1;
+        }
+        st->needs_measure = 0;
         st->F = F;
         st->theta = th;
         if (trace) {
@@ -437,10 +439,63 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
         if (!(th == th) || th > 1e300) {
             st->nonfinite = 1;
             st->done = 1;
-        } else if (th < st->theta_stop) {
+        } else if (st->mixed && st->phase == 0) {
+            if (th < st->theta_switch) st->switch_pending = 1;
+            else if (st->iter >= st->max_iter) st->done = 1;
+        } else if (th < st->theta_stop || st->iter >= st->max_iter) {
             st->done = 1;
         }
     }
+    __syncthreads();
+}
+
+// ===========================================================================
+// single-configuration kernels (one lattice per launch)
+// ===========================================================================
+template <typename T, int NE, bool APPLY_G, int LMAX>
+__global__ void __launch_bounds__(256) k_measure(Geo geo, C2<T>* U0, C2<T>* U1, const C2<T>* __restrict__ g,
+                                                 C2<T>* __restrict__ D, double* __restrict__ partial,
+                                                 const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
+                                                 const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    const int cur = st->cur;
+    measure_plane<T, NE, APPLY_G, LMAX>(geo, plane_of_block(blockIdx.x, geo.NQ), cur ? U1 : U0, cur ? U0 : U1, g, D,
+                                        partial, twx, twy, lds_raw,
+                                        reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
+}
+
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
+                                            const C2<T>* __restrict__ twt, const double* __restrict__ ptab,
+                                            double c0, int accel, const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    zt_block<T, LMAX>(geo, blockIdx.x >> 2, blockIdx.x & 3, D, twz, twt, make_scale(geo, ptab, c0, accel),
+                      reinterpret_cast<C2<T>*>(lds_raw));
+}
+
+template <typename T, int NE, bool ACC_G, int LMAX>
+__global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict__ D, C2<T>* __restrict__ g,
+                                               C2<T>* __restrict__ G, const C2<T>* __restrict__ twx,
+                                               const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    gauge_plane<T, NE, ACC_G, LMAX>(geo, plane_of_block(blockIdx.x, geo.NQ), D, g, G, twx, twy,
+                                    reinterpret_cast<C2<T>*>(lds_raw));
+}
+
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partial, int nq, int64_t V,
+                                                DevState* __restrict__ st, double* __restrict__ trace,
+                                                int counts_update)
+{
+    if (st->done) return;
+    __shared__ double red[2 * 256];
+    reduce_state(partial, nq, V, st, trace, counts_update, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,11 +505,9 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
 // promoted gauge is stored as G64.
 // ---------------------------------------------------------------------------
 template <int NE>
-__global__ void __launch_bounds__(256) k_promote_gauge(int64_t V, const C2<float>* __restrict__ G32,
-                                                       C2<double>* __restrict__ G64)
+__device__ __forceinline__ void promote_site(int64_t V, int64_t s, const C2<float>* __restrict__ G32,
+                                             C2<double>* __restrict__ G64)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
     M3<float> a;
     load_mat<float, NE>(a, G32, V, s);
     M3<double> m = cast_mat<double>(a);
@@ -463,14 +516,10 @@ __global__ void __launch_bounds__(256) k_promote_gauge(int64_t V, const C2<float
 }
 
 template <int NE>
-__global__ void __launch_bounds__(256) k_switch(Geo geo, const C2<double>* __restrict__ U0, const C2<double>* __restrict__ G,
-                                                C2<double>* __restrict__ U)
+__device__ __forceinline__ void switch_link(const Geo& geo, int mu, int64_t s, const C2<double>* __restrict__ U0,
+                                            const C2<double>* __restrict__ G, C2<double>* __restrict__ U)
 {
-    const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t V = geo.V;
-    if (li >= 4 * V) return;
-    const int mu = (int)(li / V);
-    const int64_t s = li - (int64_t)mu * V;
     int64_t rem = s;
     int c[4];
 #pragma unroll
@@ -484,8 +533,164 @@ __global__ void __launch_bounds__(256) k_switch(Geo geo, const C2<double>* __res
     load_mat<double, NE>(a, G, V, s);
     load_mat<double, NE>(u, U0 + (int64_t)mu * NE * V, V, s);
     load_mat<double, NE>(b, G, V, sn);
-    a_u_bdag(a, u, b, r);
+    a_u_bdag<double, (NE == 6 ? 2 : 3)>(a, u, b, r);
     store_mat<double, NE>(r, U + (int64_t)mu * NE * V, V, s);
+}
+
+template <int NE>
+__global__ void __launch_bounds__(256) k_promote_gauge(int64_t V, const C2<float>* __restrict__ G32,
+                                                       C2<double>* __restrict__ G64)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < V) promote_site<NE>(V, s, G32, G64);
+}
+
+template <int NE>
+__global__ void __launch_bounds__(256) k_switch(Geo geo, const C2<double>* __restrict__ U0,
+                                                const C2<double>* __restrict__ G, C2<double>* __restrict__ U)
+{
+    const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (li >= 4 * geo.V) return;
+    const int mu = (int)(li / geo.V);
+    switch_link<NE>(geo, mu, li - (int64_t)mu * geo.V, U0, G, U);
+}
+
+// ===========================================================================
+// batched kernels: many lattices of different shapes per launch (a11)
+// ===========================================================================
+// One descriptor per configuration and precision.  Work items are
+// (configuration, plane) for the plane kernels and (configuration, tile,
+// field) for the (z, t) kernel, packed as cfg << 20 | index.  Every kernel
+// walks its item list with a grid-stride loop (a persistent grid sized to
+// the device), and skips the items of configurations that are not in the
+// kernel's phase (FP32 / FP64, measure / update) or are done.
+template <typename T>
+struct BatchCfg {
+    Geo geo;
+    C2<T>* U[2];
+    C2<T>* g;
+    C2<T>* D;
+    C2<T>* G;
+    const C2<T>* tw[4];
+    const double* ptab;
+    double* partial;
+    DevState* st;
+    double c0;
+    int accel;
+    int pad;
+};
+
+constexpr int kItemShift = 20;
+
+// gate: 0 = fresh measure of configurations that need one, 1 = update
+__device__ __forceinline__ bool batch_active(const DevState* st, int phase, int gate)
+{
+    if (st->done || st->switch_pending || st->phase != phase) return false;
+    return gate == 0 ? st->needs_measure != 0 : st->needs_measure == 0;
+}
+
+template <typename T, int NE, bool APPLY_G, int LMAX>
+__global__ void __launch_bounds__(256) kb_measure(const BatchCfg<T>* __restrict__ cfgs, const uint32_t* __restrict__ items,
+                                                  int nitems, int phase)
+{
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t w = items[it];
+        const BatchCfg<T>& bc = cfgs[w >> kItemShift];
+        if (!batch_active(bc.st, phase, APPLY_G ? 1 : 0)) continue;
+        const int cur = bc.st->cur;
+        __syncthreads();
+        measure_plane<T, NE, APPLY_G, LMAX>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), cur ? bc.U[1] : bc.U[0],
+                                            cur ? bc.U[0] : bc.U[1], bc.g, bc.D, bc.partial, bc.tw[0], bc.tw[1],
+                                            lds_raw, reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
+    }
+}
+
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(512) kb_zt(const BatchCfg<T>* __restrict__ cfgs, const uint32_t* __restrict__ items,
+                                             int nitems, int phase)
+{
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t w = items[it];
+        const BatchCfg<T>& bc = cfgs[w >> kItemShift];
+        if (!batch_active(bc.st, phase, 1)) continue;
+        const int jc = (int)(w & ((1u << kItemShift) - 1));
+        __syncthreads();
+        zt_block<T, LMAX>(bc.geo, jc >> 2, jc & 3, bc.D, bc.tw[2], bc.tw[3], make_scale(bc.geo, bc.ptab, bc.c0, bc.accel),
+                          reinterpret_cast<C2<T>*>(lds_raw));
+    }
+}
+
+template <typename T, int NE, int LMAX>
+__global__ void __launch_bounds__(256) kb_gauge(const BatchCfg<T>* __restrict__ cfgs, const uint32_t* __restrict__ items,
+                                                int nitems, int phase)
+{
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t w = items[it];
+        const BatchCfg<T>& bc = cfgs[w >> kItemShift];
+        if (!batch_active(bc.st, phase, 1)) continue;
+        __syncthreads();
+        gauge_plane<T, NE, true, LMAX>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), bc.D, bc.g, bc.G, bc.tw[0],
+                                       bc.tw[1], reinterpret_cast<C2<T>*>(lds_raw));
+    }
+}
+
+// one block per configuration
+template <typename T>
+__global__ void __launch_bounds__(256) kb_reduce(const BatchCfg<T>* __restrict__ cfgs, int phase, int gate)
+{
+    __shared__ double red[2 * 256];
+    const BatchCfg<T>& bc = cfgs[blockIdx.x];
+    if (!batch_active(bc.st, phase, gate)) return;
+    reduce_state(bc.partial, bc.geo.NQ, bc.geo.V, bc.st, nullptr, gate, red);
+}
+
+// Mixed runs: the FP32 phase of a configuration ended (switch_pending).
+// Step 1: G64 = reunit(G32); step 2: U64 = G64 U0 G64^dag(x+mu) into U64[0];
+// step 3: FP64 phase, links in U[0], Delta to be measured.
+template <int NE>
+__global__ void __launch_bounds__(256) kb_promote(const BatchCfg<float>* __restrict__ c32,
+                                                  const BatchCfg<double>* __restrict__ c64,
+                                                  const uint32_t* __restrict__ items, int nitems)
+{
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t w = items[it];
+        const int cfg = (int)(w >> kItemShift);
+        if (!c64[cfg].st->switch_pending || c64[cfg].st->done) continue;
+        const Geo& geo = c64[cfg].geo;
+        const int64_t q0 = (int64_t)(w & ((1u << kItemShift) - 1)) * geo.NP;
+        for (int p = threadIdx.x; p < geo.NP; p += blockDim.x) promote_site<NE>(geo.V, q0 + p, c32[cfg].G, c64[cfg].G);
+    }
+}
+
+template <int NE>
+__global__ void __launch_bounds__(256) kb_switch(const BatchCfg<double>* __restrict__ c64, const C2<double>* const* U0,
+                                                 const uint32_t* __restrict__ items, int nitems)
+{
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t w = items[it];
+        const int cfg = (int)(w >> kItemShift);
+        const BatchCfg<double>& bc = c64[cfg];
+        if (!bc.st->switch_pending || bc.st->done) continue;
+        const int64_t q0 = (int64_t)(w & ((1u << kItemShift) - 1)) * bc.geo.NP;
+        for (int i = threadIdx.x; i < 4 * bc.geo.NP; i += blockDim.x)
+            switch_link<NE>(bc.geo, i / bc.geo.NP, q0 + i % bc.geo.NP, U0[cfg], bc.G, bc.U[0]);
+    }
+}
+
+template <int UNUSED = 0>
+__global__ void kb_switch_done(const BatchCfg<double>* __restrict__ c64, int ncfg)
+{
+    const int cfg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cfg >= ncfg) return;
+    DevState* st = c64[cfg].st;
+    if (!st->switch_pending || st->done) return;
+    st->switch_pending = 0;
+    st->phase = 1;
+    st->cur = 0;
+    st->needs_measure = 1;
 }
 
 }  // namespace lgf

@@ -20,58 +20,36 @@
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
-#include "lgf.h"
+#include "runtime.hpp"
 
 using namespace lgf;
 
-namespace {
-
-enum KernelId {
-    K_LOAD, K_STORE, K_MEASURE, K_TRANSFORM_MEASURE, K_ZT, K_GAUGE, K_REDUCE, K_FIELD, K_SWITCH, K_STATE, K_COUNT
-};
-const char* const kKernelNames[K_COUNT] = {"load",   "store",  "measure", "transform_measure", "zt_fft_scale",
-                                           "gauge",  "reduce", "field",   "precision_switch",  "state"};
-
-constexpr size_t kMaxLds = 160 * 1024;
-constexpr size_t kMaxLdsZt = 128 * 1024;
-
-template <typename T>
-struct Bufs {
-    C2<T>* U[2] = {nullptr, nullptr};
-    C2<T>* g = nullptr;
-    C2<T>* D = nullptr;
-    C2<T>* G = nullptr;
-    C2<T>* tw = nullptr;     // Lx + Ly + Lz + Lt entries
-    Geo geo{};
-    int tw_off[4] = {0, 0, 0, 0};
-};
-
-struct Pending {
-    int k;
-    hipEvent_t a, b;
-};
-
-int ilog2(int v)
-{
-    int l = 0;
-    while ((1 << l) < v) ++l;
-    return l;
-}
-
-bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
-
-}  // namespace
+using namespace lgf::rt;
 
 // small kernels on the device state (no memset: safe inside graphs)
-__global__ void k_state_init(DevState* st)
+__global__ void k_state_init(DevState* st, int phase)
 {
     st->iter = 0;
+    st->iter_fp32 = 0;
+    st->max_iter = 0x7fffffffffffffffLL;   // the host counts iterations for single lattices
     st->F = 0.0;
     st->theta = 0.0;
     st->theta_stop = -1.0;
+    st->theta_switch = 0.0;
     st->done = 0;
     st->nonfinite = 0;
+    st->cur = 0;
+    st->phase = phase;
+    st->needs_measure = 1;
+    st->switch_pending = 0;
+    st->mixed = 0;
+}
+
+__global__ void k_state_phase(DevState* st, int phase)
+{
+    st->phase = phase;
+    st->cur = 0;
+    st->needs_measure = 1;
 }
 
 __global__ void k_state_stop(DevState* st, double theta_stop, int valid)
@@ -81,17 +59,15 @@ __global__ void k_state_stop(DevState* st, double theta_stop, int valid)
     st->done = (valid && st->theta < theta_stop) ? 1 : 0;
 }
 
-struct lgf_context {
+struct lgf_context : Runner {
     lgf_params p{};
     int NE = 9;
-    hipStream_t stream = nullptr;
     bool own_stream = false;
     int phase = 1;            // 1: FP64 arithmetic, 0: FP32
     bool use64 = false, use32 = false;
     bool track = false;
     bool loaded = false;
     bool delta_valid = false; // D and the state hold Delta, F, theta of the current links
-    int cur = 0;              // links are in U[cur] (mirrors the device-side update parity)
     Bufs<double> d;
     Bufs<float> f;
     C2<double>* U0 = nullptr; // LGF_MIXED: the links as loaded, FP64
@@ -107,31 +83,11 @@ struct lgf_context {
     double c0 = 0.0;          // (alpha/2) p2max / V
     int nth_plane = 256;
     int lmax = 64;            // longest axis rounded up to 64 or 128 (kernel variant)
-    std::string err;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<Pending> pending;
-    int64_t prof_n[K_COUNT] = {};
-    double prof_ms[K_COUNT] = {};
+    hipStream_t cap_stream = nullptr;          // private stream that graph capture runs on
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // per phase: poll_every updates
 };
 
 namespace {
-
-thread_local std::string g_noctx_err;
-
-int32_t fail(lgf_context* c, int32_t code, const std::string& msg)
-{
-    if (c) c->err = msg;
-    else g_noctx_err = msg;
-    return code;
-}
-
-#define HIPCHK(c, call)                                                                          \
-    do {                                                                                         \
-        hipError_t e_ = (call);                                                                  \
-        if (e_ != hipSuccess)                                                                    \
-            return fail((c), e_ == hipErrorOutOfMemory ? LGF_E_OUT_OF_MEMORY : LGF_E_DEVICE,      \
-                        std::string(#call) + ": " + hipGetErrorString(e_));                      \
-    } while (0)
 
 template <typename T>
 Bufs<T>& bufs(lgf_context* c);
@@ -140,62 +96,11 @@ Bufs<double>& bufs<double>(lgf_context* c) { return c->d; }
 template <>
 Bufs<float>& bufs<float>(lgf_context* c) { return c->f; }
 
-hipEvent_t take_event(lgf_context* c)
-{
-    if (!c->ev_pool.empty()) {
-        hipEvent_t e = c->ev_pool.back();
-        c->ev_pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-void prof_collect(lgf_context* c)
-{
-    for (auto& pe : c->pending) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
-            c->prof_n[pe.k] += 1;
-            c->prof_ms[pe.k] += ms;
-        }
-        c->ev_pool.push_back(pe.a);
-        c->ev_pool.push_back(pe.b);
-    }
-    c->pending.clear();
-}
-
-template <typename K, typename... Args>
-int32_t launch(lgf_context* c, int kid, K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
-{
-    hipEvent_t a = nullptr, b = nullptr;
-    if (c->p.profile) {
-        a = take_event(c);
-        b = take_event(c);
-        if (a) (void)hipEventRecord(a, c->stream);
-    }
-    hipLaunchKernelGGL(kernel, grid, block, lds, c->stream, args...);
-    hipError_t e = hipGetLastError();
-    if (c->p.profile && a && b) {
-        (void)hipEventRecord(b, c->stream);
-        c->pending.push_back(Pending{kid, a, b});
-    }
-    if (e != hipSuccess) return fail(c, LGF_E_DEVICE, std::string("launch of ") + kKernelNames[kid] + ": " + hipGetErrorString(e));
-    return LGF_OK;
-}
-
-#define TRY(expr)                          \
-    do {                                   \
-        int32_t r_ = (expr);               \
-        if (r_ != LGF_OK) return r_;       \
-    } while (0)
-
 int32_t sync_state(lgf_context* c)
 {
     HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->p.profile) prof_collect(c);
+    if (c->profile) prof_collect(c);
     return LGF_OK;
 }
 
@@ -207,79 +112,6 @@ int32_t set_stop(lgf_context* c, double theta_stop)
 // ----------------------------------------------------------------------------
 // geometry and tables
 // ----------------------------------------------------------------------------
-template <typename T>
-Geo make_geo(const int32_t* dims)
-{
-    Geo g{};
-    for (int m = 0; m < 4; ++m) {
-        g.L[m] = dims[m];
-        g.logL[m] = ilog2(dims[m]);
-    }
-    g.NP = dims[0] * dims[1];
-    g.logNP = ilog2(g.NP);
-    g.NQ = dims[2] * dims[3];
-    g.logNQ = ilog2(g.NQ);
-    g.V = (int64_t)g.NP * g.NQ;
-    // runs of 64 bytes where the (z, t) block still fits its LDS budget
-    int W = (int)(64 / sizeof(C2<T>));
-    if (W > g.NP) W = g.NP;
-    while (W > 1 && (size_t)W * g.NQ * sizeof(C2<T>) > kMaxLdsZt) W >>= 1;
-    g.W = W;
-    g.logW = ilog2(W);
-    return g;
-}
-
-template <typename T>
-bool shape_fits(const int32_t* dims, int nth)
-{
-    const size_t np = (size_t)dims[0] * dims[1], nq = (size_t)dims[2] * dims[3];
-    if (4 * np * sizeof(C2<T>) + 2 * nth * sizeof(double) > kMaxLds) return false;
-    if (nq * sizeof(C2<T>) > kMaxLdsZt) return false;
-    return true;
-}
-
-template <typename T>
-int32_t alloc_bufs(lgf_context* c, Bufs<T>& b)
-{
-    const int32_t* dims = c->p.dims;
-    b.geo = make_geo<T>(dims);
-    const int64_t V = b.geo.V;
-    const size_t link = sizeof(C2<T>) * (size_t)4 * c->NE * V;
-    const size_t field = sizeof(C2<T>) * (size_t)c->NE * V;
-    HIPCHK(c, hipMalloc(&b.U[0], link));
-    HIPCHK(c, hipMalloc(&b.U[1], link));
-    HIPCHK(c, hipMalloc(&b.g, field));
-    HIPCHK(c, hipMalloc(&b.D, sizeof(C2<T>) * (size_t)4 * V));
-    c->bytes += 2 * link + field + sizeof(C2<T>) * 4 * V;
-    if (c->track) {
-        HIPCHK(c, hipMalloc(&b.G, field));
-        c->bytes += field;
-    }
-    std::vector<C2<T>> tw;
-    for (int m = 0; m < 4; ++m) {
-        b.tw_off[m] = (int)tw.size();
-        for (int k = 0; k < dims[m]; ++k) {
-            const double a = -2.0 * M_PI * (double)k / (double)dims[m];
-            tw.push_back(mk<T>((T)std::cos(a), (T)std::sin(a)));
-        }
-    }
-    HIPCHK(c, hipMalloc(&b.tw, sizeof(C2<T>) * tw.size()));
-    HIPCHK(c, hipMemcpy(b.tw, tw.data(), sizeof(C2<T>) * tw.size(), hipMemcpyHostToDevice));
-    return LGF_OK;
-}
-
-template <typename T>
-void free_bufs(Bufs<T>& b)
-{
-    (void)hipFree(b.U[0]);
-    (void)hipFree(b.U[1]);
-    (void)hipFree(b.g);
-    (void)hipFree(b.D);
-    (void)hipFree(b.G);
-    (void)hipFree(b.tw);
-    b = Bufs<T>();
-}
-
 template <typename T, int NE, int LMAX>
 int32_t set_lds_attrs(lgf_context* c)
 {
@@ -311,17 +143,20 @@ int32_t enqueue_measure(lgf_context* c, double* trace_slot)
     const Geo& g = b.geo;
     const size_t lds = 4 * g.NP * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double);
     TRY(launch(c, K_MEASURE, k_measure<T, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), lds, g,
-               (const C2<T>*)b.U[c->cur], (C2<T>*)nullptr, (const C2<T>*)nullptr, b.D, c->partial,
+               b.U[0], b.U[1], (const C2<T>*)nullptr, b.D, c->partial,
                (const C2<T>*)(b.tw + b.tw_off[0]), (const C2<T>*)(b.tw + b.tw_off[1]), (const DevState*)c->st));
-    TRY(launch(c, K_REDUCE, k_reduce, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
+    TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
                trace_slot, 0));
     c->delta_valid = true;
     return LGF_OK;
 }
 
 // filter, g, transform, Delta/F/theta of the new links (the loop body of
-// Algorithm 1).  The update flips cur; when the device stop flag is set the
-// kernels do nothing and the host learns the real parity at the next poll.
+// Algorithm 1).  The transform reads U[cur] and writes U[1 - cur] with cur
+// taken from the device state, which the reduction flips; when the stop flag
+// is set every kernel returns at once.  The launch arguments do not change
+// from one iteration to the next, so a chunk of iterations can be captured
+// once in a graph and replayed.
 template <typename T, int NE, int LMAX>
 int32_t enqueue_update(lgf_context* c, double* trace_slot)
 {
@@ -342,11 +177,10 @@ int32_t enqueue_update(lgf_context* c, double* trace_slot)
         TRY(launch(c, K_GAUGE, k_gauge<T, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.g,
                    b.G, twx, twy, (const DevState*)c->st));
     TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<T, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane), mlds, g,
-               (const C2<T>*)b.U[c->cur], b.U[1 - c->cur], (const C2<T>*)b.g, b.D, c->partial, twx, twy,
+               b.U[0], b.U[1], (const C2<T>*)b.g, b.D, c->partial, twx, twy,
                (const DevState*)c->st));
-    TRY(launch(c, K_REDUCE, k_reduce, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
+    TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
                trace_slot, 1));
-    c->cur ^= 1;
     return LGF_OK;
 }
 
@@ -375,21 +209,49 @@ struct OpUpdate {
 int32_t measure_any(lgf_context* c, double* trace_slot) { return dispatch<OpMeasure>(c, trace_slot); }
 int32_t update_any(lgf_context* c, double* trace_slot) { return dispatch<OpUpdate>(c, trace_slot); }
 
-// After a poll: the number of updates that really ran fixes the parity.
-void resync_cur(lgf_context* c, int64_t iter_before, int cur_before)
+// n updates for lgf_fix.  A full chunk of poll_every updates is captured once
+// per precision phase into a graph (the launch arguments never change) and
+// replayed; shorter chunks, profiling runs and no_graph contexts launch
+// kernel by kernel.
+int32_t enqueue_chunk(lgf_context* c, int64_t n)
 {
-    const int64_t ran = c->st_host->iter - iter_before;
-    c->cur = (int)((cur_before + ran) & 1);
+    if (c->profile || c->p.no_graph || n != c->p.poll_every) {
+        for (int64_t k = 0; k < n; ++k) TRY(update_any(c, nullptr));
+        return LGF_OK;
+    }
+    hipGraphExec_t& ex = c->gexec[c->phase];
+    if (!ex) {
+        if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t run = c->stream;
+        c->stream = c->cap_stream;
+        hipGraph_t graph = nullptr;
+        int32_t rc = LGF_OK;
+        if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = fail(c, LGF_E_DEVICE, "hipStreamBeginCapture failed");
+        } else {
+            for (int64_t k = 0; k < n && rc == LGF_OK; ++k) rc = update_any(c, nullptr);
+            const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+            if (rc == LGF_OK && e != hipSuccess) rc = fail(c, LGF_E_DEVICE, "hipStreamEndCapture failed");
+        }
+        c->stream = run;
+        if (rc == LGF_OK && hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) {
+            ex = nullptr;
+            rc = fail(c, LGF_E_DEVICE, "hipGraphInstantiate failed");
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc != LGF_OK) return rc;
+    }
+    HIPCHK(c, hipGraphLaunch(ex, c->stream));
+    return LGF_OK;
 }
 
-int64_t blocks_for(int64_t n, int per) { return (n + per - 1) / per; }
 
 template <typename T, int NE>
 int32_t enqueue_store(lgf_context* c, double* dst)
 {
     Bufs<T>& b = bufs<T>(c);
     return launch(c, K_STORE, k_store<T, NE>, dim3((unsigned)blocks_for(4 * b.geo.V, 256)), dim3(256), 0,
-                  b.geo.V, (const C2<T>*)b.U[c->cur], dst);
+                  b.geo.V, (const C2<T>*)b.U[c->st_host->cur], dst);
 }
 
 int32_t store_any(lgf_context* c, double* dst)
@@ -429,10 +291,6 @@ int32_t enqueue_switch(lgf_context* c)
     return LGF_OK;
 }
 
-double now_s()
-{
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 void fill_stats(lgf_context* c, lgf_stats* out, int32_t status, double t0)
 {
@@ -585,6 +443,7 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
     lgf_context* c = new (std::nothrow) lgf_context();
     if (!c) return fail(nullptr, LGF_E_OUT_OF_MEMORY, "host allocation failed");
     c->p = *p;
+    c->profile = p->profile;
     c->NE = p->storage == LGF_STORE12 ? 6 : 9;
     c->use64 = use64;
     c->use32 = use32;
@@ -610,28 +469,16 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
         }
         c->own_stream = true;
     }
-    if (use64 && (rc = alloc_bufs<double>(c, c->d)) != LGF_OK) return bail(rc);
-    if (use32 && (rc = alloc_bufs<float>(c, c->f)) != LGF_OK) return bail(rc);
+    if (use64 && (rc = alloc_bufs<double>(c, p->dims, c->NE, c->track, 64, c->d, c->bytes)) != LGF_OK) return bail(rc);
+    if (use32 && (rc = alloc_bufs<float>(c, p->dims, c->NE, c->track, 64, c->f, c->bytes)) != LGF_OK) return bail(rc);
     const Geo& g = use64 ? c->d.geo : c->f.geo;
     if (p->precision == LGF_MIXED) {
         const size_t link = sizeof(C2<double>) * (size_t)4 * c->NE * g.V;
         if (hipMalloc(&c->U0, link) != hipSuccess) { c->err = "hipMalloc U0"; return bail(LGF_E_OUT_OF_MEMORY); }
         c->bytes += link;
     }
-    // momentum tables, indexed by position after the forward transforms:
-    // 4 sin^2(pi n / L) for n = mode_of_position(L, pos)
-    std::vector<double> pt;
     double p2max = 0.0;
-    for (int m = 0; m < 4; ++m) {
-        const int L = p->dims[m];
-        double best = 0.0;
-        for (int pos = 0; pos < L; ++pos) {
-            const double s = std::sin(M_PI * (double)mode_of_position(L, pos) / (double)L);
-            pt.push_back(4.0 * s * s);
-            best = std::fmax(best, 4.0 * s * s);
-        }
-        p2max += best;
-    }
+    const std::vector<double> pt = momentum_tables(p->dims, &p2max);
     c->c0 = 0.5 * p->alpha * (p->accel == LGF_ACCEL_FOURIER ? p2max : 1.0) / (double)g.V;
     if (hipMalloc(&c->ptab, sizeof(double) * pt.size()) != hipSuccess) { c->err = "hipMalloc ptab"; return bail(LGF_E_OUT_OF_MEMORY); }
     if (hipMemcpy(c->ptab, pt.data(), sizeof(double) * pt.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -659,7 +506,7 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
             if (rc != LGF_OK) return bail(rc);
         }
     }
-    if ((rc = launch(c, K_STATE, k_state_init, dim3(1), dim3(1), 0, c->st)) != LGF_OK) return bail(rc);
+    if ((rc = launch(c, K_STATE, k_state_init, dim3(1), dim3(1), 0, c->st, c->phase)) != LGF_OK) return bail(rc);
     if ((rc = sync_state(c)) != LGF_OK) return bail(rc);
     *out = c;
     return LGF_OK;
@@ -678,11 +525,10 @@ int32_t lgf_destroy(lgf_ctx c)
     (void)hipFree(c->check);
     (void)hipFree(c->trace_dev);
     if (c->st_host) (void)hipHostFree(c->st_host);
-    for (auto& pe : c->pending) {
-        (void)hipEventDestroy(pe.a);
-        (void)hipEventDestroy(pe.b);
-    }
-    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    release_events(c);
+    for (auto& ex : c->gexec)
+        if (ex) (void)hipGraphExecDestroy(ex);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return LGF_OK;
@@ -723,7 +569,8 @@ int32_t lgf_load_links(lgf_ctx c, const void* links, int32_t where)
         if (rc != LGF_OK) break;
         if (c->use64 && (rc = enqueue_identity_G<double>(c)) != LGF_OK) break;
         if (c->use32 && (rc = enqueue_identity_G<float>(c)) != LGF_OK) break;
-        if ((rc = launch(c, K_STATE, k_state_init, dim3(1), dim3(1), 0, c->st)) != LGF_OK) break;
+        if ((rc = launch(c, K_STATE, k_state_init, dim3(1), dim3(1), 0, c->st, c->use64 && !c->use32 ? 1 : 0)) != LGF_OK)
+            break;
         unsigned long long chk[3] = {0, 0, 0};
         if (hipMemcpyAsync(chk, c->check, sizeof(chk), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             (rc = sync_state(c)) != LGF_OK) {
@@ -748,7 +595,6 @@ int32_t lgf_load_links(lgf_ctx c, const void* links, int32_t where)
         (void)hipFree(src);
     }
     if (rc != LGF_OK) return rc;
-    c->cur = 0;
     c->phase = c->use64 && !c->use32 ? 1 : 0;
     c->iter_fp32 = 0;
     c->loaded = true;
@@ -761,6 +607,7 @@ int32_t lgf_store_links(lgf_ctx c, void* links, int32_t where)
     if (!links || (where != LGF_HOST && where != LGF_DEVICE)) return fail(c, LGF_E_INVALID_ARG, "bad links/where");
     const int64_t V = (c->phase == 1 ? c->d.geo : c->f.geo).V;
     const size_t nbytes = sizeof(double) * 72 * (size_t)V;
+    TRY(sync_state(c));   // the current link buffer is known from the device state
     if (where == LGF_DEVICE) {
         TRY(store_any(c, static_cast<double*>(links)));
         return sync_state(c);
@@ -896,11 +743,8 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
         TRY(sync_state(c));
         while (!c->st_host->done && c->st_host->iter < c->p.max_iter) {
             const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
-            const int64_t it0 = c->st_host->iter;
-            const int cur0 = c->cur;
-            for (int64_t k = 0; k < chunk; ++k) TRY(update_any(c, nullptr));
+            TRY(enqueue_chunk(c, chunk));
             TRY(sync_state(c));
-            resync_cur(c, it0, cur0);
         }
         if (c->st_host->nonfinite) {
             fill_stats(c, out, LGF_E_NONFINITE, t0);
@@ -914,8 +758,8 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
         // FP32 phase done: rebuild the links in FP64 on the orbit of the input
         c->iter_fp32 = c->st_host->iter;
         TRY(c->NE == 9 ? enqueue_switch<9>(c) : enqueue_switch<6>(c));
+        TRY(launch(c, K_STATE, k_state_phase, dim3(1), dim3(1), 0, c->st, 1));
         c->phase = 1;
-        c->cur = 0;
         c->delta_valid = false;
     }
     fill_stats(c, out, LGF_OK, t0);

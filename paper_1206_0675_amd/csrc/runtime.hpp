@@ -1,0 +1,258 @@
+// Host-side plumbing shared by the single-lattice context and the batch:
+// error reporting, checked kernel launches with optional HIP-event timing,
+// device buffers of one lattice, geometry and the tables of the FFT and of
+// the lattice momenta.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lgf.h"
+
+namespace lgf {
+namespace rt {
+
+enum KernelId {
+    K_LOAD, K_STORE, K_MEASURE, K_TRANSFORM_MEASURE, K_ZT, K_GAUGE, K_REDUCE, K_FIELD, K_SWITCH, K_STATE, K_COUNT
+};
+inline const char* const kKernelNames[K_COUNT] = {"load",   "store",  "measure", "transform_measure", "zt_fft_scale",
+                                                  "gauge",  "reduce", "field",   "precision_switch",  "state"};
+
+constexpr size_t kMaxLds = 160 * 1024;
+constexpr size_t kMaxLdsZt = 128 * 1024;
+
+inline thread_local std::string g_noctx_err;
+
+struct Pending {
+    int k;
+    hipEvent_t a, b;
+};
+
+// What every object that launches kernels carries.
+struct Runner {
+    hipStream_t stream = nullptr;
+    int profile = 0;
+    std::string err;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<Pending> pending;
+    int64_t prof_n[K_COUNT] = {};
+    double prof_ms[K_COUNT] = {};
+};
+
+inline int32_t fail(Runner* c, int32_t code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    else g_noctx_err = msg;
+    return code;
+}
+
+#define HIPCHK(c, call)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return ::lgf::rt::fail((c), e_ == hipErrorOutOfMemory ? LGF_E_OUT_OF_MEMORY : LGF_E_DEVICE, \
+                                   std::string(#call) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+#define TRY(expr)                          \
+    do {                                   \
+        int32_t r_ = (expr);               \
+        if (r_ != LGF_OK) return r_;       \
+    } while (0)
+
+inline hipEvent_t take_event(Runner* c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+inline void prof_collect(Runner* c)
+{
+    for (auto& pe : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+            c->prof_n[pe.k] += 1;
+            c->prof_ms[pe.k] += ms;
+        }
+        c->ev_pool.push_back(pe.a);
+        c->ev_pool.push_back(pe.b);
+    }
+    c->pending.clear();
+}
+
+inline void release_events(Runner* c)
+{
+    for (auto& pe : c->pending) {
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
+    }
+    c->pending.clear();
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    c->ev_pool.clear();
+}
+
+// Launch on the runner's stream; with profiling, bracket the kernel with
+// events (read back at the next synchronisation).
+template <typename K, typename... Args>
+int32_t launch(Runner* c, int kid, K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->profile) {
+        a = take_event(c);
+        b = take_event(c);
+        if (a) (void)hipEventRecord(a, c->stream);
+    }
+    hipLaunchKernelGGL(kernel, grid, block, lds, c->stream, args...);
+    hipError_t e = hipGetLastError();
+    if (c->profile && a && b) {
+        (void)hipEventRecord(b, c->stream);
+        c->pending.push_back(Pending{kid, a, b});
+    }
+    if (e != hipSuccess)
+        return fail(c, LGF_E_DEVICE, std::string("launch of ") + kKernelNames[kid] + ": " + hipGetErrorString(e));
+    return LGF_OK;
+}
+
+inline int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+inline bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+inline int64_t blocks_for(int64_t n, int per) { return (n + per - 1) / per; }
+
+inline double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device buffers of one lattice in precision T.
+template <typename T>
+struct Bufs {
+    C2<T>* U[2] = {nullptr, nullptr};
+    C2<T>* g = nullptr;
+    C2<T>* D = nullptr;
+    C2<T>* G = nullptr;
+    C2<T>* tw = nullptr;     // Lx + Ly + Lz + Lt entries
+    Geo geo{};
+    int tw_off[4] = {0, 0, 0, 0};
+};
+
+// Geometry; the (z, t) tiles hold W plane positions, W * sizeof(complex)
+// = tile_bytes where the (z, t) block still fits its LDS budget.
+template <typename T>
+Geo make_geo(const int32_t* dims, int tile_bytes = 64)
+{
+    Geo g{};
+    for (int m = 0; m < 4; ++m) {
+        g.L[m] = dims[m];
+        g.logL[m] = ilog2(dims[m]);
+    }
+    g.NP = dims[0] * dims[1];
+    g.logNP = ilog2(g.NP);
+    g.NQ = dims[2] * dims[3];
+    g.logNQ = ilog2(g.NQ);
+    g.V = (int64_t)g.NP * g.NQ;
+    int W = (int)(tile_bytes / (int)sizeof(C2<T>));
+    if (W < 1) W = 1;
+    if (W > g.NP) W = g.NP;
+    while (W > 1 && (size_t)W * g.NQ * sizeof(C2<T>) > kMaxLdsZt) W >>= 1;
+    g.W = W;
+    g.logW = ilog2(W);
+    return g;
+}
+
+template <typename T>
+bool shape_fits(const int32_t* dims, int nth)
+{
+    const size_t np = (size_t)dims[0] * dims[1], nq = (size_t)dims[2] * dims[3];
+    if (4 * np * sizeof(C2<T>) + 2 * nth * sizeof(double) > kMaxLds) return false;
+    if (nq * sizeof(C2<T>) > kMaxLdsZt) return false;
+    return true;
+}
+
+template <typename T>
+std::vector<C2<T>> twiddles(const int32_t* dims, int* off)
+{
+    std::vector<C2<T>> tw;
+    for (int m = 0; m < 4; ++m) {
+        off[m] = (int)tw.size();
+        for (int k = 0; k < dims[m]; ++k) {
+            const double a = -2.0 * M_PI * (double)k / (double)dims[m];
+            tw.push_back(mk<T>((T)std::cos(a), (T)std::sin(a)));
+        }
+    }
+    return tw;
+}
+
+// Momentum tables indexed by position after the forward transforms:
+// 4 sin^2(pi n / L) for n = mode_of_position(L, pos), four axes in a row;
+// p2max receives the largest p^2 on the lattice.
+inline std::vector<double> momentum_tables(const int32_t* dims, double* p2max)
+{
+    std::vector<double> pt;
+    double pm = 0.0;
+    for (int m = 0; m < 4; ++m) {
+        const int L = dims[m];
+        double best = 0.0;
+        for (int pos = 0; pos < L; ++pos) {
+            const double s = std::sin(M_PI * (double)mode_of_position(L, pos) / (double)L);
+            pt.push_back(4.0 * s * s);
+            best = std::fmax(best, 4.0 * s * s);
+        }
+        pm += best;
+    }
+    if (p2max) *p2max = pm;
+    return pt;
+}
+
+template <typename T>
+int32_t alloc_bufs(Runner* c, const int32_t* dims, int NE, bool track, int tile_bytes, Bufs<T>& b, int64_t& bytes)
+{
+    b.geo = make_geo<T>(dims, tile_bytes);
+    const int64_t V = b.geo.V;
+    const size_t link = sizeof(C2<T>) * (size_t)4 * NE * V;
+    const size_t field = sizeof(C2<T>) * (size_t)NE * V;
+    HIPCHK(c, hipMalloc(&b.U[0], link));
+    HIPCHK(c, hipMalloc(&b.U[1], link));
+    HIPCHK(c, hipMalloc(&b.g, field));
+    HIPCHK(c, hipMalloc(&b.D, sizeof(C2<T>) * (size_t)4 * V));
+    bytes += 2 * link + field + sizeof(C2<T>) * 4 * V;
+    if (track) {
+        HIPCHK(c, hipMalloc(&b.G, field));
+        bytes += field;
+    }
+    std::vector<C2<T>> tw = twiddles<T>(dims, b.tw_off);
+    HIPCHK(c, hipMalloc(&b.tw, sizeof(C2<T>) * tw.size()));
+    HIPCHK(c, hipMemcpy(b.tw, tw.data(), sizeof(C2<T>) * tw.size(), hipMemcpyHostToDevice));
+    return LGF_OK;
+}
+
+template <typename T>
+void free_bufs(Bufs<T>& b)
+{
+    (void)hipFree(b.U[0]);
+    (void)hipFree(b.U[1]);
+    (void)hipFree(b.g);
+    (void)hipFree(b.D);
+    (void)hipFree(b.G);
+    (void)hipFree(b.tw);
+    b = Bufs<T>();
+}
+
+}  // namespace rt
+}  // namespace lgf

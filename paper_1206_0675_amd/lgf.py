@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("step", C.c_int32), ("accel", C.c_int32), ("track_gauge", C.c_int32),
                 ("profile", C.c_int32), ("alpha", C.c_double), ("theta_stop", C.c_double),
                 ("theta_switch", C.c_double), ("unit_tol", C.c_double), ("max_iter", C.c_int64),
-                ("poll_every", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
+                ("poll_every", C.c_int32), ("no_graph", C.c_int32), ("stream", C.c_void_p),
+                ("autotune", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -85,6 +86,15 @@ def load_library(path: str | None = None):
         "lgf_device_bytes": ([V, C.POINTER(I64)], I32),
         "lgf_strerror": ([I32], C.c_char_p),
         "lgf_last_error": ([V], C.c_char_p),
+        "lgf_batch_create": ([P, I32, C.POINTER(C.c_int32 * 4), ctx_p], I32),
+        "lgf_batch_destroy": ([V], I32),
+        "lgf_batch_load": ([V, I32, V, I32], I32),
+        "lgf_batch_fix": ([V, S], I32),
+        "lgf_batch_store": ([V, I32, V, I32], I32),
+        "lgf_batch_store_gauge": ([V, I32, V, I32], I32),
+        "lgf_batch_config": ([V, C.POINTER(I32), C.POINTER(I32)], I32),
+        "lgf_batch_last_error": ([V], C.c_char_p),
+        "lgf_fix_batch": ([P, I32, C.POINTER(C.c_int32 * 4), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), S], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -232,3 +242,91 @@ class Context:
         b = C.c_int64()
         self._check(self.lib.lgf_device_bytes(self.h, C.byref(b)))
         return b.value
+
+
+class Batch:
+    """Many lattices of different shapes gauge-fixed together (lgf_batch_*)."""
+
+    def __init__(self, dims_list, lib=None, params: Params | None = None, **kw):
+        self.lib = lib or load_library()
+        self.dims = [tuple(int(d) for d in dims) for dims in dims_list]
+        self.n = len(self.dims)
+        self.params = params if params is not None else default_params((0, 0, 0, 0), self.lib, **kw)
+        arr = (C.c_int32 * 4 * self.n)(*[(C.c_int32 * 4)(*d) for d in self.dims])
+        h = C.c_void_p()
+        rc = self.lib.lgf_batch_create(C.byref(self.params), self.n, arr, C.byref(h))
+        if rc != OK:
+            raise LgfError(rc, self.lib.lgf_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lgf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LgfError(rc, self.lib.lgf_batch_last_error(self.h).decode())
+        return rc
+
+    def _shape(self, i):
+        lx, ly, lz, lt = self.dims[i]
+        return (lt, lz, ly, lx)
+
+    def load(self, i, links):
+        ptr, where, _keep = _buffer(links)
+        self._check(self.lib.lgf_batch_load(self.h, int(i), C.c_void_p(ptr), where))
+
+    def fix(self, raise_on_error=True):
+        out = (Stats * self.n)()
+        rc = self.lib.lgf_batch_fix(self.h, out)
+        if raise_on_error:
+            self._check(rc)
+        return list(out)
+
+    def store(self, i, out=None):
+        if out is None:
+            out = np.empty(self._shape(i) + (4, 3, 3), dtype=np.complex128)
+        ptr, where, _keep = _buffer(out)
+        self._check(self.lib.lgf_batch_store(self.h, int(i), C.c_void_p(ptr), where))
+        return out
+
+    def store_gauge(self, i, out=None):
+        if out is None:
+            out = np.empty(self._shape(i) + (3, 3), dtype=np.complex128)
+        ptr, where, _keep = _buffer(out)
+        self._check(self.lib.lgf_batch_store_gauge(self.h, int(i), C.c_void_p(ptr), where))
+        return out
+
+    def config(self):
+        a, b = C.c_int32(), C.c_int32()
+        self._check(self.lib.lgf_batch_config(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+
+def fix_batch(links_list, lib=None, **kw):
+    """lgf_fix_batch on host arrays: returns (fixed links list, stats list, status)."""
+    L = lib or load_library()
+    n = len(links_list)
+    dims = [(u.shape[3], u.shape[2], u.shape[1], u.shape[0]) for u in links_list]
+    p = default_params((0, 0, 0, 0), L, **kw)
+    ins = [np.ascontiguousarray(u, dtype=np.complex128) for u in links_list]
+    outs = [np.empty_like(u) for u in ins]
+    arr = (C.c_int32 * 4 * n)(*[(C.c_int32 * 4)(*d) for d in dims])
+    pin = (C.c_void_p * n)(*[u.ctypes.data for u in ins])
+    pout = (C.c_void_p * n)(*[u.ctypes.data for u in outs])
+    st = (Stats * n)()
+    rc = L.lgf_fix_batch(C.byref(p), n, arr, pin, pout, st)
+    return outs, list(st), rc

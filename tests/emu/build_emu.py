@@ -10,14 +10,14 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
-SRC = os.path.join(ROOT, "paper_1206_0675_amd", "csrc", "lgf.hip")
+SRCS = [os.path.join(ROOT, "paper_1206_0675_amd", "csrc", f) for f in ("lgf.hip", "batch.hip")]
 
 
 def build(asan: bool = False) -> str:
     out = os.path.join(HERE, "liblgf_emu_asan.so" if asan else "liblgf_emu.so")
     cmd = ["g++", "-std=gnu++20", "-x", "c++", "-O1", "-g", "-fPIC", "-shared", "-pthread",
            "-I" + os.path.join(HERE, "include"), "-I" + os.path.join(ROOT, "include"),
-           "-I" + os.path.join(ROOT, "paper_1206_0675_amd", "csrc"), SRC, "-o", out + ".tmp"]
+           "-I" + os.path.join(ROOT, "paper_1206_0675_amd", "csrc")] + SRCS + ["-o", out + ".tmp"]
     if asan:
         cmd[5:5] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
     subprocess.run(cmd, check=True)

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -110,10 +111,49 @@ inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t)
     e->t = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
     return hipSuccess;
 }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) { *ms = (float)((b->t - a->t) * 1e3); return hipSuccess; }
 inline hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline const char* hipGetErrorString(hipError_t) { return "emulated HIP error"; }
+
+// Graph capture: launches on a capturing stream are recorded, not run, and a
+// graph launch replays them in order.
+typedef struct emu_graph* hipGraph_t;
+typedef struct emu_graph* hipGraphExec_t;
+struct emu_graph {
+    std::vector<std::function<void()>> ops;
+};
+enum hipStreamCaptureMode { hipStreamCaptureModeGlobal, hipStreamCaptureModeThreadLocal, hipStreamCaptureModeRelaxed };
+namespace emu {
+inline emu_graph* capturing = nullptr;
+}
+inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode)
+{
+    emu::capturing = new emu_graph();
+    return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g)
+{
+    *g = emu::capturing;
+    emu::capturing = nullptr;
+    return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* ex, hipGraph_t g, void*, void*, size_t)
+{
+    *ex = new emu_graph(*g);
+    return hipSuccess;
+}
+inline hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t g) { delete g; return hipSuccess; }
+inline hipError_t hipGraphLaunch(hipGraphExec_t g, hipStream_t)
+{
+    for (auto& op : g->ops) op();
+    return hipSuccess;
+}
+enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 1 };
+inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 4; return hipSuccess; }
 
 namespace emu {
 // One team of host threads per launch walks the blocks in order.  The LDS is
@@ -146,6 +186,16 @@ void launch(K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
     for (auto& x : th) x.join();
     bar = nullptr;
 }
+
+template <typename K, typename... Args>
+void launch_or_record(K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
+{
+    if (capturing)
+        capturing->ops.push_back([=] { launch(kernel, grid, block, lds, args...); });
+    else
+        launch(kernel, grid, block, lds, args...);
+}
 }  // namespace emu
 
-#define hipLaunchKernelGGL(kernel, grid, block, lds, stream, ...) emu::launch(kernel, grid, block, lds, __VA_ARGS__)
+#define hipLaunchKernelGGL(kernel, grid, block, lds, stream, ...) \
+    emu::launch_or_record(kernel, grid, block, lds, __VA_ARGS__)

@@ -140,3 +140,36 @@ def test_emulated_under_address_sanitizer():
     r = subprocess.run([sys.executable, "-c", _ASAN_SCRIPT.format(root=root, lib=lib)], env=env,
                        capture_output=True, text=True, timeout=600)
     assert r.returncode == 0 and "ASAN-CLEAN" in r.stdout, r.stderr[-3000:]
+
+
+def test_emulated_batch_members_match_oracle(E, oracle_lib):
+    dims = [(4, 4, 4, 4), (8, 4, 4, 8), (4, 8, 4, 4)]
+    Us = [synth.random_links(d, 20 + i) for i, d in enumerate(dims)]
+    with lgf.Batch(dims, lib=E, poll_every=4) as b:
+        for i, U in enumerate(Us):
+            b.load(i, U)
+        st = b.fix()
+        for i, (d, U) in enumerate(zip(dims, Us)):
+            _, it, F, th, ok, _ = oracle.fix(d, U)
+            assert st[i].status == lgf.OK and abs(st[i].iter - it) <= 1 and abs(st[i].F - F) <= 1e-12
+            Uo, _, _, _ = oracle.step(d, U, st[i].iter)
+            assert np.max(np.abs(b.store(i) - Uo)) <= 1e-12
+
+
+def test_emulated_batch_mixed_autotuned(E, oracle_lib):
+    dims = [(4, 4, 4, 4), (4, 4, 8, 4)]
+    Us = [synth.random_links(d, 30 + i, eps=0.2 + 0.2 * i) for i, d in enumerate(dims)]
+    with lgf.Batch(dims, lib=E, precision=lgf.MIXED, storage=12, poll_every=4, autotune=1) as b:
+        nth, tb = b.config()
+        assert nth in (64, 128, 256) and tb in (32, 64, 128)
+        for i, U in enumerate(Us):
+            b.load(i, U)
+        st = b.fix()
+        for i, (d, U) in enumerate(zip(dims, Us)):
+            _, it, F, th, ok, _ = oracle.fix(d, U)
+            assert st[i].status == lgf.OK and st[i].iter_fp32 > 0 and st[i].iter_fp64 > 0
+            assert abs(st[i].F - F) <= 1e-9 and st[i].theta < 1e-15
+            G = b.store_gauge(i)
+            assert np.max(np.abs(oracle.transform(d, U, G) - b.store(i))) <= 1e-12
+    outs, sts, rc = lgf.fix_batch(Us, lib=E, poll_every=4)
+    assert rc == lgf.OK and all(s.theta < 1e-15 for s in sts)

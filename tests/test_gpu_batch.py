@@ -1,0 +1,87 @@
+"""GPU parity of the batched engine (lgf_batch_*): 64 lattices of three
+shapes (24 x 8^4, 24 x 16^3x32, 16 x 16^4) with eps from 0.2 to 0.5, mixed
+FP32/FP64, iterated together.  Every member must reach theta < 1e-15 on the
+gauge orbit of its input (G U0 G^dag(x+mu) reproduces the links, plaquette
+unchanged) with the final F of its own single-lattice mixed run to 1e-9;
+members of each shape are also checked against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1206_0675_amd import lgf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lgf.load_library()
+
+
+def workload():
+    shapes = [(8, 8, 8, 8)] * 24 + [(16, 16, 16, 32)] * 24 + [(16, 16, 16, 16)] * 16
+    eps = [0.2 + 0.3 * i / 63 for i in range(64)]
+    return shapes, eps
+
+
+@pytest.fixture(scope="module")
+def batch_run(L):
+    shapes, eps = workload()
+    Us = [synth.random_links(d, 1000 + i, eps=e) for i, (d, e) in enumerate(zip(shapes, eps))]
+    print("\n[gpu] batch of 64, mixed, autotuned", flush=True)
+    with lgf.Batch(shapes, lib=L, precision=lgf.MIXED, storage=12, poll_every=8, autotune=1) as b:
+        for i, U in enumerate(Us):
+            b.load(i, U)
+        st = b.fix()
+        out = [b.store(i) for i in range(64)]
+        G = [b.store_gauge(i) for i in range(64)]
+        cfg = b.config()
+    return shapes, Us, st, out, G, cfg
+
+
+def test_batch_all_converge_on_orbit(L, oracle_lib, batch_run):
+    shapes, Us, st, out, G, cfg = batch_run
+    assert cfg[0] in (64, 128, 256)
+    for i in range(64):
+        assert st[i].status == lgf.OK and st[i].theta < 1e-15, i
+        assert st[i].iter_fp32 > 0 and st[i].iter_fp64 > 0
+        d = shapes[i]
+        assert np.max(np.abs(oracle.transform(d, Us[i], G[i]) - out[i])) <= 1e-12
+        assert abs(oracle.plaquette(d, out[i]) - oracle.plaquette(d, Us[i])) <= 1e-12
+
+
+def test_batch_members_equal_single_runs(L, batch_run):
+    shapes, Us, st, out, G, cfg = batch_run
+    for i in range(0, 64, 3):
+        with lgf.Context(shapes[i], lib=L, precision=lgf.MIXED, storage=12, poll_every=8) as c:
+            c.load(Us[i])
+            s = c.fix()
+        assert abs(s.F - st[i].F) <= 1e-9 and abs(s.iter - st[i].iter) <= 1, i
+
+
+@pytest.mark.parametrize("i", [0, 30, 55])
+def test_batch_members_match_oracle(L, oracle_lib, batch_run, i):
+    shapes, Us, st, out, G, cfg = batch_run
+    _, it, F, th, ok, _ = oracle.fix(shapes[i], Us[i])
+    assert ok and abs(st[i].F - F) <= 1e-9 and abs(st[i].iter - it) <= 2
+
+
+def test_batch_fp64_bitwise_equals_single(L):
+    dims = [(8, 8, 8, 8), (16, 8, 8, 16)]
+    Us = [synth.random_links(d, 40 + i) for i, d in enumerate(dims)]
+    with lgf.Batch(dims, lib=L, poll_every=4) as b:
+        for i, U in enumerate(Us):
+            b.load(i, U)
+        st = b.fix()
+        for i, d in enumerate(dims):
+            with lgf.Context(d, lib=L, poll_every=4) as c:
+                c.load(Us[i])
+                s = c.fix()
+                assert s.iter == st[i].iter and s.F == st[i].F
+                assert np.array_equal(c.store(), b.store(i))

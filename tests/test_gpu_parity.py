@@ -262,3 +262,23 @@ def test_smallest_and_largest_planes(L, oracle_lib, dims):
     Uo, of, ot, _ = oracle.step(dims, U, 3)
     assert rel(Ug, Uo) <= 1e-12
     assert np.max(np.abs(tt - ot) / ot) <= 1e-12
+
+
+def test_graph_replay_matches_eager(L):
+    """lgf_fix replays a captured graph of poll_every iterations; every replay
+    (several per fix, fixes repeated with reloads and syncs in between) must
+    give exactly the links of kernel-by-kernel launches."""
+    dims = (16, 16, 8, 8)
+    U = links(dims, 6)
+    announce("graph replay vs eager")
+    with lgf.Context(dims, lib=L, poll_every=4, no_graph=1) as e, lgf.Context(dims, lib=L, poll_every=4) as g:
+        e.load(U)
+        se = e.fix()
+        ref = e.store()
+        for _ in range(3):
+            g.load(U)
+            g.step(2)            # eager work between the graph replays
+            g.load(U)
+            sg = g.fix()
+            assert sg.iter == se.iter and sg.F == se.F and sg.theta == se.theta
+            assert np.array_equal(g.store(), ref)
