@@ -72,7 +72,10 @@ extern "C" {
 #define LGF_STORE12 12
 
 /* step kind */
-#define LGF_STEP_PLAIN 0  /* eq. gx: (alpha/2) p2max/p2 */
+#define LGF_STEP_PLAIN 0    /* eq. gx: (alpha/2) p2max/p2                                  */
+#define LGF_STEP_LEARNED 1  /* s_b (alpha/2) p2max/p2 with per-band factors s_b from the
+                               network set by lgf_set_model; an update that does not
+                               increase F is replaced by the plain one (FP64 only)          */
 
 /* acceleration kernel */
 #define LGF_ACCEL_FOURIER 1  /* K(p) = p2max/p2, K(0) = 0 (eq. gx)                       */
@@ -108,7 +111,7 @@ typedef struct lgf_stats {
     int64_t iter;           /* gauge transformations applied since the last load         */
     int64_t iter_fp32;      /* ... of which in FP32                                      */
     int64_t iter_fp64;      /* ... of which in FP64                                      */
-    int64_t reserved;
+    int64_t fallbacks;      /* learned steps replaced by the plain step (F did not grow) */
     double F;               /* functional of the current links                           */
     double theta;           /* convergence measure of the current links                  */
     double seconds;         /* wall time of the call                                     */
@@ -195,6 +198,57 @@ const char *lgf_batch_last_error(lgf_batch_t b);
  * (which may alias links_in[i]), destroy.  Returns the worst member status. */
 int32_t lgf_fix_batch(const lgf_params *common, int32_t n, const int32_t (*dims)[4], const double *const *links_in,
                       double *const *links_out, lgf_stats *out);
+
+/* ---------------------------------------------------------------------------
+ * Learned spectral step.  The modes p != 0 fall in 16 bands log-spaced in p^2
+ * between the smallest nonzero p^2 of the lattice and p2max.  Features:
+ * x_b = log10(P_b / V) / 8 with P_b the mean over band b of sum_c |Dhat_c|^2
+ * (the four complex fields of Delta's 8 real components; 0 for an empty
+ * band).  Network 16 -> 64 -> 64 -> 16 (ReLU), bfloat16 weights, float32
+ * biases and accumulation; factors s_b = exp(clip(y_b, -2.3, 2.3)).
+ * Model blob: int32 {0x4C47464D, 1, 16, 64, 64, 16, 0, 0}, bf16 W1[16][64],
+ * W2[64][64], W3[64][16], float32 b1[64], b2[64], b3[16]
+ * (lgf_model_bytes() bytes).
+ * ------------------------------------------------------------------------- */
+size_t lgf_model_bytes(void);
+
+/* Set the network a LGF_STEP_LEARNED context uses (copied). LGF_E_INVALID_ARG
+ * for a malformed blob. */
+int32_t lgf_set_model(lgf_ctx ctx, const void *blob, size_t bytes);
+
+/* Features x and factors s (all 1 without a model) the learned step would
+ * use at the current links of an FP64 context; the links are not changed. */
+int32_t lgf_learned_factors(lgf_ctx ctx, double features[16], double s[16]);
+
+/* Training data at the current links of an FP64 context: the band features
+ * x and the log factors ln s* that maximise F after one update, found by two
+ * sweeps of golden-section search on each ln s_b in [-2.3, 2.3] (the other
+ * factors held).  The links are not changed. */
+int32_t lgf_linesearch_bands(lgf_ctx ctx, double features[16], double log_s[16]);
+
+typedef struct lgf_train_params {
+    int64_t steps;   /* Adam steps                         */
+    int32_t batch;   /* minibatch size (<= 1024)            */
+    int32_t seed;    /* initial weights and sample order    */
+    float lr;        /* Adam learning rate                  */
+    float reserved;
+} lgf_train_params;
+
+/* Train the network on the GPU on n samples (host float32 arrays X, Y = ln s*,
+ * M = band mask, each n x 16): masked mean squared error, Adam on float32
+ * master weights, forward with bf16-rounded weights.  blob_out receives the
+ * model (*bytes in: capacity, out: size); loss_trace (steps floats, or NULL)
+ * the minibatch loss of every step. */
+int32_t lgf_mlp_train(const float *X, const float *Y, const float *M, int64_t n, const lgf_train_params *tp,
+                      void *blob_out, size_t *bytes, float *loss_trace);
+
+/* Loss and gradient (6288 floats, parameter order W1, b1, W2, b2, W3, b3) of a
+ * model on n <= 1024 samples, by the training kernels. */
+int32_t lgf_mlp_grad(const void *blob, size_t bytes, const float *X, const float *Y, const float *M, int64_t n,
+                     float *grad, double *loss);
+
+/* Network outputs y (n x 16) for inputs X (n x 16). */
+int32_t lgf_mlp_eval(const void *blob, size_t bytes, const float *X, int64_t n, float *Y);
 
 /* Per-kernel timing collected when params.profile = 1: for kernel k < n
  * (names from lgf_kernel_name), the number of launches and their summed

@@ -55,6 +55,7 @@ struct DevState {
     int32_t switch_pending;// batched mixed runs: FP32 phase finished, rebuild in FP64
     int32_t mixed;         // batched runs: FP32 phase followed by FP64
     int32_t pad;
+    double trial_F, trial_theta;   // learned step: F, theta of the candidate links
 };
 
 // plane index handled by this block: consecutive planes stay on one XCD
@@ -422,7 +423,10 @@ __device__ __forceinline__ void reduce_state(const double* __restrict__ partial,
     }
     double fs, ts;
     block_sum2(a, b, red, tid, nth, &fs, &ts);
-    if (tid == 0) {
+    if (tid == 0 && counts_update == 2) {          // candidate links of a learned step: no commit
+        st->trial_F = fs / (12.0 * (double)V);
+        st->trial_theta = ts / (3.0 * (double)V);
+    } else if (tid == 0) {
         const double F = fs / (12.0 * (double)V), th = ts / (3.0 * (double)V);
         if (counts_update) {
             st->iter += 1;
@@ -691,6 +695,188 @@ __global__ void kb_switch_done(const BatchCfg<double>* __restrict__ c64, int ncf
     st->phase = 1;
     st->cur = 0;
     st->needs_measure = 1;
+}
+
+// ===========================================================================
+// a10: learned spectral step
+// ===========================================================================
+// Band of a mode from its p^2: 16 bands log-spaced between the smallest
+// nonzero p^2 of the lattice (pmin) and p2max; -1 for the zero mode.
+struct Bands {
+    double pmin;        // smallest nonzero p^2
+    double log_range;   // log(p2max / pmin)
+    __device__ __forceinline__ int of(double p2) const
+    {
+        if (!(p2 > 0.0)) return -1;
+        int b = (int)floor(16.0 * log(p2 / pmin) / log_range);
+        return b < 0 ? 0 : (b > 15 ? 15 : b);
+    }
+};
+
+// Forward (z, t) transform of one tile, in place, and this block's band sums
+// of sum_c |Dhat_c(p)|^2 (per-thread accumulation, then a fixed-order tree
+// in LDS: the launch gives at least 16 * blockDim doubles of LDS).
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(512) k_zt_fwd_bands(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
+                                                      const C2<T>* __restrict__ twt, const double* __restrict__ ptab,
+                                                      Bands bands, double* __restrict__ band_partial,
+                                                      const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
+    const int W = geo.W, NQ = geo.NQ, n = NQ * W, Lz = geo.L[2];
+    C2<T>* src = D + (int64_t)(j * 4 + c) * NQ * W;
+    for (int i = tid; i < n; i += nth) buf[i] = src[i];
+    __syncthreads();
+    const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
+    const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
+    fft_fwd<T, LMAX>(buf, Lz, zl, twz, tid, nth);
+    fft_fwd<T, LMAX>(buf, geo.L[3], tl, twt, tid, nth);
+    const SpectralScale sc = make_scale(geo, ptab, 0.0, 1);
+    double acc[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) acc[b] = 0.0;
+    for (int i = tid; i < n; i += nth) {
+        const C2<T> v = buf[i];
+        src[i] = v;
+        const int w = i & (W - 1), qq = i >> geo.logW;
+        const int pxy = j * W + w;
+        const double p2 = sc.tx[pxy & (geo.L[0] - 1)] + sc.ty[pxy >> geo.logL[0]] + sc.tz[qq & (Lz - 1)] +
+                          sc.tt[qq >> geo.logL[2]];
+        const int b = bands.of(p2);
+        const double pw = (double)v.x * v.x + (double)v.y * v.y;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] += (k == b) ? pw : 0.0;
+    }
+    __syncthreads();
+    double* red = lds_raw;   // reuse: 16 * nth doubles fit in the tile buffer
+#pragma unroll
+    for (int k = 0; k < 16; ++k) red[k * nth + tid] = acc[k];
+    __syncthreads();
+    for (int h = nth >> 1; h > 0; h >>= 1) {
+        if (tid < h)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) red[k * nth + tid] += red[k * nth + tid + h];
+        __syncthreads();
+    }
+    if (tid < 16) band_partial[(int64_t)blockIdx.x * 16 + tid] = red[tid * nth];
+}
+
+// Scale by s_b * (alpha/2) p2max / (p^2 V) and inverse (z, t) transform of
+// one tile, from Din (the full 4D spectrum, kept) into Dout.
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __restrict__ Din, C2<T>* __restrict__ Dout,
+                                                       const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt,
+                                                       const double* __restrict__ ptab, double c0, int accel, Bands bands,
+                                                       const double* __restrict__ s, const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
+    const int W = geo.W, NQ = geo.NQ, n = NQ * W, Lz = geo.L[2];
+    const C2<T>* src = Din + (int64_t)(j * 4 + c) * NQ * W;
+    const SpectralScale sc = make_scale(geo, ptab, c0, accel);
+    for (int i = tid; i < n; i += nth) {
+        const int w = i & (W - 1), qq = i >> geo.logW;
+        const int pxy = j * W + w;
+        const double base = sc.tx[pxy & (geo.L[0] - 1)] + sc.ty[pxy >> geo.logL[0]] + sc.tz[qq & (Lz - 1)];
+        const double p2 = base + sc.tt[qq >> geo.logL[2]];
+        const int b = bands.of(p2);
+        const double sb = b < 0 ? 1.0 : s[b];
+        buf[i] = scale(src[i], (T)(sb * sc.factor(p2)));
+    }
+    __syncthreads();
+    const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
+    const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
+    fft_inv<T, LMAX>(buf, geo.L[3], tl, twt, tid, nth);
+    fft_inv<T, LMAX>(buf, Lz, zl, twz, tid, nth);
+    C2<T>* dst = Dout + (int64_t)(j * 4 + c) * NQ * W;
+    for (int i = tid; i < n; i += nth) dst[i] = buf[i];
+}
+
+__device__ __forceinline__ float bf16_to_float(uint16_t b)
+{
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// Network 16 -> 64 -> 64 -> 16 (ReLU), bf16 weights [in][out] row-major,
+// float32 biases, float32 accumulation.
+struct MlpDev {
+    const uint16_t* W1;
+    const uint16_t* W2;
+    const uint16_t* W3;
+    const float* b1;
+    const float* b2;
+    const float* b3;
+};
+
+// Band powers -> features -> factors s_b = exp(clip(y_b, -2.3, 2.3)).  One
+// block of 64 threads.  Empty bands (count 0) get feature 0.
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(64) k_bands_mlp(const double* __restrict__ band_partial, int nblk,
+                                                  const double* __restrict__ count16, int64_t V, MlpDev net,
+                                                  double* __restrict__ s_out, double* __restrict__ x_out,
+                                                  const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    __shared__ float x[16], h1[64], h2[64];
+    const int tid = threadIdx.x;
+    if (tid < 16) {
+        double p = 0.0;
+        for (int i = 0; i < nblk; ++i) p += band_partial[(int64_t)i * 16 + tid];
+        double f = 0.0;
+        if (count16[tid] > 0.0) {
+            const double pv = p / count16[tid] / (double)V;
+            f = log10(pv > 1e-300 ? pv : 1e-300) / 8.0;
+        }
+        x[tid] = (float)f;
+        if (x_out) x_out[tid] = f;
+    }
+    __syncthreads();
+    if (!net.W1) {                     // features only: the plain factors
+        if (tid < 16) s_out[tid] = 1.0;
+        return;
+    }
+    float a = net.b1[tid];
+    for (int i = 0; i < 16; ++i) a = fmaf(x[i], bf16_to_float(net.W1[i * 64 + tid]), a);
+    h1[tid] = a > 0.f ? a : 0.f;
+    __syncthreads();
+    a = net.b2[tid];
+    for (int i = 0; i < 64; ++i) a = fmaf(h1[i], bf16_to_float(net.W2[i * 64 + tid]), a);
+    h2[tid] = a > 0.f ? a : 0.f;
+    __syncthreads();
+    if (tid < 16) {
+        a = net.b3[tid];
+        for (int i = 0; i < 64; ++i) a = fmaf(h2[i], bf16_to_float(net.W3[i * 16 + tid]), a);
+        const double y = fmin(fmax((double)a, -2.3), 2.3);
+        s_out[tid] = exp(y);
+    }
+}
+
+// Learned step accepted: the candidate links become current.
+template <int UNUSED = 0>
+__global__ void k_commit_trial(DevState* st)
+{
+    if (st->done) return;
+    st->iter += 1;
+    st->cur ^= 1;
+    st->F = st->trial_F;
+    st->theta = st->trial_theta;
+    const double th = st->theta;
+    if (!(th == th) || th > 1e300) {
+        st->nonfinite = 1;
+        st->done = 1;
+    } else if (th < st->theta_stop) {
+        st->done = 1;
+    }
 }
 
 }  // namespace lgf

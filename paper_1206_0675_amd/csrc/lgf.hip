@@ -85,6 +85,21 @@ struct lgf_context : Runner {
     int lmax = 64;            // longest axis rounded up to 64 or 128 (kernel variant)
     hipStream_t cap_stream = nullptr;          // private stream that graph capture runs on
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // per phase: poll_every updates
+    // learned spectral step (FP64): model, band sums, factors, spare Delta buffers
+    bool learned = false;
+    bool has_model = false;
+    uint16_t* mw = nullptr;       // bf16 W1 | W2 | W3
+    float* mb = nullptr;          // b1 | b2 | b3
+    double* band_partial = nullptr;
+    double* counts16 = nullptr;
+    double* s_dev = nullptr;
+    double* x_dev = nullptr;
+    double* ones_dev = nullptr;
+    C2<double>* D2 = nullptr;     // scaled + inverse-(z,t) spectrum of a candidate step
+    C2<double>* D3 = nullptr;     // (x,y)-transformed Delta of the candidate links
+    Bands bands{};
+    double counts_host[16] = {};
+    int64_t fallbacks = 0;
 };
 
 namespace {
@@ -305,6 +320,7 @@ void fill_stats(lgf_context* c, lgf_stats* out, int32_t status, double t0)
     } else {
         out->iter_fp64 = out->iter;
     }
+    out->fallbacks = c->fallbacks;
     out->F = c->st_host->F;
     out->theta = c->st_host->theta;
     out->seconds = t0 > 0 ? now_s() - t0 : 0.0;
@@ -316,6 +332,153 @@ int32_t check_ctx(lgf_context* c, bool need_loaded)
 {
     if (!c) return LGF_E_INVALID_ARG;
     if (need_loaded && !c->loaded) return fail(c, LGF_E_STATE, "no links loaded");
+    return LGF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned spectral step
+// ---------------------------------------------------------------------------
+int32_t ensure_learned_buffers(lgf_context* c)
+{
+    if (c->D2) return LGF_OK;
+    if (!c->use64) return fail(c, LGF_E_STATE, "the learned step and the band line search run in FP64");
+    const Geo& g = c->d.geo;
+    HIPCHK(c, hipMalloc(&c->D2, sizeof(C2<double>) * 4 * (size_t)g.V));
+    HIPCHK(c, hipMalloc(&c->D3, sizeof(C2<double>) * 4 * (size_t)g.V));
+    const int nblk = (g.NP / g.W) * 4;
+    HIPCHK(c, hipMalloc(&c->band_partial, sizeof(double) * 16 * nblk));
+    HIPCHK(c, hipMalloc(&c->counts16, sizeof(double) * 16));
+    HIPCHK(c, hipMalloc(&c->s_dev, sizeof(double) * 16));
+    HIPCHK(c, hipMalloc(&c->x_dev, sizeof(double) * 16));
+    HIPCHK(c, hipMalloc(&c->ones_dev, sizeof(double) * 16));
+    c->bytes += 2 * sizeof(C2<double>) * 4 * (size_t)g.V;
+    // bands: log-spaced in p^2 from the smallest nonzero p^2 to p2max; the
+    // number of modes in each is counted here with the kernels' formula
+    double p2max = 0.0;
+    const std::vector<double> pt = momentum_tables(c->p.dims, &p2max);
+    double pmin = 1e300;
+    for (int m = 0; m < 4; ++m) {
+        const double sn = std::sin(M_PI / (double)c->p.dims[m]);
+        pmin = std::fmin(pmin, 4.0 * sn * sn);
+    }
+    c->bands = Bands{pmin, std::log(p2max / pmin)};
+    const int* L = c->p.dims;
+    const double* tx = pt.data();
+    const double* ty = tx + L[0];
+    const double* tz = ty + L[1];
+    const double* tt = tz + L[2];
+    double cnt[16] = {};
+    for (int t = 0; t < L[3]; ++t)
+        for (int z = 0; z < L[2]; ++z)
+            for (int y = 0; y < L[1]; ++y)
+                for (int x = 0; x < L[0]; ++x) {
+                    const double p2 = tx[x] + ty[y] + tz[z] + tt[t];
+                    if (!(p2 > 0.0)) continue;
+                    int b = (int)std::floor(16.0 * std::log(p2 / pmin) / c->bands.log_range);
+                    cnt[b < 0 ? 0 : (b > 15 ? 15 : b)] += 1.0;
+                }
+    std::memcpy(c->counts_host, cnt, sizeof cnt);
+    std::vector<double> ones(16, 1.0);
+    HIPCHK(c, hipMemcpy(c->counts16, cnt, sizeof cnt, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ones_dev, ones.data(), sizeof(double) * 16, hipMemcpyHostToDevice));
+    const size_t zl = std::max((size_t)g.NQ * g.W * sizeof(C2<double>), (size_t)16 * 512 * sizeof(double));
+    for (auto f : {reinterpret_cast<const void*>(&k_zt_fwd_bands<double, 64>),
+                   reinterpret_cast<const void*>(&k_zt_fwd_bands<double, 128>)})
+        HIPCHK(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)zl));
+    for (auto f : {reinterpret_cast<const void*>(&k_zt_inv_scaled<double, 64>),
+                   reinterpret_cast<const void*>(&k_zt_inv_scaled<double, 128>)})
+        HIPCHK(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)((size_t)g.NQ * g.W * sizeof(C2<double>))));
+    return LGF_OK;
+}
+
+MlpDev model_ptrs(lgf_context* c, bool use_model)
+{
+    if (!use_model || !c->has_model) return MlpDev{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    return MlpDev{c->mw, c->mw + 16 * 64, c->mw + 16 * 64 + 64 * 64, c->mb, c->mb + 64, c->mb + 128};
+}
+
+// Full 4D spectrum of Delta in D (in place), band sums, features and (with a
+// model) the factors s.
+template <int LMAX>
+int32_t enqueue_bands(lgf_context* c, bool use_model)
+{
+    Bufs<double>& b = c->d;
+    const Geo& g = b.geo;
+    const int nblk = (g.NP / g.W) * 4;
+    const size_t zl = std::max((size_t)g.NQ * g.W * sizeof(C2<double>), (size_t)16 * 512 * sizeof(double));
+    TRY(launch(c, K_ZT_FWD, k_zt_fwd_bands<double, LMAX>, dim3(nblk), dim3(512), zl, g, b.D,
+               (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
+               (const double*)c->ptab, c->bands, c->band_partial, (const DevState*)c->st));
+    TRY(launch(c, K_BANDS_MLP, k_bands_mlp<>, dim3(1), dim3(64), 0, (const double*)c->band_partial, nblk,
+               (const double*)c->counts16, g.V, model_ptrs(c, use_model), c->s_dev, c->x_dev, (const DevState*)c->st));
+    return LGF_OK;
+}
+
+// One update with per-band factors s from the spectrum in D: candidate
+// links into U[1 - cur] and their Delta into D3.  mode 2: a candidate (F and
+// theta recorded as trial values, nothing committed); mode 1: committed.
+template <int NE, int LMAX>
+int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode)
+{
+    Bufs<double>& b = c->d;
+    const Geo& g = b.geo;
+    const C2<double>* twx = b.tw + b.tw_off[0];
+    const C2<double>* twy = b.tw + b.tw_off[1];
+    const size_t glds = 4 * g.NP * sizeof(C2<double>);
+    TRY(launch(c, K_ZT_INV, k_zt_inv_scaled<double, LMAX>, dim3((g.NP / g.W) * 4), dim3(512),
+               (size_t)g.NQ * g.W * sizeof(C2<double>), g, (const C2<double>*)b.D, c->D2,
+               (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
+               (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), c->bands, s,
+               (const DevState*)c->st));
+    TRY(launch(c, K_GAUGE, k_gauge<double, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g,
+               (const C2<double>*)c->D2, b.g, b.G, twx, twy, (const DevState*)c->st));
+    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<double, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane),
+               glds + 2 * c->nth_plane * sizeof(double), g, b.U[0], b.U[1], (const C2<double>*)b.g, c->D3,
+               c->partial, twx, twy, (const DevState*)c->st));
+    TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
+               (double*)nullptr, mode));
+    return LGF_OK;
+}
+
+int32_t bands_any(lgf_context* c, bool use_model)
+{
+    return c->lmax > 64 ? enqueue_bands<128>(c, use_model) : enqueue_bands<64>(c, use_model);
+}
+
+int32_t scaled_update_any(lgf_context* c, const double* s, int mode)
+{
+    const bool big = c->lmax > 64;
+    if (c->NE == 9) return big ? enqueue_scaled_update<9, 128>(c, s, mode) : enqueue_scaled_update<9, 64>(c, s, mode);
+    return big ? enqueue_scaled_update<6, 128>(c, s, mode) : enqueue_scaled_update<6, 64>(c, s, mode);
+}
+
+// One learned update (Delta of the current links in D, state current): the
+// network's factors give candidate links; they are kept if F grows,
+// otherwise the plain update is taken.  Leaves Delta of the new links in D.
+int32_t learned_update(lgf_context* c)
+{
+    TRY(bands_any(c, true));
+    TRY(scaled_update_any(c, c->s_dev, 2));
+    TRY(sync_state(c));
+    if (c->st_host->done) return LGF_OK;
+    if (c->st_host->trial_F > c->st_host->F) {
+        TRY(launch(c, K_STATE, k_commit_trial<>, dim3(1), dim3(1), 0, c->st));
+    } else {
+        c->fallbacks += 1;
+        TRY(scaled_update_any(c, c->ones_dev, 1));
+    }
+    std::swap(c->d.D, c->D3);
+    return LGF_OK;
+}
+
+// F after one update with factors s, the links kept as they are.
+int32_t trial_F(lgf_context* c, const std::vector<double>& s, double* F)
+{
+    HIPCHK(c, hipMemcpyAsync(c->s_dev, s.data(), sizeof(double) * 16, hipMemcpyHostToDevice, c->stream));
+    TRY(scaled_update_any(c, c->s_dev, 2));
+    TRY(sync_state(c));
+    *F = c->st_host->trial_F;
     return LGF_OK;
 }
 
@@ -424,7 +587,10 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
         return fail(nullptr, LGF_E_INVALID_ARG, "precision must be LGF_FP64, LGF_FP32 or LGF_MIXED");
     if (p->storage != LGF_STORE18 && p->storage != LGF_STORE12)
         return fail(nullptr, LGF_E_INVALID_ARG, "storage must be LGF_STORE18 or LGF_STORE12");
-    if (p->step != LGF_STEP_PLAIN) return fail(nullptr, LGF_E_INVALID_ARG, "unknown step kind");
+    if (p->step != LGF_STEP_PLAIN && p->step != LGF_STEP_LEARNED)
+        return fail(nullptr, LGF_E_INVALID_ARG, "unknown step kind");
+    if (p->step == LGF_STEP_LEARNED && (p->precision != LGF_FP64 || p->track_gauge))
+        return fail(nullptr, LGF_E_INVALID_ARG, "the learned step runs in FP64 without gauge tracking");
     if (p->accel != LGF_ACCEL_FOURIER && p->accel != LGF_ACCEL_NONE)
         return fail(nullptr, LGF_E_INVALID_ARG, "accel must be LGF_ACCEL_FOURIER or LGF_ACCEL_NONE");
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(nullptr, LGF_E_INVALID_ARG, "alpha must be > 0");
@@ -444,6 +610,7 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
     if (!c) return fail(nullptr, LGF_E_OUT_OF_MEMORY, "host allocation failed");
     c->p = *p;
     c->profile = p->profile;
+    c->learned = p->step == LGF_STEP_LEARNED;
     c->NE = p->storage == LGF_STORE12 ? 6 : 9;
     c->use64 = use64;
     c->use32 = use32;
@@ -524,6 +691,9 @@ int32_t lgf_destroy(lgf_ctx c)
     (void)hipFree(c->st);
     (void)hipFree(c->check);
     (void)hipFree(c->trace_dev);
+    for (void* q : {(void*)c->mw, (void*)c->mb, (void*)c->band_partial, (void*)c->counts16, (void*)c->s_dev,
+                    (void*)c->x_dev, (void*)c->ones_dev, (void*)c->D2, (void*)c->D3})
+        (void)hipFree(q);
     if (c->st_host) (void)hipHostFree(c->st_host);
     release_events(c);
     for (auto& ex : c->gexec)
@@ -597,6 +767,7 @@ int32_t lgf_load_links(lgf_ctx c, const void* links, int32_t where)
     if (rc != LGF_OK) return rc;
     c->phase = c->use64 && !c->use32 ? 1 : 0;
     c->iter_fp32 = 0;
+    c->fallbacks = 0;
     c->loaded = true;
     return LGF_OK;
 }
@@ -713,7 +884,23 @@ int32_t lgf_step(lgf_ctx c, int64_t n, lgf_stats* trace)
     }
     TRY(set_stop(c, -1.0));
     if (!c->delta_valid || trace) TRY(measure_any(c, tr));
-    for (int64_t k = 1; k <= n; ++k) TRY(update_any(c, tr ? tr + 2 * k : nullptr));
+    if (c->learned) {
+        if (!c->has_model) return fail(c, LGF_E_STATE, "the learned step needs lgf_set_model first");
+        TRY(ensure_learned_buffers(c));
+        TRY(sync_state(c));
+        std::vector<double> lt;
+        for (int64_t k = 1; k <= n; ++k) {
+            TRY(learned_update(c));
+            TRY(sync_state(c));
+            lt.push_back(c->st_host->F);
+            lt.push_back(c->st_host->theta);
+        }
+        if (trace)
+            for (int64_t k = 1; k <= n; ++k)
+                HIPCHK(c, hipMemcpy(tr + 2 * k, lt.data() + 2 * (k - 1), 2 * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        for (int64_t k = 1; k <= n; ++k) TRY(update_any(c, tr ? tr + 2 * k : nullptr));
+    }
     TRY(sync_state(c));
     if (c->st_host->nonfinite) return fail(c, LGF_E_NONFINITE, "theta became non-finite");
     if (trace) {
@@ -741,9 +928,17 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
         TRY(set_stop(c, stop));
         if (!c->delta_valid) TRY(measure_any(c, nullptr));
         TRY(sync_state(c));
+        if (c->learned) {
+            if (!c->has_model) return fail(c, LGF_E_STATE, "the learned step needs lgf_set_model first");
+            TRY(ensure_learned_buffers(c));
+        }
         while (!c->st_host->done && c->st_host->iter < c->p.max_iter) {
-            const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
-            TRY(enqueue_chunk(c, chunk));
+            if (c->learned) {
+                TRY(learned_update(c));
+            } else {
+                const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
+                TRY(enqueue_chunk(c, chunk));
+            }
             TRY(sync_state(c));
         }
         if (c->st_host->nonfinite) {
@@ -763,6 +958,88 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
         c->delta_valid = false;
     }
     fill_stats(c, out, LGF_OK, t0);
+    return LGF_OK;
+}
+
+int32_t lgf_set_model(lgf_ctx c, const void* blob, size_t bytes)
+{
+    TRY(check_ctx(c, false));
+    const uint16_t* w = nullptr;
+    const float* b = nullptr;
+    if (!parse_model(blob, bytes, &w, &b)) return fail(c, LGF_E_INVALID_ARG, "malformed model blob");
+    if (!c->mw) HIPCHK(c, hipMalloc(&c->mw, sizeof(uint16_t) * kModelWeights));
+    if (!c->mb) HIPCHK(c, hipMalloc(&c->mb, sizeof(float) * kModelBiases));
+    HIPCHK(c, hipMemcpy(c->mw, w, sizeof(uint16_t) * kModelWeights, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->mb, b, sizeof(float) * kModelBiases, hipMemcpyHostToDevice));
+    c->has_model = true;
+    return LGF_OK;
+}
+
+int32_t lgf_learned_factors(lgf_ctx c, double features[16], double s[16])
+{
+    TRY(check_ctx(c, true));
+    if (!features || !s) return fail(c, LGF_E_INVALID_ARG, "NULL output");
+    if (c->phase != 1) return fail(c, LGF_E_STATE, "the learned step runs in FP64");
+    TRY(ensure_learned_buffers(c));
+    TRY(set_stop(c, -1.0));
+    if (!c->delta_valid) TRY(measure_any(c, nullptr));
+    TRY(bands_any(c, true));
+    HIPCHK(c, hipMemcpyAsync(features, c->x_dev, sizeof(double) * 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(s, c->s_dev, sizeof(double) * 16, hipMemcpyDeviceToHost, c->stream));
+    TRY(sync_state(c));
+    c->delta_valid = false;          // D now holds the full spectrum
+    return LGF_OK;
+}
+
+int32_t lgf_linesearch_bands(lgf_ctx c, double features[16], double log_s[16])
+{
+    TRY(check_ctx(c, true));
+    if (!features || !log_s) return fail(c, LGF_E_INVALID_ARG, "NULL output");
+    if (c->phase != 1) return fail(c, LGF_E_STATE, "the band line search runs in FP64");
+    TRY(ensure_learned_buffers(c));
+    TRY(set_stop(c, -1.0));
+    if (!c->delta_valid) TRY(measure_any(c, nullptr));
+    TRY(bands_any(c, false));
+    HIPCHK(c, hipMemcpyAsync(features, c->x_dev, sizeof(double) * 16, hipMemcpyDeviceToHost, c->stream));
+    TRY(sync_state(c));
+    c->delta_valid = false;          // D now holds the full spectrum
+    std::vector<double> s(16, 1.0);
+    double best = 0.0;
+    TRY(trial_F(c, s, &best));
+    const double lo = -2.3, hi = 2.3, gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (int sweep = 0; sweep < 2; ++sweep)
+        for (int band = 0; band < 16; ++band) {
+            if (c->counts_host[band] == 0.0) continue;
+            auto eval = [&](double u, double* F) {
+                std::vector<double> t = s;
+                t[band] = std::exp(u);
+                return trial_F(c, t, F);
+            };
+            double a = lo, b = hi, x1 = b - gr * (b - a), x2 = a + gr * (b - a), f1, f2;
+            TRY(eval(x1, &f1));
+            TRY(eval(x2, &f2));
+            for (int it = 0; it < 12; ++it) {
+                if (f1 > f2) {
+                    b = x2;
+                    x2 = x1;
+                    f2 = f1;
+                    x1 = b - gr * (b - a);
+                    TRY(eval(x1, &f1));
+                } else {
+                    a = x1;
+                    x1 = x2;
+                    f1 = f2;
+                    x2 = a + gr * (b - a);
+                    TRY(eval(x2, &f2));
+                }
+            }
+            const double u = f1 > f2 ? x1 : x2, fu = f1 > f2 ? f1 : f2;
+            if (fu > best) {
+                best = fu;
+                s[band] = std::exp(u);
+            }
+        }
+    for (int b = 0; b < 16; ++b) log_s[b] = std::log(s[b]);
     return LGF_OK;
 }
 

@@ -18,10 +18,29 @@ namespace lgf {
 namespace rt {
 
 enum KernelId {
-    K_LOAD, K_STORE, K_MEASURE, K_TRANSFORM_MEASURE, K_ZT, K_GAUGE, K_REDUCE, K_FIELD, K_SWITCH, K_STATE, K_COUNT
+    K_LOAD, K_STORE, K_MEASURE, K_TRANSFORM_MEASURE, K_ZT, K_GAUGE, K_REDUCE, K_FIELD, K_SWITCH, K_STATE,
+    K_ZT_FWD, K_BANDS_MLP, K_ZT_INV, K_MLP, K_COUNT
 };
-inline const char* const kKernelNames[K_COUNT] = {"load",   "store",  "measure", "transform_measure", "zt_fft_scale",
-                                                  "gauge",  "reduce", "field",   "precision_switch",  "state"};
+inline const char* const kKernelNames[K_COUNT] = {
+    "load",  "store", "measure", "transform_measure", "zt_fft_scale", "gauge",         "reduce",
+    "field", "precision_switch", "state", "zt_fft_bands", "bands_mlp", "zt_scale_ifft", "mlp"};
+
+// Learned-step model blob: int32 header {magic, 1, 16, 64, 64, 16, 0, 0},
+// bf16 W1[16][64], W2[64][64], W3[64][16], float32 b1[64], b2[64], b3[16].
+constexpr int32_t kModelMagic = 0x4C47464D;
+constexpr int kModelWeights = 16 * 64 + 64 * 64 + 64 * 16;
+constexpr int kModelBiases = 64 + 64 + 16;
+constexpr size_t kModelBytes = 32 + 2 * kModelWeights + 4 * kModelBiases;
+
+inline bool parse_model(const void* blob, size_t bytes, const uint16_t** w, const float** b)
+{
+    if (!blob || bytes != kModelBytes) return false;
+    const int32_t* h = static_cast<const int32_t*>(blob);
+    if (h[0] != kModelMagic || h[1] != 1 || h[2] != 16 || h[3] != 64 || h[4] != 64 || h[5] != 16) return false;
+    *w = reinterpret_cast<const uint16_t*>(static_cast<const char*>(blob) + 32);
+    *b = reinterpret_cast<const float*>(static_cast<const char*>(blob) + 32 + 2 * kModelWeights);
+    return true;
+}
 
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr size_t kMaxLdsZt = 128 * 1024;

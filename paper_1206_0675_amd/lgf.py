@@ -41,11 +41,16 @@ class Params(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("iter", C.c_int64), ("iter_fp32", C.c_int64), ("iter_fp64", C.c_int64),
-                ("reserved", C.c_int64), ("F", C.c_double), ("theta", C.c_double),
+                ("fallbacks", C.c_int64), ("F", C.c_double), ("theta", C.c_double),
                 ("seconds", C.c_double), ("phase", C.c_int32), ("status", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("batch", C.c_int32), ("seed", C.c_int32), ("lr", C.c_float),
+                ("reserved", C.c_float)]
 
 
 class LgfError(RuntimeError):
@@ -95,6 +100,15 @@ def load_library(path: str | None = None):
         "lgf_batch_config": ([V, C.POINTER(I32), C.POINTER(I32)], I32),
         "lgf_batch_last_error": ([V], C.c_char_p),
         "lgf_fix_batch": ([P, I32, C.POINTER(C.c_int32 * 4), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), S], I32),
+        "lgf_model_bytes": ([], C.c_size_t),
+        "lgf_set_model": ([V, C.c_char_p, C.c_size_t], I32),
+        "lgf_learned_factors": ([V, C.POINTER(C.c_double), C.POINTER(C.c_double)], I32),
+        "lgf_linesearch_bands": ([V, C.POINTER(C.c_double), C.POINTER(C.c_double)], I32),
+        "lgf_mlp_train": ([C.POINTER(C.c_float)] * 3 + [I64, C.POINTER(TrainParams), C.c_void_p,
+                          C.POINTER(C.c_size_t), C.POINTER(C.c_float)], I32),
+        "lgf_mlp_grad": ([C.c_char_p, C.c_size_t] + [C.POINTER(C.c_float)] * 3 + [I64, C.POINTER(C.c_float),
+                         C.POINTER(C.c_double)], I32),
+        "lgf_mlp_eval": ([C.c_char_p, C.c_size_t, C.POINTER(C.c_float), I64, C.POINTER(C.c_float)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -224,6 +238,20 @@ class Context:
             self._check(rc)
         return s
 
+    # -- learned step ----------------------------------------------------------
+    def set_model(self, blob: bytes):
+        self._check(self.lib.lgf_set_model(self.h, blob, len(blob)))
+
+    def learned_factors(self):
+        x, s = (C.c_double * 16)(), (C.c_double * 16)()
+        self._check(self.lib.lgf_learned_factors(self.h, x, s))
+        return np.array(x[:]), np.array(s[:])
+
+    def linesearch_bands(self):
+        x, ls = (C.c_double * 16)(), (C.c_double * 16)()
+        self._check(self.lib.lgf_linesearch_bands(self.h, x, ls))
+        return np.array(x[:]), np.array(ls[:])
+
     # -- profiling -----------------------------------------------------------
     def profile(self):
         n = 32
@@ -330,3 +358,50 @@ def fix_batch(links_list, lib=None, **kw):
     st = (Stats * n)()
     rc = L.lgf_fix_batch(C.byref(p), n, arr, pin, pout, st)
     return outs, list(st), rc
+
+
+def _f32(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def mlp_train(X, Y, M, steps=2000, batch=256, seed=1, lr=1e-3, lib=None):
+    """Train the learned-step network on the GPU: (model blob, loss per step)."""
+    L = lib or load_library()
+    X, px = _f32(X)
+    Y, py = _f32(Y)
+    M, pm = _f32(M)
+    n = X.shape[0]
+    tp = TrainParams(steps=int(steps), batch=int(batch), seed=int(seed), lr=float(lr))
+    cap = C.c_size_t(L.lgf_model_bytes())
+    blob = C.create_string_buffer(cap.value)
+    trace = np.zeros(max(int(steps), 1), dtype=np.float32)
+    rc = L.lgf_mlp_train(px, py, pm, n, C.byref(tp), blob, C.byref(cap), trace.ctypes.data_as(C.POINTER(C.c_float)))
+    if rc != OK:
+        raise LgfError(rc, L.lgf_last_error(None).decode())
+    return blob.raw[:cap.value], trace[:int(steps)]
+
+
+def mlp_grad(blob, X, Y, M, lib=None):
+    """(loss, gradient[6288]) of a model on samples, by the training kernels."""
+    L = lib or load_library()
+    X, px = _f32(X)
+    Y, py = _f32(Y)
+    M, pm = _f32(M)
+    g = np.zeros(6288, dtype=np.float32)
+    loss = C.c_double()
+    rc = L.lgf_mlp_grad(blob, len(blob), px, py, pm, X.shape[0], g.ctypes.data_as(C.POINTER(C.c_float)),
+                        C.byref(loss))
+    if rc != OK:
+        raise LgfError(rc, L.lgf_last_error(None).decode())
+    return loss.value, g
+
+
+def mlp_eval(blob, X, lib=None):
+    L = lib or load_library()
+    X, px = _f32(X)
+    Y = np.zeros_like(X)
+    rc = L.lgf_mlp_eval(blob, len(blob), px, X.shape[0], Y.ctypes.data_as(C.POINTER(C.c_float)))
+    if rc != OK:
+        raise LgfError(rc, L.lgf_last_error(None).decode())
+    return Y

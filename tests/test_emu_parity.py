@@ -173,3 +173,95 @@ def test_emulated_batch_mixed_autotuned(E, oracle_lib):
             assert np.max(np.abs(oracle.transform(d, U, G) - b.store(i))) <= 1e-12
     outs, sts, rc = lgf.fix_batch(Us, lib=E, poll_every=4)
     assert rc == lgf.OK and all(s.theta < 1e-15 for s in sts)
+
+
+# ---------------------------------------------------------------------------
+# learned spectral step (FP64) and the network kernels
+# ---------------------------------------------------------------------------
+from oracle import mlp as omlp  # noqa: E402
+
+
+def _rand_blob(seed, scale=0.3, b3=None):
+    rng = np.random.default_rng(seed)
+    p = {k: rng.normal(scale=scale, size=s) for k, s in omlp.SHAPES}
+    if b3 is not None:
+        p["b3"] = np.full(16, b3)
+    return omlp.blob_from_params(p)
+
+
+def test_emulated_learned_zero_model_is_plain(E, oracle_lib):
+    dims = (4, 4, 8, 4)
+    U = synth.random_links(dims, 7)
+    zero = omlp.blob_from_params({k: np.zeros(s) for k, s in omlp.SHAPES})
+    with lgf.Context(dims, lib=E, step=1) as a, lgf.Context(dims, lib=E) as b:
+        a.set_model(zero)
+        a.load(U)
+        b.load(U)
+        fa, ta = a.step(3, trace=True)
+        fb, tb = b.step(3, trace=True)
+        assert np.array_equal(a.store(), b.store()) and np.array_equal(fa, fb)
+
+
+def test_emulated_learned_factors_and_update_match_oracle(E, oracle_lib):
+    dims = (8, 4, 4, 8)
+    V = synth.volume(dims)
+    U = synth.random_links(dims, 8)
+    blob = _rand_blob(9, scale=0.2)
+    p = omlp.params_from_blob(blob)
+    with lgf.Context(dims, lib=E, step=1) as c:
+        c.set_model(blob)
+        c.load(U)
+        x, s = c.learned_factors()
+        _, _, delta = oracle.measure(dims, U)
+        P, cnt = oracle.band_powers(dims, delta)
+        xo = omlp.features(P, cnt, V)
+        assert np.max(np.abs(x - xo)) <= 1e-12
+        so = omlp.factors(p, xo)
+        assert np.max(np.abs(s / so - 1)) <= 1e-5
+        c.step(1)
+        Ug = c.store()
+        st = c.measure()
+    F0 = oracle.measure(dims, U)[0]
+    Uc = omlp.update_with(dims, U, s)
+    Uo = Uc if oracle.measure(dims, Uc)[0] > F0 else oracle.step(dims, U, 1)[0]
+    assert np.max(np.abs(Ug - Uo)) <= 1e-12
+
+
+def test_emulated_mlp_kernels_match_oracle(E):
+    blob = _rand_blob(10)
+    p = omlp.params_from_blob(blob)
+    rng = np.random.default_rng(11)
+    X, T = rng.normal(size=(40, 16)), rng.normal(size=(40, 16))
+    M = (rng.random((40, 16)) > 0.25).astype(float)
+    Y = lgf.mlp_eval(blob, X, lib=E)
+    Yo, _ = omlp.forward(p, X.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(Y - Yo)) <= 1e-5 * max(1.0, np.max(np.abs(Yo)))
+    loss, g = lgf.mlp_grad(blob, X, T, M, lib=E)
+    lo, go = omlp.loss_and_grad(p, X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64), M)
+    go = omlp.flat(go)
+    assert abs(loss - lo) <= 1e-5 * lo
+    assert np.linalg.norm(g - go) <= 1e-5 * np.linalg.norm(go)
+
+
+def test_emulated_mlp_training_reduces_loss(E):
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(512, 16)) * 0.5
+    T = np.tanh(X @ rng.normal(size=(16, 16)) * 0.3)
+    M = np.ones_like(X)
+    blob, trace = lgf.mlp_train(X, T, M, steps=300, batch=64, seed=3, lr=3e-3, lib=E)
+    p = omlp.params_from_blob(blob)
+    l_end = omlp.loss_and_grad(p, X, T, M)[0]
+    assert trace[-20:].mean() < 0.5 * trace[:5].mean() and l_end < 0.5 * trace[0]
+
+
+def test_emulated_linesearch_matches_oracle(E, oracle_lib):
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 13)
+    with lgf.Context(dims, lib=E) as c:
+        c.load(U)
+        x, ls = c.linesearch_bands()
+        assert np.array_equal(c.store(), U)          # the links are not changed
+    xo, lso, best = omlp.linesearch(dims, U)
+    assert np.max(np.abs(x - xo)) <= 1e-12
+    Fg = oracle.measure(dims, omlp.update_with(dims, U, np.exp(ls)))[0]
+    assert abs(Fg - best) <= 1e-10
