@@ -98,6 +98,7 @@ int32_t build_tables(lgf_batch* b)
         Bufs<T>& bf = mbufs<T>(b->m[i]);
         bf.geo = make_geo<T>(b->dims[i].data(), b->tile_bytes);
         const Geo& g = bf.geo;
+        if (delta_elems(g) > bf.d_cap) return fail(b, LGF_E_STATE, "Delta buffer too small for this tile width");
         BatchCfg<T>& c = host[i];
         c.geo = g;
         c.U[0] = bf.U[0];
@@ -272,8 +273,9 @@ int32_t identity_member(lgf_batch* b, int i)
     const int64_t V = bf.geo.V;
     const dim3 gr((unsigned)blocks_for(V, 256));
     for (int mu = 0; mu < 4; ++mu)
-        TRY(launch(b, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, V, bf.U[0] + (int64_t)mu * NE * V));
-    return launch(b, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, V, bf.G);
+        TRY(launch(b, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, V, bf.geo.VS,
+                   bf.U[0] + (int64_t)mu * NE * bf.geo.VS));
+    return launch(b, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, V, bf.geo.VS, bf.G);
 }
 
 int32_t identity_all(lgf_batch* b)
@@ -312,7 +314,7 @@ int32_t autotune(lgf_batch* b)
     std::vector<std::pair<int, int>> cand;
     for (int nth : {64, 128, 256})
         if (nth <= std::max(64, max_np))
-            for (int tb : {32, 64, 128}) cand.push_back({nth, tb});
+            for (int tb : kTileChoices) cand.push_back({nth, tb});
     hipEvent_t e0, e1;
     HIPCHK(b, hipEventCreate(&e0));
     HIPCHK(b, hipEventCreate(&e1));
@@ -367,7 +369,8 @@ template <typename T, int NE>
 int32_t load_member(lgf_batch* b, int i, const double* src, C2<T>* U)
 {
     const int64_t V = mbufs<T>(b->m[i]).geo.V;
-    return launch(b, K_LOAD, k_load<T, NE>, dim3((unsigned)blocks_for(4 * V, 256)), dim3(256), 0, V, src, U, b->check);
+    return launch(b, K_LOAD, k_load<T, NE>, dim3((unsigned)blocks_for(4 * V, 256)), dim3(256), 0, V,
+                  mbufs<T>(b->m[i]).geo.VS, src, U, b->check);
 }
 
 template <typename T, int NE>
@@ -375,7 +378,7 @@ int32_t store_member(lgf_batch* b, int i, double* dst)
 {
     Bufs<T>& bf = mbufs<T>(b->m[i]);
     const int64_t V = bf.geo.V;
-    return launch(b, K_STORE, k_store<T, NE>, dim3((unsigned)blocks_for(4 * V, 256)), dim3(256), 0, V,
+    return launch(b, K_STORE, k_store<T, NE>, dim3((unsigned)blocks_for(4 * V, 256)), dim3(256), 0, V, bf.geo.VS,
                   (const C2<T>*)bf.U[b->st_host[i].cur], dst);
 }
 
@@ -384,7 +387,7 @@ int32_t store_member_gauge(lgf_batch* b, int i, double* dst)
 {
     Bufs<T>& bf = mbufs<T>(b->m[i]);
     const int64_t V = bf.geo.V;
-    return launch(b, K_FIELD, k_field_store<T, NE>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V,
+    return launch(b, K_FIELD, k_field_store<T, NE>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V, bf.geo.VS,
                   (const C2<T>*)bf.G, dst);
 }
 
@@ -509,7 +512,7 @@ int32_t lgf_batch_create(const lgf_params* p, int32_t n, const int32_t (*dims)[4
         const int64_t V = (int64_t)d[0] * d[1] * d[2] * d[3];
         const int NQ = d[2] * d[3];
         if (b->mixed) {
-            const size_t link = sizeof(C2<double>) * (size_t)4 * b->NE * V;
+            const size_t link = sizeof(C2<double>) * (size_t)4 * b->NE * mm.d.geo.VS;
             if (hipMalloc(&mm.U0, link) != hipSuccess) { b->err = "hipMalloc U0"; return bail(LGF_E_OUT_OF_MEMORY); }
             b->bytes += link;
             u0[i] = mm.U0;
@@ -587,11 +590,11 @@ int32_t lgf_batch_load(lgf_batch_t b, int32_t i, const void* links, int32_t wher
         if (rc != LGF_OK) break;
         const dim3 gr((unsigned)blocks_for(V, 256));
         if (b->use64)
-            rc = b->NE == 9 ? launch(b, K_FIELD, k_field_identity<double, 9>, gr, dim3(256), 0, V, mm.d.G)
-                            : launch(b, K_FIELD, k_field_identity<double, 6>, gr, dim3(256), 0, V, mm.d.G);
+            rc = b->NE == 9 ? launch(b, K_FIELD, k_field_identity<double, 9>, gr, dim3(256), 0, V, mm.d.geo.VS, mm.d.G)
+                            : launch(b, K_FIELD, k_field_identity<double, 6>, gr, dim3(256), 0, V, mm.d.geo.VS, mm.d.G);
         if (rc == LGF_OK && b->use32)
-            rc = b->NE == 9 ? launch(b, K_FIELD, k_field_identity<float, 9>, gr, dim3(256), 0, V, mm.f.G)
-                            : launch(b, K_FIELD, k_field_identity<float, 6>, gr, dim3(256), 0, V, mm.f.G);
+            rc = b->NE == 9 ? launch(b, K_FIELD, k_field_identity<float, 9>, gr, dim3(256), 0, V, mm.f.geo.VS, mm.f.G)
+                            : launch(b, K_FIELD, k_field_identity<float, 6>, gr, dim3(256), 0, V, mm.f.geo.VS, mm.f.G);
         if (rc != LGF_OK) break;
         const DevState s0 = initial_state(b, false);
         if (hipMemcpyAsync(b->st + i, &s0, sizeof(DevState), hipMemcpyHostToDevice, b->stream) != hipSuccess ||

@@ -19,7 +19,7 @@
 // Site index s = q * NP + p with p = y * Lx + x (plane offset) and
 // q = t * Lz + z (plane index).  Delta after the (x, y) transform is kept in
 // a tiled layout: element (field c, plane position p, plane q) at
-//   D[((p / W) * 4 + c) * NQ + q) * W + p % W]
+//   D[((p / W) * 4 + c) * DS + q * W + p % W]      (DS >= NQ * W)
 // so the (x, y) kernels read and write runs of W consecutive complex values
 // and the (z, t) kernel reads one contiguous block of NQ * W values.
 #pragma once
@@ -35,6 +35,11 @@ struct Geo {
     int NQ, logNQ;  // Lz * Lt
     int W, logW;    // tile width of the Delta layout
     int64_t V;
+    int64_t VS;     // stride between the component arrays of a link or gauge field:
+                    // V plus a pad, so the arrays do not sit a power of two apart
+                    // (which would map them onto the same cache sets and channels)
+    int64_t DS;     // stride between the (tile, field) chunks of the Delta layout:
+                    // NQ * W plus a pad, for the same reason
 };
 
 // Per-configuration state on the device.  The host reads it back only at
@@ -95,7 +100,7 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* red, int 
 // (non-negative doubles order like their bit patterns); dev[2]: number of
 // links with a non-finite entry.
 template <typename T, int NE>
-__global__ void __launch_bounds__(256) k_load(int64_t V, const double* __restrict__ src,
+__global__ void __launch_bounds__(256) k_load(int64_t V, int64_t VS, const double* __restrict__ src,
                                               C2<T>* __restrict__ U, unsigned long long* __restrict__ dev)
 {
     __shared__ double red[2 * 256];
@@ -130,7 +135,7 @@ __global__ void __launch_bounds__(256) k_load(int64_t V, const double* __restric
             dd = sqrt((det.x - 1.0) * (det.x - 1.0) + det.y * det.y);
         }
 #pragma unroll
-        for (int e = 0; e < NE; ++e) U[(mu * NE + e) * V + s] = mk<T>((T)m.e[e].x, (T)m.e[e].y);
+        for (int e = 0; e < NE; ++e) U[(mu * NE + e) * VS + s] = mk<T>((T)m.e[e].x, (T)m.e[e].y);
     }
     // block max
     red[2 * tid] = du;
@@ -152,14 +157,15 @@ __global__ void __launch_bounds__(256) k_load(int64_t V, const double* __restric
 
 // SoA links of type T -> canonical FP64, third row rebuilt when NE = 6.
 template <typename T, int NE>
-__global__ void __launch_bounds__(256) k_store(int64_t V, const C2<T>* __restrict__ U, double* __restrict__ dst)
+__global__ void __launch_bounds__(256) k_store(int64_t V, int64_t VS, const C2<T>* __restrict__ U,
+                                               double* __restrict__ dst)
 {
     const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (li >= 4 * V) return;
     const int64_t s = li >> 2;
     const int mu = (int)(li & 3);
     M3<T> m;
-    load_mat<T, NE>(m, U + (int64_t)mu * NE * V, V, s);
+    load_mat<T, NE>(m, U + (int64_t)mu * NE * VS, VS, s);
     C2<double>* p = reinterpret_cast<C2<double>*>(dst) + li * 9;
 #pragma unroll
     for (int e = 0; e < 9; ++e) p[e] = mk<double>((double)m.e[e].x, (double)m.e[e].y);
@@ -167,34 +173,36 @@ __global__ void __launch_bounds__(256) k_store(int64_t V, const C2<T>* __restric
 
 // per-site matrix field (g or G): canonical FP64 [s][3][3] <-> SoA
 template <typename T, int NE>
-__global__ void __launch_bounds__(256) k_field_store(int64_t V, const C2<T>* __restrict__ f, double* __restrict__ dst)
+__global__ void __launch_bounds__(256) k_field_store(int64_t V, int64_t VS, const C2<T>* __restrict__ f,
+                                                     double* __restrict__ dst)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
     M3<T> m;
-    load_mat<T, NE>(m, f, V, s);
+    load_mat<T, NE>(m, f, VS, s);
     C2<double>* p = reinterpret_cast<C2<double>*>(dst) + s * 9;
 #pragma unroll
     for (int e = 0; e < 9; ++e) p[e] = mk<double>((double)m.e[e].x, (double)m.e[e].y);
 }
 
 template <typename T, int NE>
-__global__ void __launch_bounds__(256) k_field_load(int64_t V, const double* __restrict__ src, C2<T>* __restrict__ f)
+__global__ void __launch_bounds__(256) k_field_load(int64_t V, int64_t VS, const double* __restrict__ src,
+                                                    C2<T>* __restrict__ f)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
     const C2<double>* p = reinterpret_cast<const C2<double>*>(src) + s * 9;
 #pragma unroll
-    for (int e = 0; e < NE; ++e) f[e * V + s] = mk<T>((T)p[e].x, (T)p[e].y);
+    for (int e = 0; e < NE; ++e) f[e * VS + s] = mk<T>((T)p[e].x, (T)p[e].y);
 }
 
 template <typename T, int NE>
-__global__ void __launch_bounds__(256) k_field_identity(int64_t V, C2<T>* __restrict__ f)
+__global__ void __launch_bounds__(256) k_field_identity(int64_t V, int64_t VS, C2<T>* __restrict__ f)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
 #pragma unroll
-    for (int e = 0; e < NE; ++e) f[e * V + s] = mk<T>((e == 0 || e == 4 || e == 8) ? T(1) : T(0), T(0));
+    for (int e = 0; e < NE; ++e) f[e * VS + s] = mk<T>((e == 0 || e == 4 || e == 8) ? T(1) : T(0), T(0));
 }
 
 
@@ -211,7 +219,7 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
     const int tid = threadIdx.x, nth = blockDim.x;
     const int Lx = geo.L[0], Ly = geo.L[1], Lz = geo.L[2], Lt = geo.L[3];
     const int NP = geo.NP;
-    const int64_t V = geo.V;
+    const int64_t VS = geo.VS;
     const int z = q & (Lz - 1), t = q >> geo.logL[2];
     const int64_t qzp = (int64_t)(t * Lz + ((z + 1) & (Lz - 1))) * NP;
     const int64_t qzm = (int64_t)(t * Lz + ((z - 1) & (Lz - 1))) * NP;
@@ -229,17 +237,17 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc.c[c] = mk<T>(T(0), T(0));
         M3<T> gx;
-        if (APPLY_G) load_mat<T, NE>(gx, g, V, s);
+        if (APPLY_G) load_mat<T, NE>(gx, g, VS, s);
         double f = 0.0;
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             M3<T> u;
-            load_mat<T, NE>(u, Uin + (int64_t)mu * NE * V, V, s);
+            load_mat<T, NE>(u, Uin + (int64_t)mu * NE * VS, VS, s);
             if (APPLY_G) {
                 M3<T> gn, r;
-                load_mat<T, NE>(gn, g, V, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
+                load_mat<T, NE>(gn, g, VS, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
                 a_u_bdag<T, (NE == 6 ? 2 : 3)>(gx, u, gn, r);
-                store_mat<T, NE>(r, Uout + (int64_t)mu * NE * V, V, s);
+                store_mat<T, NE>(r, Uout + (int64_t)mu * NE * VS, VS, s);
                 u = r;
             }
             f += re_trace(u);
@@ -249,10 +257,10 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
         for (int nu = 0; nu < 4; ++nu) {
             M3<T> u;
             const int64_t sb = nu == 0 ? xm : nu == 1 ? ym : nu == 2 ? qzm + p : qtm + p;
-            load_mat<T, NE>(u, Uin + (int64_t)nu * NE * V, V, sb);
+            load_mat<T, NE>(u, Uin + (int64_t)nu * NE * VS, VS, sb);
             if (APPLY_G) {
                 M3<T> gb, r;
-                load_mat<T, NE>(gb, g, V, sb);
+                load_mat<T, NE>(gb, g, VS, sb);
                 a_u_bdag<T, (NE == 6 ? 2 : 3)>(gb, u, gx, r);
                 u = r;
             }
@@ -275,7 +283,7 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
     const int W = geo.W;
     for (int i = tid; i < 4 * NP; i += nth) {
         const int c = i >> geo.logNP, p = i & (NP - 1);
-        D[((int64_t)((p >> geo.logW) * 4 + c) * geo.NQ + q) * W + (p & (W - 1))] = buf[i];
+        D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))] = buf[i];
     }
 }
 
@@ -344,7 +352,7 @@ __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, co
 {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int W = geo.W, NQ = geo.NQ, n = NQ * W;
-    C2<T>* src = D + (int64_t)(j * 4 + c) * NQ * W;
+    C2<T>* src = D + (int64_t)(j * 4 + c) * geo.DS;
     for (int i = tid; i < n; i += nth) buf[i] = src[i];
     __syncthreads();
     const int Lz = geo.L[2];
@@ -374,10 +382,10 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
 {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int NP = geo.NP, W = geo.W;
-    const int64_t V = geo.V;
+    const int64_t VS = geo.VS;
     for (int i = tid; i < 4 * NP; i += nth) {
         const int c = i >> geo.logNP, p = i & (NP - 1);
-        buf[i] = D[((int64_t)((p >> geo.logW) * 4 + c) * geo.NQ + q) * W + (p & (W - 1))];
+        buf[i] = D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))];
     }
     __syncthreads();
     fft_inv<T, LMAX>(buf, geo.L[1], Lines{geo.logL[0], 2, 1, NP, geo.L[0]}, twy, tid, nth);
@@ -390,10 +398,10 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
         M3<double> m;
         one_plus_alg_reunit(c, m);
         const int64_t s = q0 + p;
-        store_mat<T, NE>(cast_mat<T>(m), g, V, s);
+        store_mat<T, NE>(cast_mat<T>(m), g, VS, s);
         if (ACC_G) {
             M3<T> Gt;
-            load_mat<T, NE>(Gt, G, V, s);
+            load_mat<T, NE>(Gt, G, VS, s);
             M3<double> Gd = cast_mat<double>(Gt), r;
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -402,7 +410,7 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
                     r.e[3 * i + k] =
                         cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
             reunit(r);
-            store_mat<T, NE>(cast_mat<T>(r), G, V, s);
+            store_mat<T, NE>(cast_mat<T>(r), G, VS, s);
         }
     }
 }
@@ -509,21 +517,21 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
 // promoted gauge is stored as G64.
 // ---------------------------------------------------------------------------
 template <int NE>
-__device__ __forceinline__ void promote_site(int64_t V, int64_t s, const C2<float>* __restrict__ G32,
+__device__ __forceinline__ void promote_site(int64_t VS32, int64_t VS64, int64_t s, const C2<float>* __restrict__ G32,
                                              C2<double>* __restrict__ G64)
 {
     M3<float> a;
-    load_mat<float, NE>(a, G32, V, s);
+    load_mat<float, NE>(a, G32, VS32, s);
     M3<double> m = cast_mat<double>(a);
     reunit(m);
-    store_mat<double, NE>(m, G64, V, s);
+    store_mat<double, NE>(m, G64, VS64, s);
 }
 
 template <int NE>
 __device__ __forceinline__ void switch_link(const Geo& geo, int mu, int64_t s, const C2<double>* __restrict__ U0,
                                             const C2<double>* __restrict__ G, C2<double>* __restrict__ U)
 {
-    const int64_t V = geo.V;
+    const int64_t VS = geo.VS;
     int64_t rem = s;
     int c[4];
 #pragma unroll
@@ -534,19 +542,19 @@ __device__ __forceinline__ void switch_link(const Geo& geo, int mu, int64_t s, c
     c[mu] = (c[mu] + 1) & (geo.L[mu] - 1);
     const int64_t sn = (((int64_t)c[3] * geo.L[2] + c[2]) * geo.L[1] + c[1]) * geo.L[0] + c[0];
     M3<double> a, u, b, r;
-    load_mat<double, NE>(a, G, V, s);
-    load_mat<double, NE>(u, U0 + (int64_t)mu * NE * V, V, s);
-    load_mat<double, NE>(b, G, V, sn);
+    load_mat<double, NE>(a, G, VS, s);
+    load_mat<double, NE>(u, U0 + (int64_t)mu * NE * VS, VS, s);
+    load_mat<double, NE>(b, G, VS, sn);
     a_u_bdag<double, (NE == 6 ? 2 : 3)>(a, u, b, r);
-    store_mat<double, NE>(r, U + (int64_t)mu * NE * V, V, s);
+    store_mat<double, NE>(r, U + (int64_t)mu * NE * VS, VS, s);
 }
 
 template <int NE>
-__global__ void __launch_bounds__(256) k_promote_gauge(int64_t V, const C2<float>* __restrict__ G32,
-                                                       C2<double>* __restrict__ G64)
+__global__ void __launch_bounds__(256) k_promote_gauge(int64_t V, int64_t VS32, int64_t VS64,
+                                                       const C2<float>* __restrict__ G32, C2<double>* __restrict__ G64)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < V) promote_site<NE>(V, s, G32, G64);
+    if (s < V) promote_site<NE>(VS32, VS64, s, G32, G64);
 }
 
 template <int NE>
@@ -665,7 +673,8 @@ __global__ void __launch_bounds__(256) kb_promote(const BatchCfg<float>* __restr
         if (!c64[cfg].st->switch_pending || c64[cfg].st->done) continue;
         const Geo& geo = c64[cfg].geo;
         const int64_t q0 = (int64_t)(w & ((1u << kItemShift) - 1)) * geo.NP;
-        for (int p = threadIdx.x; p < geo.NP; p += blockDim.x) promote_site<NE>(geo.V, q0 + p, c32[cfg].G, c64[cfg].G);
+        for (int p = threadIdx.x; p < geo.NP; p += blockDim.x)
+            promote_site<NE>(c32[cfg].geo.VS, geo.VS, q0 + p, c32[cfg].G, c64[cfg].G);
     }
 }
 
@@ -728,7 +737,7 @@ __global__ void __launch_bounds__(512) k_zt_fwd_bands(Geo geo, C2<T>* __restrict
     const int tid = threadIdx.x, nth = blockDim.x;
     const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
     const int W = geo.W, NQ = geo.NQ, n = NQ * W, Lz = geo.L[2];
-    C2<T>* src = D + (int64_t)(j * 4 + c) * NQ * W;
+    C2<T>* src = D + (int64_t)(j * 4 + c) * geo.DS;
     for (int i = tid; i < n; i += nth) buf[i] = src[i];
     __syncthreads();
     const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
@@ -779,7 +788,7 @@ __global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __r
     const int tid = threadIdx.x, nth = blockDim.x;
     const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
     const int W = geo.W, NQ = geo.NQ, n = NQ * W, Lz = geo.L[2];
-    const C2<T>* src = Din + (int64_t)(j * 4 + c) * NQ * W;
+    const C2<T>* src = Din + (int64_t)(j * 4 + c) * geo.DS;
     const SpectralScale sc = make_scale(geo, ptab, c0, accel);
     for (int i = tid; i < n; i += nth) {
         const int w = i & (W - 1), qq = i >> geo.logW;
@@ -795,7 +804,7 @@ __global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __r
     const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
     fft_inv<T, LMAX>(buf, geo.L[3], tl, twt, tid, nth);
     fft_inv<T, LMAX>(buf, Lz, zl, twz, tid, nth);
-    C2<T>* dst = Dout + (int64_t)(j * 4 + c) * NQ * W;
+    C2<T>* dst = Dout + (int64_t)(j * 4 + c) * geo.DS;
     for (int i = tid; i < n; i += nth) dst[i] = buf[i];
 }
 

@@ -266,7 +266,7 @@ int32_t enqueue_store(lgf_context* c, double* dst)
 {
     Bufs<T>& b = bufs<T>(c);
     return launch(c, K_STORE, k_store<T, NE>, dim3((unsigned)blocks_for(4 * b.geo.V, 256)), dim3(256), 0,
-                  b.geo.V, (const C2<T>*)b.U[c->st_host->cur], dst);
+                  b.geo.V, b.geo.VS, (const C2<T>*)b.U[c->st_host->cur], dst);
 }
 
 int32_t store_any(lgf_context* c, double* dst)
@@ -279,7 +279,8 @@ template <typename T, int NE>
 int32_t enqueue_load(lgf_context* c, const double* src, C2<T>* U)
 {
     const int64_t V = bufs<T>(c).geo.V;
-    return launch(c, K_LOAD, k_load<T, NE>, dim3((unsigned)blocks_for(4 * V, 256)), dim3(256), 0, V, src, U,
+    return launch(c, K_LOAD, k_load<T, NE>, dim3((unsigned)blocks_for(4 * V, 256)), dim3(256), 0, V,
+                  bufs<T>(c).geo.VS, src, U,
                   c->check);
 }
 
@@ -290,8 +291,10 @@ int32_t enqueue_identity_G(lgf_context* c)
     if (!b.G) return LGF_OK;
     const int64_t V = b.geo.V;
     if (c->NE == 9)
-        return launch(c, K_FIELD, k_field_identity<T, 9>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V, b.G);
-    return launch(c, K_FIELD, k_field_identity<T, 6>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V, b.G);
+        return launch(c, K_FIELD, k_field_identity<T, 9>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V,
+                      b.geo.VS, b.G);
+    return launch(c, K_FIELD, k_field_identity<T, 6>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V,
+                  b.geo.VS, b.G);
 }
 
 // LGF_MIXED: leave FP32.  G64 = reunit(G32); U64 = G64 U0 G64^dag(x+mu).
@@ -300,6 +303,7 @@ int32_t enqueue_switch(lgf_context* c)
 {
     const Geo& g = c->d.geo;
     TRY(launch(c, K_SWITCH, k_promote_gauge<NE>, dim3((unsigned)blocks_for(g.V, 256)), dim3(256), 0, g.V,
+               c->f.geo.VS, g.VS,
                (const C2<float>*)c->f.G, c->d.G));
     TRY(launch(c, K_SWITCH, k_switch<NE>, dim3((unsigned)blocks_for(4 * g.V, 256)), dim3(256), 0, g,
                (const C2<double>*)c->U0, (const C2<double>*)c->d.G, c->d.U[0]));
@@ -343,15 +347,15 @@ int32_t ensure_learned_buffers(lgf_context* c)
     if (c->D2) return LGF_OK;
     if (!c->use64) return fail(c, LGF_E_STATE, "the learned step and the band line search run in FP64");
     const Geo& g = c->d.geo;
-    HIPCHK(c, hipMalloc(&c->D2, sizeof(C2<double>) * 4 * (size_t)g.V));
-    HIPCHK(c, hipMalloc(&c->D3, sizeof(C2<double>) * 4 * (size_t)g.V));
+    HIPCHK(c, hipMalloc(&c->D2, sizeof(C2<double>) * (size_t)delta_elems(g)));
+    HIPCHK(c, hipMalloc(&c->D3, sizeof(C2<double>) * (size_t)delta_elems(g)));
     const int nblk = (g.NP / g.W) * 4;
     HIPCHK(c, hipMalloc(&c->band_partial, sizeof(double) * 16 * nblk));
     HIPCHK(c, hipMalloc(&c->counts16, sizeof(double) * 16));
     HIPCHK(c, hipMalloc(&c->s_dev, sizeof(double) * 16));
     HIPCHK(c, hipMalloc(&c->x_dev, sizeof(double) * 16));
     HIPCHK(c, hipMalloc(&c->ones_dev, sizeof(double) * 16));
-    c->bytes += 2 * sizeof(C2<double>) * 4 * (size_t)g.V;
+    c->bytes += 2 * sizeof(C2<double>) * (size_t)delta_elems(g);
     // bands: log-spaced in p^2 from the smallest nonzero p^2 to p2max; the
     // number of modes in each is counted here with the kernels' formula
     double p2max = 0.0;
@@ -640,7 +644,7 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
     if (use32 && (rc = alloc_bufs<float>(c, p->dims, c->NE, c->track, 64, c->f, c->bytes)) != LGF_OK) return bail(rc);
     const Geo& g = use64 ? c->d.geo : c->f.geo;
     if (p->precision == LGF_MIXED) {
-        const size_t link = sizeof(C2<double>) * (size_t)4 * c->NE * g.V;
+        const size_t link = sizeof(C2<double>) * (size_t)4 * c->NE * c->d.geo.VS;
         if (hipMalloc(&c->U0, link) != hipSuccess) { c->err = "hipMalloc U0"; return bail(LGF_E_OUT_OF_MEMORY); }
         c->bytes += link;
     }
@@ -806,11 +810,11 @@ int32_t lgf_store_gauge(lgf_ctx c, void* G, int32_t where)
     int32_t rc;
     const dim3 grid((unsigned)blocks_for(V, 256));
     if (c->phase == 1)
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<double, 9>, grid, dim3(256), 0, V, (const C2<double>*)c->d.G, dst)
-                        : launch(c, K_FIELD, k_field_store<double, 6>, grid, dim3(256), 0, V, (const C2<double>*)c->d.G, dst);
+        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<double, 9>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)c->d.G, dst)
+                        : launch(c, K_FIELD, k_field_store<double, 6>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)c->d.G, dst);
     else
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<float, 9>, grid, dim3(256), 0, V, (const C2<float>*)c->f.G, dst)
-                        : launch(c, K_FIELD, k_field_store<float, 6>, grid, dim3(256), 0, V, (const C2<float>*)c->f.G, dst);
+        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<float, 9>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)c->f.G, dst)
+                        : launch(c, K_FIELD, k_field_store<float, 6>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)c->f.G, dst);
     if (rc == LGF_OK && where == LGF_HOST &&
         hipMemcpyAsync(G, dst, nbytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
         rc = fail(c, LGF_E_DEVICE, "hipMemcpyAsync G out");
@@ -840,11 +844,11 @@ int32_t lgf_load_gauge(lgf_ctx c, const void* G, int32_t where)
     int32_t rc;
     const dim3 grid((unsigned)blocks_for(V, 256));
     if (c->phase == 1)
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<double, 9>, grid, dim3(256), 0, V, (const double*)src, c->d.G)
-                        : launch(c, K_FIELD, k_field_load<double, 6>, grid, dim3(256), 0, V, (const double*)src, c->d.G);
+        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<double, 9>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, c->d.G)
+                        : launch(c, K_FIELD, k_field_load<double, 6>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, c->d.G);
     else
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<float, 9>, grid, dim3(256), 0, V, (const double*)src, c->f.G)
-                        : launch(c, K_FIELD, k_field_load<float, 6>, grid, dim3(256), 0, V, (const double*)src, c->f.G);
+        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<float, 9>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, c->f.G)
+                        : launch(c, K_FIELD, k_field_load<float, 6>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, c->f.G);
     if (rc == LGF_OK) rc = sync_state(c);
     if (where == LGF_HOST) {
         (void)hipStreamSynchronize(c->stream);

@@ -5,6 +5,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -167,6 +168,7 @@ struct Bufs {
     C2<T>* D = nullptr;
     C2<T>* G = nullptr;
     C2<T>* tw = nullptr;     // Lx + Ly + Lz + Lt entries
+    int64_t d_cap = 0;       // complex elements allocated for D
     Geo geo{};
     int tw_off[4] = {0, 0, 0, 0};
 };
@@ -192,7 +194,26 @@ Geo make_geo(const int32_t* dims, int tile_bytes = 64)
     while (W > 1 && (size_t)W * g.NQ * sizeof(C2<T>) > kMaxLdsZt) W >>= 1;
     g.W = W;
     g.logW = ilog2(W);
+    // pads: 8 KiB + 256 B between component arrays, 256 B between Delta chunks
+    g.VS = g.V + (int64_t)((8192 + 256) / sizeof(C2<T>));
+    g.DS = (int64_t)g.NQ * W + (int64_t)(256 / sizeof(C2<T>));
     return g;
+}
+
+// Complex elements of the Delta buffer.
+inline int64_t delta_elems(const Geo& g) { return (int64_t)(g.NP / g.W) * 4 * g.DS; }
+
+// Tile widths (bytes) a geometry may be rebuilt with after allocation.
+constexpr int kTileChoices[3] = {32, 64, 128};
+
+// Delta capacity that holds the layout of every tile choice (smaller tiles
+// mean more chunks and so more padding).
+template <typename T>
+int64_t delta_capacity(const int32_t* dims, int tile_bytes)
+{
+    int64_t cap = delta_elems(make_geo<T>(dims, tile_bytes));
+    for (int tb : kTileChoices) cap = std::max(cap, delta_elems(make_geo<T>(dims, tb)));
+    return cap;
 }
 
 template <typename T>
@@ -243,14 +264,16 @@ template <typename T>
 int32_t alloc_bufs(Runner* c, const int32_t* dims, int NE, bool track, int tile_bytes, Bufs<T>& b, int64_t& bytes)
 {
     b.geo = make_geo<T>(dims, tile_bytes);
-    const int64_t V = b.geo.V;
-    const size_t link = sizeof(C2<T>) * (size_t)4 * NE * V;
-    const size_t field = sizeof(C2<T>) * (size_t)NE * V;
+    const int64_t VS = b.geo.VS;
+    const size_t link = sizeof(C2<T>) * (size_t)4 * NE * VS;
+    const size_t field = sizeof(C2<T>) * (size_t)NE * VS;
+    b.d_cap = delta_capacity<T>(dims, tile_bytes);
+    const size_t dbytes = sizeof(C2<T>) * (size_t)b.d_cap;
     HIPCHK(c, hipMalloc(&b.U[0], link));
     HIPCHK(c, hipMalloc(&b.U[1], link));
     HIPCHK(c, hipMalloc(&b.g, field));
-    HIPCHK(c, hipMalloc(&b.D, sizeof(C2<T>) * (size_t)4 * V));
-    bytes += 2 * link + field + sizeof(C2<T>) * 4 * V;
+    HIPCHK(c, hipMalloc(&b.D, dbytes));
+    bytes += 2 * link + field + dbytes;
     if (track) {
         HIPCHK(c, hipMalloc(&b.G, field));
         bytes += field;

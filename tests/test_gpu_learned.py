@@ -1,0 +1,161 @@
+"""GPU parity of the learned spectral step and of the network kernels.
+
+The gfx950 library, through its C ABI, against the FP64 reference in
+oracle/mlp.py: band features to 1e-12, factors to 1e-5 (the network runs
+with bfloat16 weights and float32 arithmetic), one learned update (with
+its accept-or-fall-back decision) to 1e-12 in the links, the golden-section
+line search to the oracle's best F, and the forward/backward/Adam kernels.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp as omlp
+from paper_1206_0675_amd import lgf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lgf.load_library()
+
+
+def announce(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rand_blob(seed, scale=0.3, b3=None):
+    rng = np.random.default_rng(seed)
+    p = {k: rng.normal(scale=scale, size=s) for k, s in omlp.SHAPES}
+    if b3 is not None:
+        p["b3"] = np.full(16, b3)
+    return omlp.blob_from_params(p)
+
+
+def oracle_learned(dims, U, s):
+    """The oracle's update for given factors s, with the accept rule."""
+    F0 = oracle.measure(dims, U)[0]
+    Uc = omlp.update_with(dims, U, s)
+    return Uc if oracle.measure(dims, Uc)[0] > F0 else oracle.step(dims, U, 1)[0]
+
+
+def test_zero_model_is_plain(L):
+    dims = (8, 8, 8, 8)
+    announce(f"zero model dims={dims}")
+    U = synth.random_links(dims, 7)
+    zero = omlp.blob_from_params({k: np.zeros(s) for k, s in omlp.SHAPES})
+    with lgf.Context(dims, lib=L, step=1) as a, lgf.Context(dims, lib=L) as b:
+        a.set_model(zero)
+        a.load(U)
+        b.load(U)
+        fa, _ = a.step(4, trace=True)
+        fb, _ = b.step(4, trace=True)
+        assert np.array_equal(a.store(), b.store()) and np.array_equal(fa, fb)
+
+
+@pytest.mark.parametrize("dims,seed,scale,b3", [((8, 4, 4, 8), 8, 0.2, None), ((16, 8, 8, 16), 21, 0.2, 0.4),
+                                                ((8, 8, 16, 4), 22, 0.1, -0.5)])
+def test_learned_factors_and_update(L, dims, seed, scale, b3):
+    announce(f"learned update dims={dims} seed={seed}")
+    V = synth.volume(dims)
+    U = synth.random_links(dims, seed)
+    blob = rand_blob(seed + 1, scale=scale, b3=b3)
+    p = omlp.params_from_blob(blob)
+    with lgf.Context(dims, lib=L, step=1) as c:
+        c.set_model(blob)
+        c.load(U)
+        x, s = c.learned_factors()
+        _, _, delta = oracle.measure(dims, U)
+        P, cnt = oracle.band_powers(dims, delta)
+        xo = omlp.features(P, cnt, V)
+        assert np.max(np.abs(x - xo)) <= 1e-12
+        assert np.max(np.abs(s / omlp.factors(p, xo) - 1)) <= 1e-5
+        c.step(1)
+        Ug = c.store()
+    assert np.max(np.abs(Ug - oracle_learned(dims, U, s))) <= 1e-12
+
+
+def test_learned_fallback_taken(L):
+    """Factors far too large in the linear regime lower F: the plain update
+    must be taken and counted."""
+    dims = (8, 8, 8, 8)
+    announce("learned fallback")
+    U = synth.small_field(dims, 31, 1e-3)
+    blob = rand_blob(32, scale=0.0, b3=2.3)
+    with lgf.Context(dims, lib=L, step=1) as c:
+        c.set_model(blob)
+        c.load(U)
+        c.step(1)
+        Ug = c.store()
+        st = c.measure()
+    assert st.fallbacks == 1
+    assert np.max(np.abs(Ug - oracle.step(dims, U, 1)[0])) <= 1e-12
+
+
+def test_learned_fix_converges(L):
+    dims = (16, 16, 16, 16)
+    announce("learned fix 16^4")
+    U = synth.random_links(dims, 33)
+    blob = rand_blob(34, scale=0.05, b3=0.2)
+    with lgf.Context(dims, lib=L, step=1, theta_stop=1e-15, max_iter=3000) as c:
+        c.set_model(blob)
+        c.load(U)
+        st = c.fix()
+        Ug = c.store()
+    assert st.theta < 1e-15 and st.iter > 0
+    Fo, tho, _ = oracle.measure(dims, Ug)
+    assert abs(st.F - Fo) <= 1e-12 and tho < 1e-15
+    P0 = oracle.plaquette(dims, U)
+    assert abs(oracle.plaquette(dims, Ug) - P0) <= 1e-12
+
+
+def test_linesearch(L):
+    dims = (8, 4, 4, 8)
+    announce("line search")
+    U = synth.random_links(dims, 13)
+    with lgf.Context(dims, lib=L) as c:
+        c.load(U)
+        x, ls = c.linesearch_bands()
+        assert np.array_equal(c.store(), U)
+    xo, lso, best = omlp.linesearch(dims, U)
+    assert np.max(np.abs(x - xo)) <= 1e-12
+    Fg = oracle.measure(dims, omlp.update_with(dims, U, np.exp(ls)))[0]
+    assert abs(Fg - best) <= 1e-10
+
+
+def test_mlp_kernels(L):
+    announce("mlp forward/backward")
+    blob = rand_blob(10)
+    p = omlp.params_from_blob(blob)
+    rng = np.random.default_rng(11)
+    X, T = rng.normal(size=(300, 16)), rng.normal(size=(300, 16))
+    M = (rng.random((300, 16)) > 0.25).astype(float)
+    X32, T32 = X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64)
+    Y = lgf.mlp_eval(blob, X, lib=L)
+    Yo, _ = omlp.forward(p, X32)
+    assert np.max(np.abs(Y - Yo)) <= 1e-5 * max(1.0, np.max(np.abs(Yo)))
+    loss, g = lgf.mlp_grad(blob, X, T, M, lib=L)
+    lo, go = omlp.loss_and_grad(p, X32, T32, M)
+    assert abs(loss - lo) <= 1e-5 * lo
+    assert np.linalg.norm(g - omlp.flat(go)) <= 1e-5 * np.linalg.norm(omlp.flat(go))
+
+
+def test_mlp_training_reduces_loss(L):
+    announce("mlp training")
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(2048, 16)) * 0.5
+    T = np.tanh(X @ rng.normal(size=(16, 16)) * 0.3)
+    M = np.ones_like(X)
+    blob, trace = lgf.mlp_train(X, T, M, steps=600, batch=128, seed=3, lr=3e-3, lib=L)
+    l_end = omlp.loss_and_grad(omlp.params_from_blob(blob), X, T, M)[0]
+    assert trace[-20:].mean() < 0.5 * trace[:5].mean() and l_end < 0.5 * trace[0]
+    blob2, trace2 = lgf.mlp_train(X, T, M, steps=600, batch=128, seed=3, lr=3e-3, lib=L)
+    assert blob2 == blob and np.array_equal(trace, trace2)      # deterministic
