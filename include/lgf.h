@@ -55,6 +55,7 @@ extern "C" {
 #define LGF_E_NONFINITE (-6)         /* NaN/Inf in the input, or theta became non-finite    */
 #define LGF_E_NOT_CONVERGED (-7)     /* max_iter reached with theta >= theta_stop           */
 #define LGF_E_STATE (-8)             /* call not valid now (e.g. step before load)          */
+#define LGF_E_MODEL (-9)             /* learned-step model blob malformed (size or header)  */
 
 /* where a caller's buffer lives */
 #define LGF_HOST 0
@@ -212,8 +213,8 @@ int32_t lgf_fix_batch(const lgf_params *common, int32_t n, const int32_t (*dims)
  * ------------------------------------------------------------------------- */
 size_t lgf_model_bytes(void);
 
-/* Set the network a LGF_STEP_LEARNED context uses (copied). LGF_E_INVALID_ARG
- * for a malformed blob. */
+/* Set the network a LGF_STEP_LEARNED context uses (copied). LGF_E_MODEL for
+ * a blob of the wrong size or header. */
 int32_t lgf_set_model(lgf_ctx ctx, const void *blob, size_t bytes);
 
 /* Features x and factors s (all 1 without a model) the learned step would
@@ -243,11 +244,13 @@ int32_t lgf_mlp_train(const float *X, const float *Y, const float *M, int64_t n,
                       void *blob_out, size_t *bytes, float *loss_trace);
 
 /* Loss and gradient (6288 floats, parameter order W1, b1, W2, b2, W3, b3) of a
- * model on n <= 1024 samples, by the training kernels. */
+ * model on n <= 1024 samples, by the training kernels.  LGF_E_MODEL for a
+ * malformed blob. */
 int32_t lgf_mlp_grad(const void *blob, size_t bytes, const float *X, const float *Y, const float *M, int64_t n,
                      float *grad, double *loss);
 
-/* Network outputs y (n x 16) for inputs X (n x 16). */
+/* Network outputs y (n x 16) for inputs X (n x 16).  LGF_E_MODEL for a
+ * malformed blob. */
 int32_t lgf_mlp_eval(const void *blob, size_t bytes, const float *X, int64_t n, float *Y);
 
 /* Per-kernel timing collected when params.profile = 1: for kernel k < n

@@ -522,6 +522,7 @@ const char* lgf_strerror(int32_t code)
     case LGF_E_NONFINITE: return "non-finite value";
     case LGF_E_NOT_CONVERGED: return "max_iter reached before theta < theta_stop";
     case LGF_E_STATE: return "call not valid in the current state";
+    case LGF_E_MODEL: return "malformed model blob";
     default: return "unknown status";
     }
 }
@@ -970,7 +971,7 @@ int32_t lgf_set_model(lgf_ctx c, const void* blob, size_t bytes)
     TRY(check_ctx(c, false));
     const uint16_t* w = nullptr;
     const float* b = nullptr;
-    if (!parse_model(blob, bytes, &w, &b)) return fail(c, LGF_E_INVALID_ARG, "malformed model blob");
+    if (!parse_model(blob, bytes, &w, &b)) return fail(c, LGF_E_MODEL, "malformed model blob");
     if (!c->mw) HIPCHK(c, hipMalloc(&c->mw, sizeof(uint16_t) * kModelWeights));
     if (!c->mb) HIPCHK(c, hipMalloc(&c->mb, sizeof(float) * kModelBiases));
     HIPCHK(c, hipMemcpy(c->mw, w, sizeof(uint16_t) * kModelWeights, hipMemcpyHostToDevice));

@@ -268,7 +268,7 @@ size_t lgf_model_bytes(void) { return kBlobBytes; }
 int32_t lgf_mlp_eval(const void* blob, size_t bytes, const float* X, int64_t n, float* Y)
 {
     std::vector<float> w;
-    if (!blob_to_flat(blob, bytes, w)) return fail(nullptr, LGF_E_INVALID_ARG, "malformed model blob");
+    if (!blob_to_flat(blob, bytes, w)) return fail(nullptr, LGF_E_MODEL, "malformed model blob");
     if (!X || !Y || n < 1) return fail(nullptr, LGF_E_INVALID_ARG, "bad arrays");
     MlpRun r;
     HIPCHK(&r, hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
@@ -286,7 +286,7 @@ int32_t lgf_mlp_grad(const void* blob, size_t bytes, const float* X, const float
                      float* grad, double* loss)
 {
     std::vector<float> w;
-    if (!blob_to_flat(blob, bytes, w)) return fail(nullptr, LGF_E_INVALID_ARG, "malformed model blob");
+    if (!blob_to_flat(blob, bytes, w)) return fail(nullptr, LGF_E_MODEL, "malformed model blob");
     if (!X || !Y || !M || !grad || n < 1 || n > kMaxBatch) return fail(nullptr, LGF_E_INVALID_ARG, "bad arrays");
     MlpRun r;
     HIPCHK(&r, hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));

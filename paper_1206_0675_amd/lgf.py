@@ -22,7 +22,7 @@ DEFAULT_LIB = os.path.join(_HERE, "liblgf.so")
 
 OK = 0
 E_INVALID_ARG, E_UNSUPPORTED_SHAPE, E_OUT_OF_MEMORY, E_DEVICE = -1, -2, -3, -4
-E_NOT_UNITARY, E_NONFINITE, E_NOT_CONVERGED, E_STATE = -5, -6, -7, -8
+E_NOT_UNITARY, E_NONFINITE, E_NOT_CONVERGED, E_STATE, E_MODEL = -5, -6, -7, -8, -9
 HOST, DEVICE = 0, 1
 FP64, FP32, MIXED = 0, 1, 2
 STORE18, STORE12 = 18, 12

@@ -107,11 +107,21 @@ def test_create_rejects_params_before_touching_the_device(L, field, value):
 
 
 def test_error_strings(L):
-    for code in range(0, -9, -1):
-        assert L.lgf_strerror(code)
+    for code in range(0, -10, -1):
+        assert L.lgf_strerror(code) != b"unknown status"
     assert L.lgf_strerror(-100) == b"unknown status"
     assert L.lgf_destroy(None) == lgf.OK
     assert L.lgf_kernel_name(0) == b"load" and L.lgf_kernel_name(99) is None
+
+
+def test_malformed_model_rejected_before_touching_the_device(L):
+    import numpy as np
+    n = L.lgf_model_bytes()
+    good_size = bytes(n)                                  # right size, zero header
+    for blob in (good_size, bytes(n - 2), b""):
+        with pytest.raises(lgf.LgfError) as e:
+            lgf.mlp_eval(blob, np.zeros((2, 16)), lib=L)
+        assert e.value.code == lgf.E_MODEL
 
 
 def test_product_path_has_no_fallback(tmp_path):
