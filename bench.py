@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+GEN_WORKERS = 8                     # input generation, before the GPU is touched
+LEARNED_DIMS = (32, 32, 32, 64)
 PAPER_C2070_ITERS_PER_S = 16.35    # 32^4, DP, 12-real, texture, ECC off (Table 3)
 
 
@@ -79,6 +81,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the time-to-theta runs")
+    ap.add_argument("--learned-seeds", type=int, default=4,
+                    help="32^3x64 fields (seeds 3000...) for the learned-vs-plain comparison (0: skip)")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="for hardware counters: a few iterations, then one plain device copy of "
                          "--copy-mib MiB (a kernel of known traffic that scales FETCH_SIZE/WRITE_SIZE); no JSON")
@@ -91,20 +95,31 @@ def main():
               "A multi-GPU layout is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import synth
+
+    # All inputs are generated before anything touches the GPU: the generator's
+    # worker processes are started by fork and exec.
+    dims = tuple(args.dims)
+    V = synth.volume(dims)
+    t = time.time()
+    U = synth.random_links(dims, args.seed, workers=GEN_WORKERS)
+    print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    model_path = os.path.join(ROOT, "paper_1206_0675_amd", "models", "learned_step.bin")
+    learned_fields = []
+    if not (args.pmc_sample or args.no_extras) and args.learned_seeds > 0 and os.path.exists(model_path):
+        t = time.time()
+        learned_fields = [(seed, synth.random_links(LEARNED_DIMS, seed, workers=GEN_WORKERS))
+                          for seed in range(3000, 3000 + args.learned_seeds)]
+        print(f"# generated {len(learned_fields)} fields {LEARNED_DIMS} in {time.time() - t:.1f}s", file=sys.stderr,
+              flush=True)
+
     import torch
 
-    import synth
     from paper_1206_0675_amd import lgf
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     L = lgf.load_library()
-    dims = tuple(args.dims)
-    V = synth.volume(dims)
-    t = time.time()
-    U = synth.random_links(dims, args.seed)
-    print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     R = args.storage
     ab = alg_bytes(V, 8, R)
 
@@ -169,6 +184,34 @@ def main():
             extras[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "iters_fp32": s.iter_fp32,
                              "F": s.F, "theta": s.theta}
 
+    # ---- learned vs plain step: time to theta < 1e-15 on 32^3 x 64 ----------
+    learned = None
+    if learned_fields:
+        with open(model_path, "rb") as fh:
+            blob = fh.read()
+        ld = LEARNED_DIMS
+        runs = []
+        for seed, Ul in learned_fields:
+            rec = {"seed": seed}
+            for label, kw in (("plain", {}), ("learned", {"step": lgf.STEP_LEARNED})):
+                with lgf.Context(ld, lib=L, storage=12, poll_every=8, **kw) as ctx:
+                    if kw:
+                        ctx.set_model(blob)
+                    ctx.load(Ul)
+                    ctx.measure()
+                    torch.cuda.synchronize()
+                    s = ctx.fix()
+                rec[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "fallbacks": s.fallbacks, "F": s.F,
+                              "theta": s.theta}
+            rec["F_diff"] = abs(rec["learned"]["F"] - rec["plain"]["F"])
+            runs.append(rec)
+            print(f"# learned vs plain seed {seed}: {rec['plain']['iters']} -> {rec['learned']['iters']} iterations, "
+                  f"{rec['plain']['seconds']:.4f} -> {rec['learned']['seconds']:.4f} s", file=sys.stderr, flush=True)
+        tp = sum(r["plain"]["seconds"] for r in runs)
+        tl = sum(r["learned"]["seconds"] for r in runs)
+        learned = {"dims": list(ld), "storage": 12, "runs": runs, "plain_seconds": round(tp, 5),
+                   "learned_seconds": round(tl, 5), "speedup": round(tp / tl, 4) if tl > 0 else None}
+
     # ---- CPU baseline: the FP64 oracle on this host -------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -210,6 +253,7 @@ def main():
         "iteration_frac": round(it_bytes * iters_per_s / 1e9 / HBM_PEAK_GBPS, 4),
         "kernels": kernels,
         "time_to_theta": extras,
+        "learned_vs_plain": learned,
         "cpu_baseline": cpu,
         "context": {"paper_c2070_iters_per_s": PAPER_C2070_ITERS_PER_S,
                     "device": torch.cuda.get_device_name(0), "source_digest": source_digest()},

@@ -59,8 +59,9 @@ struct DevState {
     int32_t needs_measure; // Delta, F, theta of the current links are not computed yet
     int32_t switch_pending;// batched mixed runs: FP32 phase finished, rebuild in FP64
     int32_t mixed;         // batched runs: FP32 phase followed by FP64
-    int32_t pad;
+    int32_t skip;          // learned step: candidate accepted, the plain update is skipped
     double trial_F, trial_theta;   // learned step: F, theta of the candidate links
+    int64_t fallbacks;     // learned step: updates that fell back to the plain factors
 };
 
 // plane index handled by this block: consecutive planes stay on one XCD
@@ -470,7 +471,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, C2<T>* U0, C2<T>* U1, 
                                                  const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
                                                  const DevState* __restrict__ st)
 {
-    if (st->done) return;
+    if (st->done || st->skip) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     const int cur = st->cur;
     measure_plane<T, NE, APPLY_G, LMAX>(geo, plane_of_block(blockIdx.x, geo.NQ), cur ? U1 : U0, cur ? U0 : U1, g, D,
@@ -494,7 +495,7 @@ __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict_
                                                C2<T>* __restrict__ G, const C2<T>* __restrict__ twx,
                                                const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
 {
-    if (st->done) return;
+    if (st->done || st->skip) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     gauge_plane<T, NE, ACC_G, LMAX>(geo, plane_of_block(blockIdx.x, geo.NQ), D, g, G, twx, twy,
                                     reinterpret_cast<C2<T>*>(lds_raw));
@@ -505,7 +506,7 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
                                                 DevState* __restrict__ st, double* __restrict__ trace,
                                                 int counts_update)
 {
-    if (st->done) return;
+    if (st->done || st->skip) return;
     __shared__ double red[2 * 256];
     reduce_state(partial, nq, V, st, trace, counts_update, red);
 }
@@ -782,7 +783,7 @@ __global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __r
                                                        const double* __restrict__ ptab, double c0, int accel, Bands bands,
                                                        const double* __restrict__ s, const DevState* __restrict__ st)
 {
-    if (st->done) return;
+    if (st->done || st->skip) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -870,22 +871,41 @@ __global__ void __launch_bounds__(64) k_bands_mlp(const double* __restrict__ ban
     }
 }
 
-// Learned step accepted: the candidate links become current.
+// Learned step, decided on the device: the candidate links (F, theta from
+// the trial reduction) become current if they raise F; otherwise the plain
+// update that follows runs (skip = 0) and the fallback is counted.
 template <int UNUSED = 0>
-__global__ void k_commit_trial(DevState* st)
+__global__ void k_decide_trial(DevState* st, double* trace)
 {
     if (st->done) return;
-    st->iter += 1;
-    st->cur ^= 1;
-    st->F = st->trial_F;
-    st->theta = st->trial_theta;
-    const double th = st->theta;
-    if (!(th == th) || th > 1e300) {
-        st->nonfinite = 1;
-        st->done = 1;
-    } else if (th < st->theta_stop) {
-        st->done = 1;
+    if (st->trial_F > st->F) {
+        st->iter += 1;
+        st->cur ^= 1;
+        st->needs_measure = 0;
+        st->F = st->trial_F;
+        st->theta = st->trial_theta;
+        if (trace) {
+            trace[0] = st->F;
+            trace[1] = st->theta;
+        }
+        const double th = st->theta;
+        if (!(th == th) || th > 1e300) {
+            st->nonfinite = 1;
+            st->done = 1;
+        } else if (th < st->theta_stop || st->iter >= st->max_iter) {
+            st->done = 1;
+        }
+        st->skip = 1;
+    } else {
+        st->fallbacks += 1;
+        st->skip = 0;
     }
+}
+
+template <int UNUSED = 0>
+__global__ void k_clear_skip(DevState* st)
+{
+    st->skip = 0;
 }
 
 }  // namespace lgf

@@ -43,6 +43,10 @@ __global__ void k_state_init(DevState* st, int phase)
     st->needs_measure = 1;
     st->switch_pending = 0;
     st->mixed = 0;
+    st->skip = 0;
+    st->trial_F = 0.0;
+    st->trial_theta = 0.0;
+    st->fallbacks = 0;
 }
 
 __global__ void k_state_phase(DevState* st, int phase)
@@ -85,6 +89,8 @@ struct lgf_context : Runner {
     int lmax = 64;            // longest axis rounded up to 64 or 128 (kernel variant)
     hipStream_t cap_stream = nullptr;          // private stream that graph capture runs on
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // per phase: poll_every updates
+    hipGraphExec_t gexec_learned[2] = {nullptr, nullptr};   // learned updates, per Delta-buffer parity
+    int dpar = 0;                                            // parity of the D <-> D3 swaps
     // learned spectral step (FP64): model, band sums, factors, spare Delta buffers
     bool learned = false;
     bool has_model = false;
@@ -99,7 +105,6 @@ struct lgf_context : Runner {
     C2<double>* D3 = nullptr;     // (x,y)-transformed Delta of the candidate links
     Bands bands{};
     double counts_host[16] = {};
-    int64_t fallbacks = 0;
 };
 
 namespace {
@@ -224,17 +229,22 @@ struct OpUpdate {
 int32_t measure_any(lgf_context* c, double* trace_slot) { return dispatch<OpMeasure>(c, trace_slot); }
 int32_t update_any(lgf_context* c, double* trace_slot) { return dispatch<OpUpdate>(c, trace_slot); }
 
+int32_t learned_update(lgf_context* c, double* trace_slot);
+
+int32_t one_update(lgf_context* c) { return c->learned ? learned_update(c, nullptr) : update_any(c, nullptr); }
+
 // n updates for lgf_fix.  A full chunk of poll_every updates is captured once
 // per precision phase into a graph (the launch arguments never change) and
 // replayed; shorter chunks, profiling runs and no_graph contexts launch
-// kernel by kernel.
+// kernel by kernel.  Learned updates alternate two Delta buffers, so their
+// graphs need an even chunk and are kept per buffer parity.
 int32_t enqueue_chunk(lgf_context* c, int64_t n)
 {
-    if (c->profile || c->p.no_graph || n != c->p.poll_every) {
-        for (int64_t k = 0; k < n; ++k) TRY(update_any(c, nullptr));
+    if (c->profile || c->p.no_graph || n != c->p.poll_every || (c->learned && (n & 1))) {
+        for (int64_t k = 0; k < n; ++k) TRY(one_update(c));
         return LGF_OK;
     }
-    hipGraphExec_t& ex = c->gexec[c->phase];
+    hipGraphExec_t& ex = c->learned ? c->gexec_learned[c->dpar] : c->gexec[c->phase];
     if (!ex) {
         if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         hipStream_t run = c->stream;
@@ -244,7 +254,7 @@ int32_t enqueue_chunk(lgf_context* c, int64_t n)
         if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = fail(c, LGF_E_DEVICE, "hipStreamBeginCapture failed");
         } else {
-            for (int64_t k = 0; k < n && rc == LGF_OK; ++k) rc = update_any(c, nullptr);
+            for (int64_t k = 0; k < n && rc == LGF_OK; ++k) rc = one_update(c);
             const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
             if (rc == LGF_OK && e != hipSuccess) rc = fail(c, LGF_E_DEVICE, "hipStreamEndCapture failed");
         }
@@ -324,7 +334,7 @@ void fill_stats(lgf_context* c, lgf_stats* out, int32_t status, double t0)
     } else {
         out->iter_fp64 = out->iter;
     }
-    out->fallbacks = c->fallbacks;
+    out->fallbacks = c->st_host->fallbacks;
     out->F = c->st_host->F;
     out->theta = c->st_host->theta;
     out->seconds = t0 > 0 ? now_s() - t0 : 0.0;
@@ -423,7 +433,7 @@ int32_t enqueue_bands(lgf_context* c, bool use_model)
 // links into U[1 - cur] and their Delta into D3.  mode 2: a candidate (F and
 // theta recorded as trial values, nothing committed); mode 1: committed.
 template <int NE, int LMAX>
-int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode)
+int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double* trace_slot)
 {
     Bufs<double>& b = c->d;
     const Geo& g = b.geo;
@@ -441,7 +451,7 @@ int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode)
                glds + 2 * c->nth_plane * sizeof(double), g, b.U[0], b.U[1], (const C2<double>*)b.g, c->D3,
                c->partial, twx, twy, (const DevState*)c->st));
     TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
-               (double*)nullptr, mode));
+               trace_slot, mode));
     return LGF_OK;
 }
 
@@ -450,29 +460,28 @@ int32_t bands_any(lgf_context* c, bool use_model)
     return c->lmax > 64 ? enqueue_bands<128>(c, use_model) : enqueue_bands<64>(c, use_model);
 }
 
-int32_t scaled_update_any(lgf_context* c, const double* s, int mode)
+int32_t scaled_update_any(lgf_context* c, const double* s, int mode, double* tr = nullptr)
 {
     const bool big = c->lmax > 64;
-    if (c->NE == 9) return big ? enqueue_scaled_update<9, 128>(c, s, mode) : enqueue_scaled_update<9, 64>(c, s, mode);
-    return big ? enqueue_scaled_update<6, 128>(c, s, mode) : enqueue_scaled_update<6, 64>(c, s, mode);
+    if (c->NE == 9)
+        return big ? enqueue_scaled_update<9, 128>(c, s, mode, tr) : enqueue_scaled_update<9, 64>(c, s, mode, tr);
+    return big ? enqueue_scaled_update<6, 128>(c, s, mode, tr) : enqueue_scaled_update<6, 64>(c, s, mode, tr);
 }
 
 // One learned update (Delta of the current links in D, state current): the
 // network's factors give candidate links; they are kept if F grows,
-// otherwise the plain update is taken.  Leaves Delta of the new links in D.
-int32_t learned_update(lgf_context* c)
+// otherwise the plain update is taken.  The choice is made on the device,
+// so updates can be queued (and captured) back to back.  Leaves Delta of
+// the new links in D.
+int32_t learned_update(lgf_context* c, double* trace_slot)
 {
     TRY(bands_any(c, true));
     TRY(scaled_update_any(c, c->s_dev, 2));
-    TRY(sync_state(c));
-    if (c->st_host->done) return LGF_OK;
-    if (c->st_host->trial_F > c->st_host->F) {
-        TRY(launch(c, K_STATE, k_commit_trial<>, dim3(1), dim3(1), 0, c->st));
-    } else {
-        c->fallbacks += 1;
-        TRY(scaled_update_any(c, c->ones_dev, 1));
-    }
+    TRY(launch(c, K_STATE, k_decide_trial<>, dim3(1), dim3(1), 0, c->st, trace_slot));
+    TRY(scaled_update_any(c, c->ones_dev, 1, trace_slot));
+    TRY(launch(c, K_STATE, k_clear_skip<>, dim3(1), dim3(1), 0, c->st));
     std::swap(c->d.D, c->D3);
+    c->dpar ^= 1;
     return LGF_OK;
 }
 
@@ -701,6 +710,8 @@ int32_t lgf_destroy(lgf_ctx c)
         (void)hipFree(q);
     if (c->st_host) (void)hipHostFree(c->st_host);
     release_events(c);
+    for (auto& ex : c->gexec_learned)
+        if (ex) (void)hipGraphExecDestroy(ex);
     for (auto& ex : c->gexec)
         if (ex) (void)hipGraphExecDestroy(ex);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -772,7 +783,6 @@ int32_t lgf_load_links(lgf_ctx c, const void* links, int32_t where)
     if (rc != LGF_OK) return rc;
     c->phase = c->use64 && !c->use32 ? 1 : 0;
     c->iter_fp32 = 0;
-    c->fallbacks = 0;
     c->loaded = true;
     return LGF_OK;
 }
@@ -892,17 +902,7 @@ int32_t lgf_step(lgf_ctx c, int64_t n, lgf_stats* trace)
     if (c->learned) {
         if (!c->has_model) return fail(c, LGF_E_STATE, "the learned step needs lgf_set_model first");
         TRY(ensure_learned_buffers(c));
-        TRY(sync_state(c));
-        std::vector<double> lt;
-        for (int64_t k = 1; k <= n; ++k) {
-            TRY(learned_update(c));
-            TRY(sync_state(c));
-            lt.push_back(c->st_host->F);
-            lt.push_back(c->st_host->theta);
-        }
-        if (trace)
-            for (int64_t k = 1; k <= n; ++k)
-                HIPCHK(c, hipMemcpy(tr + 2 * k, lt.data() + 2 * (k - 1), 2 * sizeof(double), hipMemcpyHostToDevice));
+        for (int64_t k = 1; k <= n; ++k) TRY(learned_update(c, tr ? tr + 2 * k : nullptr));
     } else {
         for (int64_t k = 1; k <= n; ++k) TRY(update_any(c, tr ? tr + 2 * k : nullptr));
     }
@@ -938,12 +938,8 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
             TRY(ensure_learned_buffers(c));
         }
         while (!c->st_host->done && c->st_host->iter < c->p.max_iter) {
-            if (c->learned) {
-                TRY(learned_update(c));
-            } else {
-                const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
-                TRY(enqueue_chunk(c, chunk));
-            }
+            const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
+            TRY(enqueue_chunk(c, chunk));
             TRY(sync_state(c));
         }
         if (c->st_host->nonfinite) {

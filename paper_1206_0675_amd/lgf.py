@@ -26,7 +26,7 @@ E_NOT_UNITARY, E_NONFINITE, E_NOT_CONVERGED, E_STATE, E_MODEL = -5, -6, -7, -8, 
 HOST, DEVICE = 0, 1
 FP64, FP32, MIXED = 0, 1, 2
 STORE18, STORE12 = 18, 12
-STEP_PLAIN = 0
+STEP_PLAIN, STEP_LEARNED = 0, 1
 ACCEL_NONE, ACCEL_FOURIER = 0, 1
 
 

@@ -1,0 +1,120 @@
+"""Train the learned spectral step on the GPU.
+
+    python -m paper_1206_0675_amd.train_learned [--configs 256] [--out DIR]
+
+1. For each generated field (seeds 2000, 2001, ... of the seeded generator,
+   16^4, plaquette 0.6), run the plain FP64 method; every `--every`
+   iterations until theta < 1e-13, record the band features of Delta and the
+   line-search-optimal log factors (lgf_linesearch_bands, on the GPU).
+2. Train the 16-64-64-16 network on these samples with the library's own
+   forward, backward and Adam kernels (lgf_mlp_train).
+3. Write the model blob and a JSON record of the run.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1206_0675_amd import lgf  # noqa: E402
+
+MODEL_DIR = os.path.join(HERE, "models")
+MODEL_PATH = os.path.join(MODEL_DIR, "learned_step.bin")
+
+
+def band_mask(dims):
+    """Which of the 16 bands hold modes (the definition the library uses)."""
+    L = np.array(dims, dtype=np.float64)
+    axes = [4.0 * np.sin(np.pi * np.arange(int(n)) / n) ** 2 for n in L]
+    p2 = (axes[3][:, None, None, None] + axes[2][None, :, None, None] + axes[1][None, None, :, None]
+          + axes[0][None, None, None, :]).ravel()
+    pmin = min(4.0 * np.sin(np.pi / n) ** 2 for n in L)
+    pmax = sum(a.max() for a in axes)
+    nz = p2[p2 > 0]
+    b = np.clip(np.floor(16.0 * np.log(nz / pmin) / np.log(pmax / pmin)).astype(int), 0, 15)
+    return np.bincount(b, minlength=16) > 0
+
+
+def generate(dims, seeds, workers=8):
+    """The training fields, generated in worker processes.  Call this before
+    anything touches the GPU: the workers are started by fork and exec."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import synth
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(synth.random_links, [dims] * len(seeds), seeds))
+
+
+def collect(dims, fields, every=4, theta_min=1e-13, lib=None, log=print):
+    X, Y = [], []
+    mask = band_mask(dims)
+    for k, U in enumerate(fields):
+        with lgf.Context(dims, lib=lib) as c:
+            c.load(U)
+            it = 0
+            while it < 200:
+                st = c.measure()
+                if st.theta < theta_min:
+                    break
+                if it % every == 0:
+                    x, ls = c.linesearch_bands()
+                    X.append(x)
+                    Y.append(ls)
+                c.step(1)
+                it += 1
+        if log and (k % 16 == 0 or k == len(fields) - 1):
+            log(f"# collected {len(X)} samples from {k + 1} fields")
+    X, Y = np.array(X), np.array(Y)
+    M = np.broadcast_to(mask.astype(np.float64), X.shape).copy()
+    return X, Y, M
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--configs", type=int, default=256)
+    ap.add_argument("--seed0", type=int, default=2000)
+    ap.add_argument("--dims", type=int, nargs=4, default=[16, 16, 16, 16])
+    ap.add_argument("--every", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out", default=MODEL_DIR)
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    dims = tuple(args.dims)
+    fields = generate(dims, list(range(args.seed0, args.seed0 + args.configs)))
+    print(f"# generated {len(fields)} fields in {time.time() - t0:.1f}s", flush=True)
+    L = lgf.load_library()
+    X, Y, M = collect(dims, fields, args.every, lib=L, log=lambda m: print(m, flush=True))
+    t1 = time.time()
+    blob, trace = lgf.mlp_train(X, Y, M, steps=args.steps, batch=args.batch, seed=1, lr=args.lr, lib=L)
+    t2 = time.time()
+    pred = lgf.mlp_eval(blob, X, lib=L)
+    mse = float(np.sum(M * (pred - Y) ** 2) / np.sum(M))
+    base = float(np.sum(M * Y ** 2) / np.sum(M))        # the plain step (all log factors 0)
+    os.makedirs(args.out, exist_ok=True)
+    with open(os.path.join(args.out, "learned_step.bin"), "wb") as f:
+        f.write(blob)
+    rec = {"dims": list(dims), "seeds": [args.seed0, args.seed0 + args.configs - 1], "every": args.every,
+           "samples": int(X.shape[0]), "steps": args.steps, "batch": args.batch, "lr": args.lr,
+           "train_mse": mse, "plain_step_mse": base, "loss_first": float(trace[0]), "loss_last": float(trace[-1]),
+           "collect_seconds": round(t1 - t0, 1), "train_seconds": round(t2 - t1, 2),
+           "mean_target_log_s": Y.mean(axis=0).round(4).tolist()}
+    with open(os.path.join(args.out, "learned_step.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    np.savez_compressed(os.path.join(args.out, "learned_step_samples.npz"), X=X, Y=Y, M=M)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,14 +168,46 @@ def _rotate(links: np.ndarray, g: np.ndarray) -> np.ndarray:
     return out
 
 
-def random_links(dims, seed: int, eps: float = EPS_PLAQ_06, rotate: bool = True) -> np.ndarray:
-    """U_mu(x) = g(x) exp(i eps H_mu(x)) g^dagger(x + mu)  (canonical layout)."""
+def _rotated_slice(args) -> np.ndarray:
+    """Time slice t of g exp(i eps H) g^dag(x + mu): the same arithmetic as
+    _rotate on the whole field, so the result is bitwise the same."""
+    dims, seed, eps, t = args
+    lx, ly, lz, lt = dims
+    slab = lx * ly * lz
+    h = normals(seed, KIND_ALGEBRA, t * slab * 32, slab * 32).reshape(slab * 4, 8)
+    links = algebra_exp(h, eps).reshape(lz, ly, lx, 4, 3, 3)
+    g = haar_su3(seed, slab, start=t * slab).reshape(lz, ly, lx, 3, 3)
+    t1 = (t + 1) % lt
+    g_next = haar_su3(seed, slab, start=t1 * slab).reshape(lz, ly, lx, 3, 3)
+    out = np.empty_like(links)
+    for mu in range(4):
+        gn = g_next if mu == 3 else np.roll(g, -1, axis=2 - mu)
+        out[..., mu, :, :] = g @ links[..., mu, :, :] @ np.conj(np.swapaxes(gn, -1, -2))
+    return out
+
+
+def random_links(dims, seed: int, eps: float = EPS_PLAQ_06, rotate: bool = True, workers: int = 1) -> np.ndarray:
+    """U_mu(x) = g(x) exp(i eps H_mu(x)) g^dagger(x + mu)  (canonical layout).
+
+    workers > 1 generates one time slice per task in that many worker
+    processes (fresh interpreters, numpy only); each slice depends only on the
+    counter streams, so the result is bitwise the same for any worker count.
+    Only call it that way from a process that has not touched a GPU: the
+    workers are started by fork and exec."""
     _check_dims(dims)
     dims = tuple(int(d) for d in dims)
-    links = _algebra_links(dims, seed, eps)
     if not rotate:
-        return links
-    return _rotate(links, _gauge_field(dims, seed))
+        return _algebra_links(dims, seed, eps)
+    if workers <= 1 or volume(dims) < (1 << 16):
+        return _rotate(_algebra_links(dims, seed, eps), _gauge_field(dims, seed))
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    lx, ly, lz, lt = dims
+    out = np.empty((lt, lz, ly, lx, 4, 3, 3), dtype=np.complex128)
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        for t, sl in enumerate(ex.map(_rotated_slice, [(dims, seed, eps, t) for t in range(lt)])):
+            out[t] = sl
+    return out
 
 
 def small_field(dims, seed: int, eps: float = 1e-5) -> np.ndarray:

@@ -23,8 +23,10 @@ sys.path.insert(0, os.path.join(HERE, "emu"))
 
 @pytest.fixture(scope="module")
 def E():
+    """The emulated library; LGF_EMU_ASAN=1 selects the AddressSanitizer build
+    (run the suite with libasan preloaded)."""
     import build_emu
-    return lgf.load_library(build_emu.build())
+    return lgf.load_library(build_emu.build(asan=os.environ.get("LGF_EMU_ASAN") == "1"))
 
 
 CASES = [((4, 4, 4, 4), {}), ((8, 4, 4, 4), {}), ((4, 8, 4, 8), {}), ((4, 4, 16, 4), {}),
@@ -225,6 +227,62 @@ def test_emulated_learned_factors_and_update_match_oracle(E, oracle_lib):
     Uc = omlp.update_with(dims, U, s)
     Uo = Uc if oracle.measure(dims, Uc)[0] > F0 else oracle.step(dims, U, 1)[0]
     assert np.max(np.abs(Ug - Uo)) <= 1e-12
+
+
+def test_emulated_learned_steps_trace_match_oracle(E, oracle_lib):
+    """Three learned updates queued back to back (the accept decision on the
+    device) equal, bitwise, three single updates; those follow the oracle's
+    update and accept rule for the factors the network gave (the network runs
+    in float32, so its factors are compared to the oracle's at 1e-5)."""
+    dims = (4, 8, 4, 4)
+    U = synth.random_links(dims, 14)
+    blob = _rand_blob(15, scale=0.2, b3=0.3)
+    p = omlp.params_from_blob(blob)
+    with lgf.Context(dims, lib=E, step=1) as c:
+        c.set_model(blob)
+        c.load(U)
+        tf, tt = c.step(3, trace=True)
+        Ug = c.store()
+        fb = c.measure().fallbacks
+    S = []
+    with lgf.Context(dims, lib=E, step=1) as c:
+        c.set_model(blob)
+        c.load(U)
+        for _ in range(3):
+            S.append(c.learned_factors()[1])
+            c.step(1)
+        assert np.array_equal(c.store(), Ug)
+    Uo, rejected = U, 0
+    for s in S:
+        F0, _, delta = oracle.measure(dims, Uo)
+        P, cnt = oracle.band_powers(dims, delta)
+        assert np.max(np.abs(s / omlp.factors(p, omlp.features(P, cnt, synth.volume(dims))) - 1)) <= 1e-5
+        Uc = omlp.update_with(dims, Uo, s)
+        if oracle.measure(dims, Uc)[0] > F0:
+            Uo = Uc
+        else:
+            Uo, rejected = oracle.step(dims, Uo, 1)[0], rejected + 1
+    assert np.max(np.abs(Ug - Uo)) <= 1e-12
+    assert fb == rejected
+    Fo, tho, _ = oracle.measure(dims, Uo)
+    assert abs(tf[-1] - Fo) <= 1e-13 and abs(tt[-1] / tho - 1) <= 1e-9
+
+
+@pytest.mark.parametrize("poll", [2])
+def test_emulated_learned_fix_graph_matches_eager(E, poll):
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 16)
+    blob = _rand_blob(17, scale=0.1, b3=0.2)
+    out = []
+    for kw in (dict(poll_every=poll), dict(poll_every=poll, no_graph=1)):
+        with lgf.Context(dims, lib=E, step=1, max_iter=400, theta_stop=1e-6, **kw) as c:
+            c.set_model(blob)
+            c.load(U)
+            c.step(1)                       # odd number of Delta-buffer swaps before the graph
+            st = c.fix()
+            out.append((c.store(), st.iter, st.fallbacks, st.F))
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2] and out[0][3] == out[1][3]
+    assert np.array_equal(out[0][0], out[1][0])
 
 
 def test_emulated_mlp_kernels_match_oracle(E):
