@@ -59,7 +59,8 @@ struct DevState {
     int32_t needs_measure; // Delta, F, theta of the current links are not computed yet
     int32_t switch_pending;// batched mixed runs: FP32 phase finished, rebuild in FP64
     int32_t mixed;         // batched runs: FP32 phase followed by FP64
-    int32_t skip;          // learned step: candidate accepted, the plain update is skipped
+    int32_t skip;          // learned step: candidate accepted; 1 + the real `done` while
+                           // `done` is held at 1 so that the plain update is skipped
     double trial_F, trial_theta;   // learned step: F, theta of the candidate links
     int64_t fallbacks;     // learned step: updates that fell back to the plain factors
 };
@@ -471,7 +472,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, C2<T>* U0, C2<T>* U1, 
                                                  const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
                                                  const DevState* __restrict__ st)
 {
-    if (st->done || st->skip) return;
+    if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     const int cur = st->cur;
     measure_plane<T, NE, APPLY_G, LMAX>(geo, plane_of_block(blockIdx.x, geo.NQ), cur ? U1 : U0, cur ? U0 : U1, g, D,
@@ -495,7 +496,7 @@ __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict_
                                                C2<T>* __restrict__ G, const C2<T>* __restrict__ twx,
                                                const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
 {
-    if (st->done || st->skip) return;
+    if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     gauge_plane<T, NE, ACC_G, LMAX>(geo, plane_of_block(blockIdx.x, geo.NQ), D, g, G, twx, twy,
                                     reinterpret_cast<C2<T>*>(lds_raw));
@@ -506,7 +507,7 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
                                                 DevState* __restrict__ st, double* __restrict__ trace,
                                                 int counts_update)
 {
-    if (st->done || st->skip) return;
+    if (st->done) return;
     __shared__ double red[2 * 256];
     reduce_state(partial, nq, V, st, trace, counts_update, red);
 }
@@ -783,7 +784,7 @@ __global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __r
                                                        const double* __restrict__ ptab, double c0, int accel, Bands bands,
                                                        const double* __restrict__ s, const DevState* __restrict__ st)
 {
-    if (st->done || st->skip) return;
+    if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -873,7 +874,9 @@ __global__ void __launch_bounds__(64) k_bands_mlp(const double* __restrict__ ban
 
 // Learned step, decided on the device: the candidate links (F, theta from
 // the trial reduction) become current if they raise F; otherwise the plain
-// update that follows runs (skip = 0) and the fallback is counted.
+// update that follows runs and the fallback is counted.  An accepted step
+// holds `done` at 1 through the plain update's kernels (which then return at
+// once) and k_end_trial restores the real value kept in `skip`.
 template <int UNUSED = 0>
 __global__ void k_decide_trial(DevState* st, double* trace)
 {
@@ -889,23 +892,27 @@ __global__ void k_decide_trial(DevState* st, double* trace)
             trace[1] = st->theta;
         }
         const double th = st->theta;
+        int fin = 0;
         if (!(th == th) || th > 1e300) {
             st->nonfinite = 1;
-            st->done = 1;
+            fin = 1;
         } else if (th < st->theta_stop || st->iter >= st->max_iter) {
-            st->done = 1;
+            fin = 1;
         }
-        st->skip = 1;
+        st->skip = 1 + fin;
+        st->done = 1;
     } else {
         st->fallbacks += 1;
-        st->skip = 0;
     }
 }
 
 template <int UNUSED = 0>
-__global__ void k_clear_skip(DevState* st)
+__global__ void k_end_trial(DevState* st)
 {
-    st->skip = 0;
+    if (st->skip) {
+        st->done = st->skip - 1;
+        st->skip = 0;
+    }
 }
 
 }  // namespace lgf

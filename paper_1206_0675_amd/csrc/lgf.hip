@@ -479,7 +479,7 @@ int32_t learned_update(lgf_context* c, double* trace_slot)
     TRY(scaled_update_any(c, c->s_dev, 2));
     TRY(launch(c, K_STATE, k_decide_trial<>, dim3(1), dim3(1), 0, c->st, trace_slot));
     TRY(scaled_update_any(c, c->ones_dev, 1, trace_slot));
-    TRY(launch(c, K_STATE, k_clear_skip<>, dim3(1), dim3(1), 0, c->st));
+    TRY(launch(c, K_STATE, k_end_trial<>, dim3(1), dim3(1), 0, c->st));
     std::swap(c->d.D, c->D3);
     c->dpar ^= 1;
     return LGF_OK;

@@ -173,6 +173,13 @@ struct Bufs {
     int tw_off[4] = {0, 0, 0, 0};
 };
 
+// Optional gaps between the component arrays of a field and between the
+// (tile, field) chunks of the Delta layout, so that arrays read at the same
+// offsets do not sit a power of two apart.  Both are 0 (no gap): the padded
+// layout is switched off until a GPU memory fault seen with it is explained.
+constexpr size_t kComponentPadBytes = 0;
+constexpr size_t kChunkPadBytes = 0;
+
 // Geometry; the (z, t) tiles hold W plane positions, W * sizeof(complex)
 // = tile_bytes where the (z, t) block still fits its LDS budget.
 template <typename T>
@@ -194,9 +201,8 @@ Geo make_geo(const int32_t* dims, int tile_bytes = 64)
     while (W > 1 && (size_t)W * g.NQ * sizeof(C2<T>) > kMaxLdsZt) W >>= 1;
     g.W = W;
     g.logW = ilog2(W);
-    // pads: 8 KiB + 256 B between component arrays, 256 B between Delta chunks
-    g.VS = g.V + (int64_t)((8192 + 256) / sizeof(C2<T>));
-    g.DS = (int64_t)g.NQ * W + (int64_t)(256 / sizeof(C2<T>));
+    g.VS = g.V + (int64_t)(kComponentPadBytes / sizeof(C2<T>));
+    g.DS = (int64_t)g.NQ * W + (int64_t)(kChunkPadBytes / sizeof(C2<T>));
     return g;
 }
 
