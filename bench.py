@@ -28,7 +28,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-GEN_WORKERS = 8                     # input generation, before the GPU is touched
 LEARNED_DIMS = (32, 32, 32, 64)
 PAPER_C2070_ITERS_PER_S = 16.35    # 32^4, DP, 12-real, texture, ECC off (Table 3)
 
@@ -87,6 +86,9 @@ def main():
                     help="for hardware counters: a few iterations, then one plain device copy of "
                          "--copy-mib MiB (a kernel of known traffic that scales FETCH_SIZE/WRITE_SIZE); no JSON")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--gen-workers", type=int, default=1,
+                    help="worker processes for input generation (fork + exec); leave at 1 under a profiler, "
+                         "which sets up the GPU before this program starts")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -97,18 +99,18 @@ def main():
 
     import synth
 
-    # All inputs are generated before anything touches the GPU: the generator's
-    # worker processes are started by fork and exec.
+    # All inputs are generated before this program touches the GPU (with
+    # --gen-workers > 1 the generator starts worker processes by fork and exec).
     dims = tuple(args.dims)
     V = synth.volume(dims)
     t = time.time()
-    U = synth.random_links(dims, args.seed, workers=GEN_WORKERS)
+    U = synth.random_links(dims, args.seed, workers=args.gen_workers)
     print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     model_path = os.path.join(ROOT, "paper_1206_0675_amd", "models", "learned_step.bin")
     learned_fields = []
     if not (args.pmc_sample or args.no_extras) and args.learned_seeds > 0 and os.path.exists(model_path):
         t = time.time()
-        learned_fields = [(seed, synth.random_links(LEARNED_DIMS, seed, workers=GEN_WORKERS))
+        learned_fields = [(seed, synth.random_links(LEARNED_DIMS, seed, workers=args.gen_workers))
                           for seed in range(3000, 3000 + args.learned_seeds)]
         print(f"# generated {len(learned_fields)} fields {LEARNED_DIMS} in {time.time() - t:.1f}s", file=sys.stderr,
               flush=True)
