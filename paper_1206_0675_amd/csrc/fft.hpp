@@ -59,7 +59,9 @@ __device__ __forceinline__ C2<T> twiddle_const(C2<T> v)
         const T c = (T)cos_pi8(i);
         const T s = (T)cos_pi8(i <= 4 ? 4 - i : i - 4);   // sin(i pi / 8)
         const T sn = INV ? s : -s;
-        return mk<T>(v.x * c - v.y * sn, v.x * sn + v.y * c);
+        // explicit fused multiply-adds: the same bits in every kernel that
+        // inlines this (the compiler may not contract them differently)
+        return mk<T>(fma(-v.y, sn, v.x * c), fma(v.y, c, v.x * sn));
     }
 }
 

@@ -15,7 +15,7 @@ SRCS = [os.path.join(ROOT, "paper_1206_0675_amd", "csrc", f) for f in ("lgf.hip"
 
 def build(asan: bool = False) -> str:
     out = os.path.join(HERE, "liblgf_emu_asan.so" if asan else "liblgf_emu.so")
-    cmd = ["g++", "-std=gnu++20", "-x", "c++", "-O1", "-g", "-fPIC", "-shared", "-pthread",
+    cmd = ["g++", "-std=gnu++20", "-x", "c++", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-mfma", "-ffp-contract=off",
            "-I" + os.path.join(HERE, "include"), "-I" + os.path.join(ROOT, "include"),
            "-I" + os.path.join(ROOT, "paper_1206_0675_amd", "csrc")] + SRCS + ["-o", out + ".tmp"]
     if asan:
