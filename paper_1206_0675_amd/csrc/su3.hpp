@@ -19,10 +19,21 @@ struct alignas(2 * sizeof(T)) C2 {
 
 template <typename T>
 __host__ __device__ __forceinline__ C2<T> mk(T a, T b) { C2<T> r; r.x = a; r.y = b; return r; }
+// Sums, differences and real scalings are never fused with a neighbouring
+// product (no contraction inside them), so a value rounds the same way whether
+// it is kept in registers or stored and read back between two kernels.
 template <typename T>
-__device__ __forceinline__ C2<T> operator+(C2<T> a, C2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ C2<T> operator+(C2<T> a, C2<T> b)
+{
+#pragma clang fp contract(off)
+    return mk<T>(a.x + b.x, a.y + b.y);
+}
 template <typename T>
-__device__ __forceinline__ C2<T> operator-(C2<T> a, C2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ C2<T> operator-(C2<T> a, C2<T> b)
+{
+#pragma clang fp contract(off)
+    return mk<T>(a.x - b.x, a.y - b.y);
+}
 // Complex products with explicit fused multiply-adds in a fixed order, so
 // the same product gives the same bits wherever it is evaluated (the
 // compiler may not re-contract them).
@@ -52,7 +63,11 @@ __device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) { return cfmac(a, b, mk
 template <typename T>
 __device__ __forceinline__ C2<T> conjg(C2<T> a) { return mk<T>(a.x, -a.y); }
 template <typename T>
-__device__ __forceinline__ C2<T> scale(C2<T> a, T f) { return mk<T>(a.x * f, a.y * f); }
+__device__ __forceinline__ C2<T> scale(C2<T> a, T f)
+{
+#pragma clang fp contract(off)
+    return mk<T>(a.x * f, a.y * f);
+}
 // i * a and -i * a
 template <typename T>
 __device__ __forceinline__ C2<T> mul_i(C2<T> a) { return mk<T>(-a.y, a.x); }

@@ -48,7 +48,7 @@ def oracle_learned(dims, U, s):
 
 
 def test_zero_model_is_plain(L):
-    dims = (8, 8, 8, 8)
+    dims = (8, 8, 4, 8)
     announce(f"zero model dims={dims}")
     U = synth.random_links(dims, 7)
     zero = omlp.blob_from_params({k: np.zeros(s) for k, s in omlp.SHAPES})
