@@ -485,13 +485,13 @@ int32_t learned_update(lgf_context* c, double* trace_slot)
     return LGF_OK;
 }
 
-// F after one update with factors s, the links kept as they are.
-int32_t trial_F(lgf_context* c, const std::vector<double>& s, double* F)
+// theta after one update with factors s, the links kept as they are.
+int32_t trial_theta(lgf_context* c, const std::vector<double>& s, double* theta)
 {
     HIPCHK(c, hipMemcpyAsync(c->s_dev, s.data(), sizeof(double) * 16, hipMemcpyHostToDevice, c->stream));
     TRY(scaled_update_any(c, c->s_dev, 2));
     TRY(sync_state(c));
-    *F = c->st_host->trial_F;
+    *theta = c->st_host->trial_theta;
     return LGF_OK;
 }
 
@@ -1006,21 +1006,21 @@ int32_t lgf_linesearch_bands(lgf_ctx c, double features[16], double log_s[16])
     c->delta_valid = false;          // D now holds the full spectrum
     std::vector<double> s(16, 1.0);
     double best = 0.0;
-    TRY(trial_F(c, s, &best));
+    TRY(trial_theta(c, s, &best));
     const double lo = -2.3, hi = 2.3, gr = 0.5 * (std::sqrt(5.0) - 1.0);
     for (int sweep = 0; sweep < 2; ++sweep)
         for (int band = 0; band < 16; ++band) {
             if (c->counts_host[band] == 0.0) continue;
-            auto eval = [&](double u, double* F) {
+            auto eval = [&](double u, double* th) {
                 std::vector<double> t = s;
                 t[band] = std::exp(u);
-                return trial_F(c, t, F);
+                return trial_theta(c, t, th);
             };
             double a = lo, b = hi, x1 = b - gr * (b - a), x2 = a + gr * (b - a), f1, f2;
             TRY(eval(x1, &f1));
             TRY(eval(x2, &f2));
             for (int it = 0; it < 12; ++it) {
-                if (f1 > f2) {
+                if (f1 < f2) {
                     b = x2;
                     x2 = x1;
                     f2 = f1;
@@ -1034,8 +1034,8 @@ int32_t lgf_linesearch_bands(lgf_ctx c, double features[16], double log_s[16])
                     TRY(eval(x2, &f2));
                 }
             }
-            const double u = f1 > f2 ? x1 : x2, fu = f1 > f2 ? f1 : f2;
-            if (fu > best) {
+            const double u = f1 < f2 ? x1 : x2, fu = f1 < f2 ? f1 : f2;
+            if (fu < best) {
                 best = fu;
                 s[band] = std::exp(u);
             }

@@ -4,8 +4,9 @@
 
 1. For each generated field (seeds 2000, 2001, ... of the seeded generator,
    16^4, plaquette 0.6), run the plain FP64 method; every `--every`
-   iterations until theta < 1e-13, record the band features of Delta and the
-   line-search-optimal log factors (lgf_linesearch_bands, on the GPU).
+   iterations until theta < 1e-14, record the band features of Delta and the
+   log factors that minimise theta after one update (lgf_linesearch_bands, a
+   golden-section search on the GPU).
 2. Train the 16-64-64-16 network on these samples with the library's own
    forward, backward and Adam kernels (lgf_mlp_train).
 3. Write the model blob and a JSON record of the run.
@@ -55,7 +56,7 @@ def generate(dims, seeds, workers=8):
         return list(ex.map(synth.random_links, [dims] * len(seeds), seeds))
 
 
-def collect(dims, fields, every=4, theta_min=1e-13, lib=None, log=print):
+def collect(dims, fields, every=3, theta_min=1e-14, lib=None, log=print):
     X, Y = [], []
     mask = band_mask(dims)
     for k, U in enumerate(fields):
@@ -84,7 +85,7 @@ def main(argv=None):
     ap.add_argument("--configs", type=int, default=256)
     ap.add_argument("--seed0", type=int, default=2000)
     ap.add_argument("--dims", type=int, nargs=4, default=[16, 16, 16, 16])
-    ap.add_argument("--every", type=int, default=4)
+    ap.add_argument("--every", type=int, default=3)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)

@@ -321,5 +321,8 @@ def test_emulated_linesearch_matches_oracle(E, oracle_lib):
         assert np.array_equal(c.store(), U)          # the links are not changed
     xo, lso, best = omlp.linesearch(dims, U)
     assert np.max(np.abs(x - xo)) <= 1e-12
-    Fg = oracle.measure(dims, omlp.update_with(dims, U, np.exp(ls)))[0]
-    assert abs(Fg - best) <= 1e-10
+    # both searches end in the same minimum of theta (they may split at
+    # near-ties, so compare theta at the chosen factors, not the factors)
+    thg = oracle.measure(dims, omlp.update_with(dims, U, np.exp(ls)))[1]
+    assert abs(thg / best - 1) <= 1e-6
+    assert thg < oracle.measure(dims, oracle.step(dims, U, 1)[0])[1]

@@ -127,8 +127,11 @@ def test_linesearch(L):
         assert np.array_equal(c.store(), U)
     xo, lso, best = omlp.linesearch(dims, U)
     assert np.max(np.abs(x - xo)) <= 1e-12
-    Fg = oracle.measure(dims, omlp.update_with(dims, U, np.exp(ls)))[0]
-    assert abs(Fg - best) <= 1e-10
+    # both searches end in the same minimum of theta (they may split at
+    # near-ties, so compare theta at the chosen factors, not the factors)
+    thg = oracle.measure(dims, omlp.update_with(dims, U, np.exp(ls)))[1]
+    assert abs(thg / best - 1) <= 1e-6
+    assert thg < oracle.measure(dims, oracle.step(dims, U, 1)[0])[1]
 
 
 def test_mlp_kernels(L):
