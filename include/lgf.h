@@ -222,10 +222,11 @@ int32_t lgf_set_model(lgf_ctx ctx, const void *blob, size_t bytes);
 int32_t lgf_learned_factors(lgf_ctx ctx, double features[16], double s[16]);
 
 /* Training data at the current links of an FP64 context: the band features
- * x and the log factors ln s* that minimise theta after one update, found by
- * two sweeps of golden-section search (12 shrink steps) on each ln s_b in
- * [-2.3, 2.3], bands in order, the other factors held; a band keeps a new
- * value only if it lowered the best theta so far.  The links are not changed. */
+ * x and the log factor ln s* of the one factor, common to all bands, that
+ * minimises theta after one update (golden-section search, 20 shrink steps,
+ * on ln s in [-2.3, 2.3]; s* = 1 unless it beats the plain step).  log_s
+ * holds ln s* for every band that holds modes and 0 for empty bands.  The
+ * links are not changed. */
 int32_t lgf_linesearch_bands(lgf_ctx ctx, double features[16], double log_s[16]);
 
 typedef struct lgf_train_params {

@@ -20,11 +20,14 @@ biases in float32; this reference evaluates the network in float64 on those
 exact values.  An update with factors s is accepted only if it increases F;
 otherwise the plain update (s = 1) is taken.
 
-Training targets are the log factors minimising theta after one update (theta
-is what the stop test reads, and it stays resolvable down to 1e-15, where the
-gain in F is lost in rounding), found by coordinate-wise golden-section search
-on ln s_b in [-2.3, 2.3]; the loss is the masked mean squared error over the
-bands that hold modes.  The accept rule (F must grow) is unchanged.
+Training targets: the one factor s, common to all bands, that minimises theta
+after one update (theta is what the stop test reads, and it stays resolvable
+down to 1e-15, where the gain in F is lost in rounding), found by
+golden-section search on ln s in [-2.3, 2.3] and kept only if it beats the
+plain step; it is the target of every band that holds modes.  (Choosing each
+band's factor greedily starves the slow low-momentum bands and lengthens the
+run.)  The loss is the masked mean squared error over the bands that hold
+modes.  The accept rule (F must grow) is unchanged.
 """
 from __future__ import annotations
 
@@ -160,44 +163,36 @@ def learned_step(dims, U, p: dict, alpha=0.08):
     return update_with(dims, U, None, alpha), False, s, x
 
 
-def linesearch(dims, U, alpha=0.08, sweeps=2, iters=12):
-    """Log factors minimising theta after one update: coordinate-wise
-    golden-section search on ln s_b in [-2.3, 2.3], bands in order, the others
-    held; a band's value changes only if the search beat the best theta so far.
-    Returns (features, log s, best theta)."""
+def linesearch(dims, U, alpha=0.08, iters=20):
+    """Log factors minimising theta after one update with one factor s for all
+    bands: golden-section search on ln s in [-2.3, 2.3]; s = 1 unless the
+    search beat the plain step.  Returns (features, log s per band: ln s for
+    every band that holds modes and 0 for empty ones, best theta)."""
     V = int(np.prod(dims))
     _, _, delta = lgfo.measure(dims, U)
     P, cnt = lgfo.band_powers(dims, delta)
     x = features(P, cnt, V)
-    s = np.ones(NB)
 
-    def theta_of(t):
-        return lgfo.measure(dims, update_with(dims, U, t, alpha))[1]
+    def f(u):
+        return lgfo.measure(dims, update_with(dims, U, np.full(NB, np.exp(u)), alpha))[1]
 
-    best = theta_of(s)
+    best = lgfo.measure(dims, update_with(dims, U, np.ones(NB), alpha))[1]
     g = 0.5 * (np.sqrt(5.0) - 1.0)
-    for _ in range(sweeps):
-        for b in range(NB):
-            if cnt[b] == 0:
-                continue
-
-            def f(u):
-                t = s.copy()
-                t[b] = np.exp(u)
-                return theta_of(t)
-            lo, hi = -CLIP, CLIP
-            u1, u2 = hi - g * (hi - lo), lo + g * (hi - lo)
-            f1, f2 = f(u1), f(u2)
-            for _ in range(iters):
-                if f1 < f2:
-                    hi, u2, f2 = u2, u1, f1
-                    u1 = hi - g * (hi - lo)
-                    f1 = f(u1)
-                else:
-                    lo, u1, f1 = u1, u2, f2
-                    u2 = lo + g * (hi - lo)
-                    f2 = f(u2)
-            u, fu = (u1, f1) if f1 < f2 else (u2, f2)
-            if fu < best:
-                best, s[b] = fu, np.exp(u)
-    return x, np.log(s), best
+    lo, hi = -CLIP, CLIP
+    u1, u2 = hi - g * (hi - lo), lo + g * (hi - lo)
+    f1, f2 = f(u1), f(u2)
+    for _ in range(iters):
+        if f1 < f2:
+            hi, u2, f2 = u2, u1, f1
+            u1 = hi - g * (hi - lo)
+            f1 = f(u1)
+        else:
+            lo, u1, f1 = u1, u2, f2
+            u2 = lo + g * (hi - lo)
+            f2 = f(u2)
+    u, fu = (u1, f1) if f1 < f2 else (u2, f2)
+    ls = np.zeros(NB)
+    if fu < best:
+        best = fu
+        ls[np.asarray(cnt) > 0] = u
+    return x, ls, best

@@ -1004,43 +1004,31 @@ int32_t lgf_linesearch_bands(lgf_ctx c, double features[16], double log_s[16])
     HIPCHK(c, hipMemcpyAsync(features, c->x_dev, sizeof(double) * 16, hipMemcpyDeviceToHost, c->stream));
     TRY(sync_state(c));
     c->delta_valid = false;          // D now holds the full spectrum
-    std::vector<double> s(16, 1.0);
+    // one factor for all bands: golden-section search on ln s in [-2.3, 2.3]
     double best = 0.0;
-    TRY(trial_theta(c, s, &best));
-    const double lo = -2.3, hi = 2.3, gr = 0.5 * (std::sqrt(5.0) - 1.0);
-    for (int sweep = 0; sweep < 2; ++sweep)
-        for (int band = 0; band < 16; ++band) {
-            if (c->counts_host[band] == 0.0) continue;
-            auto eval = [&](double u, double* th) {
-                std::vector<double> t = s;
-                t[band] = std::exp(u);
-                return trial_theta(c, t, th);
-            };
-            double a = lo, b = hi, x1 = b - gr * (b - a), x2 = a + gr * (b - a), f1, f2;
+    TRY(trial_theta(c, std::vector<double>(16, 1.0), &best));
+    auto eval = [&](double u, double* th) { return trial_theta(c, std::vector<double>(16, std::exp(u)), th); };
+    const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    double a = -2.3, b = 2.3, x1 = b - gr * (b - a), x2 = a + gr * (b - a), f1, f2;
+    TRY(eval(x1, &f1));
+    TRY(eval(x2, &f2));
+    for (int it = 0; it < 20; ++it) {
+        if (f1 < f2) {
+            b = x2;
+            x2 = x1;
+            f2 = f1;
+            x1 = b - gr * (b - a);
             TRY(eval(x1, &f1));
+        } else {
+            a = x1;
+            x1 = x2;
+            f1 = f2;
+            x2 = a + gr * (b - a);
             TRY(eval(x2, &f2));
-            for (int it = 0; it < 12; ++it) {
-                if (f1 < f2) {
-                    b = x2;
-                    x2 = x1;
-                    f2 = f1;
-                    x1 = b - gr * (b - a);
-                    TRY(eval(x1, &f1));
-                } else {
-                    a = x1;
-                    x1 = x2;
-                    f1 = f2;
-                    x2 = a + gr * (b - a);
-                    TRY(eval(x2, &f2));
-                }
-            }
-            const double u = f1 < f2 ? x1 : x2, fu = f1 < f2 ? f1 : f2;
-            if (fu < best) {
-                best = fu;
-                s[band] = std::exp(u);
-            }
         }
-    for (int b = 0; b < 16; ++b) log_s[b] = std::log(s[b]);
+    }
+    const double u = f1 < f2 ? x1 : x2, fu = f1 < f2 ? f1 : f2;
+    for (int k = 0; k < 16; ++k) log_s[k] = (fu < best && c->counts_host[k] > 0.0) ? u : 0.0;
     return LGF_OK;
 }
 
