@@ -59,8 +59,8 @@ struct DevState {
     int32_t needs_measure; // Delta, F, theta of the current links are not computed yet
     int32_t switch_pending;// batched mixed runs: FP32 phase finished, rebuild in FP64
     int32_t mixed;         // batched runs: FP32 phase followed by FP64
-    int32_t skip;          // learned step: candidate accepted; 1 + the real `done` while
-                           // `done` is held at 1 so that the plain update is skipped
+    int32_t fallback;      // learned step: candidate rejected; `done` is held at 1 until
+                           // the host has run the plain update
     double trial_F, trial_theta;   // learned step: F, theta of the candidate links
     int64_t fallbacks;     // learned step: updates that fell back to the plain factors
 };
@@ -713,24 +713,16 @@ __global__ void kb_switch_done(const BatchCfg<double>* __restrict__ c64, int ncf
 // ===========================================================================
 // Band of a mode from its p^2: 16 bands log-spaced between the smallest
 // nonzero p^2 of the lattice (pmin) and p2max; -1 for the zero mode.
-struct Bands {
-    double pmin;        // smallest nonzero p^2
-    double log_range;   // log(p2max / pmin)
-    __device__ __forceinline__ int of(double p2) const
-    {
-        if (!(p2 > 0.0)) return -1;
-        int b = (int)floor(16.0 * log(p2 / pmin) / log_range);
-        return b < 0 ? 0 : (b > 15 ? 15 : b);
-    }
-};
 
-// Forward (z, t) transform of one tile, in place, and this block's band sums
-// of sum_c |Dhat_c(p)|^2 (per-thread accumulation, then a fixed-order tree
-// in LDS: the launch gives at least 16 * blockDim doubles of LDS).
+// Forward (z, t) transform of one tile from Din into Dspec (Din keeps Delta)
+// and this block's band sums of sum_c |Dhat_c(p)|^2: per-thread accumulation,
+// then a fixed-order tree in LDS (the launch gives at least 16 * blockDim
+// doubles of LDS).  btab: the band of every spectrum position, laid out like
+// one field of a Delta chunk (-1 for the zero mode).
 template <typename T, int LMAX>
-__global__ void __launch_bounds__(512) k_zt_fwd_bands(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
-                                                      const C2<T>* __restrict__ twt, const double* __restrict__ ptab,
-                                                      Bands bands, double* __restrict__ band_partial,
+__global__ void __launch_bounds__(512) k_zt_fwd_bands(Geo geo, const C2<T>* __restrict__ Din, C2<T>* __restrict__ Dspec,
+                                                      const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt,
+                                                      const int8_t* __restrict__ btab, double* __restrict__ band_partial,
                                                       const DevState* __restrict__ st)
 {
     if (st->done) return;
@@ -739,25 +731,22 @@ __global__ void __launch_bounds__(512) k_zt_fwd_bands(Geo geo, C2<T>* __restrict
     const int tid = threadIdx.x, nth = blockDim.x;
     const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
     const int W = geo.W, NQ = geo.NQ, n = NQ * W, Lz = geo.L[2];
-    C2<T>* src = D + (int64_t)(j * 4 + c) * geo.DS;
+    const C2<T>* src = Din + (int64_t)(j * 4 + c) * geo.DS;
+    C2<T>* dst = Dspec + (int64_t)(j * 4 + c) * geo.DS;
+    const int8_t* bt = btab + (int64_t)j * n;
     for (int i = tid; i < n; i += nth) buf[i] = src[i];
     __syncthreads();
     const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
     const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
     fft_fwd<T, LMAX>(buf, Lz, zl, twz, tid, nth);
     fft_fwd<T, LMAX>(buf, geo.L[3], tl, twt, tid, nth);
-    const SpectralScale sc = make_scale(geo, ptab, 0.0, 1);
     double acc[16];
 #pragma unroll
     for (int b = 0; b < 16; ++b) acc[b] = 0.0;
     for (int i = tid; i < n; i += nth) {
         const C2<T> v = buf[i];
-        src[i] = v;
-        const int w = i & (W - 1), qq = i >> geo.logW;
-        const int pxy = j * W + w;
-        const double p2 = sc.tx[pxy & (geo.L[0] - 1)] + sc.ty[pxy >> geo.logL[0]] + sc.tz[qq & (Lz - 1)] +
-                          sc.tt[qq >> geo.logL[2]];
-        const int b = bands.of(p2);
+        dst[i] = v;
+        const int b = bt[i];
         const double pw = (double)v.x * v.x + (double)v.y * v.y;
 #pragma unroll
         for (int k = 0; k < 16; ++k) acc[k] += (k == b) ? pw : 0.0;
@@ -777,12 +766,13 @@ __global__ void __launch_bounds__(512) k_zt_fwd_bands(Geo geo, C2<T>* __restrict
 }
 
 // Scale by s_b * (alpha/2) p2max / (p^2 V) and inverse (z, t) transform of
-// one tile, from Din (the full 4D spectrum, kept) into Dout.
+// one tile, from Dspec (the full 4D spectrum, kept) into Dout.
 template <typename T, int LMAX>
-__global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __restrict__ Din, C2<T>* __restrict__ Dout,
+__global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __restrict__ Dspec, C2<T>* __restrict__ Dout,
                                                        const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt,
-                                                       const double* __restrict__ ptab, double c0, int accel, Bands bands,
-                                                       const double* __restrict__ s, const DevState* __restrict__ st)
+                                                       const double* __restrict__ ptab, double c0, int accel,
+                                                       const int8_t* __restrict__ btab, const double* __restrict__ s,
+                                                       const DevState* __restrict__ st)
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
@@ -790,14 +780,15 @@ __global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __r
     const int tid = threadIdx.x, nth = blockDim.x;
     const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
     const int W = geo.W, NQ = geo.NQ, n = NQ * W, Lz = geo.L[2];
-    const C2<T>* src = Din + (int64_t)(j * 4 + c) * geo.DS;
+    const C2<T>* src = Dspec + (int64_t)(j * 4 + c) * geo.DS;
+    const int8_t* bt = btab + (int64_t)j * n;
     const SpectralScale sc = make_scale(geo, ptab, c0, accel);
     for (int i = tid; i < n; i += nth) {
         const int w = i & (W - 1), qq = i >> geo.logW;
         const int pxy = j * W + w;
         const double base = sc.tx[pxy & (geo.L[0] - 1)] + sc.ty[pxy >> geo.logL[0]] + sc.tz[qq & (Lz - 1)];
         const double p2 = base + sc.tt[qq >> geo.logL[2]];
-        const int b = bands.of(p2);
+        const int b = bt[i];
         const double sb = b < 0 ? 1.0 : s[b];
         buf[i] = scale(src[i], (T)(sb * sc.factor(p2)));
     }
@@ -830,19 +821,32 @@ struct MlpDev {
 };
 
 // Band powers -> features -> factors s_b = exp(clip(y_b, -2.3, 2.3)).  One
-// block of 64 threads.  Empty bands (count 0) get feature 0.
+// block of 256 threads: the per-block band sums are added in 16 interleaved
+// slices and a fixed-order tree (deterministic), then the network runs on the
+// first 64 threads.  Empty bands (count 0) get feature 0.
 template <int UNUSED = 0>
-__global__ void __launch_bounds__(64) k_bands_mlp(const double* __restrict__ band_partial, int nblk,
-                                                  const double* __restrict__ count16, int64_t V, MlpDev net,
-                                                  double* __restrict__ s_out, double* __restrict__ x_out,
-                                                  const DevState* __restrict__ st)
+__global__ void __launch_bounds__(256) k_bands_mlp(const double* __restrict__ band_partial, int nblk,
+                                                   const double* __restrict__ count16, int64_t V, MlpDev net,
+                                                   double* __restrict__ s_out, double* __restrict__ x_out,
+                                                   const DevState* __restrict__ st)
 {
     if (st->done) return;
+    __shared__ double psum[16 * 16];
     __shared__ float x[16], h1[64], h2[64];
     const int tid = threadIdx.x;
-    if (tid < 16) {
+    {
+        const int band = tid & 15, slice = tid >> 4;
         double p = 0.0;
-        for (int i = 0; i < nblk; ++i) p += band_partial[(int64_t)i * 16 + tid];
+        for (int i = slice; i < nblk; i += 16) p += band_partial[(int64_t)i * 16 + band];
+        psum[slice * 16 + band] = p;
+    }
+    __syncthreads();
+    for (int h = 8; h > 0; h >>= 1) {
+        if ((tid >> 4) < h) psum[tid] += psum[tid + 16 * h];
+        __syncthreads();
+    }
+    if (tid < 16) {
+        const double p = psum[tid];
         double f = 0.0;
         if (count16[tid] > 0.0) {
             const double pv = p / count16[tid] / (double)V;
@@ -856,16 +860,20 @@ __global__ void __launch_bounds__(64) k_bands_mlp(const double* __restrict__ ban
         if (tid < 16) s_out[tid] = 1.0;
         return;
     }
-    float a = net.b1[tid];
-    for (int i = 0; i < 16; ++i) a = fmaf(x[i], bf16_to_float(net.W1[i * 64 + tid]), a);
-    h1[tid] = a > 0.f ? a : 0.f;
+    if (tid < 64) {
+        float a = net.b1[tid];
+        for (int i = 0; i < 16; ++i) a = fmaf(x[i], bf16_to_float(net.W1[i * 64 + tid]), a);
+        h1[tid] = a > 0.f ? a : 0.f;
+    }
     __syncthreads();
-    a = net.b2[tid];
-    for (int i = 0; i < 64; ++i) a = fmaf(h1[i], bf16_to_float(net.W2[i * 64 + tid]), a);
-    h2[tid] = a > 0.f ? a : 0.f;
+    if (tid < 64) {
+        float a = net.b2[tid];
+        for (int i = 0; i < 64; ++i) a = fmaf(h1[i], bf16_to_float(net.W2[i * 64 + tid]), a);
+        h2[tid] = a > 0.f ? a : 0.f;
+    }
     __syncthreads();
     if (tid < 16) {
-        a = net.b3[tid];
+        float a = net.b3[tid];
         for (int i = 0; i < 64; ++i) a = fmaf(h2[i], bf16_to_float(net.W3[i * 16 + tid]), a);
         const double y = fmin(fmax((double)a, -2.3), 2.3);
         s_out[tid] = exp(y);
@@ -873,10 +881,9 @@ __global__ void __launch_bounds__(64) k_bands_mlp(const double* __restrict__ ban
 }
 
 // Learned step, decided on the device: the candidate links (F, theta from
-// the trial reduction) become current if they raise F; otherwise the plain
-// update that follows runs and the fallback is counted.  An accepted step
-// holds `done` at 1 through the plain update's kernels (which then return at
-// once) and k_end_trial restores the real value kept in `skip`.
+// the trial reduction) become current if they raise F.  Otherwise `fallback`
+// is raised and `done` held at 1, so the rest of a queued chunk does nothing,
+// until the host has run the plain update (k_fallback_begin first).
 template <int UNUSED = 0>
 __global__ void k_decide_trial(DevState* st, double* trace)
 {
@@ -892,26 +899,25 @@ __global__ void k_decide_trial(DevState* st, double* trace)
             trace[1] = st->theta;
         }
         const double th = st->theta;
-        int fin = 0;
         if (!(th == th) || th > 1e300) {
             st->nonfinite = 1;
-            fin = 1;
+            st->done = 1;
         } else if (th < st->theta_stop || st->iter >= st->max_iter) {
-            fin = 1;
+            st->done = 1;
         }
-        st->skip = 1 + fin;
-        st->done = 1;
     } else {
-        st->fallbacks += 1;
+        st->fallback = 1;
+        st->done = 1;
     }
 }
 
 template <int UNUSED = 0>
-__global__ void k_end_trial(DevState* st)
+__global__ void k_fallback_begin(DevState* st)
 {
-    if (st->skip) {
-        st->done = st->skip - 1;
-        st->skip = 0;
+    if (st->fallback) {
+        st->fallback = 0;
+        st->done = 0;
+        st->fallbacks += 1;
     }
 }
 

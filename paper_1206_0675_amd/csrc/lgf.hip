@@ -43,7 +43,7 @@ __global__ void k_state_init(DevState* st, int phase)
     st->needs_measure = 1;
     st->switch_pending = 0;
     st->mixed = 0;
-    st->skip = 0;
+    st->fallback = 0;
     st->trial_F = 0.0;
     st->trial_theta = 0.0;
     st->fallbacks = 0;
@@ -89,8 +89,7 @@ struct lgf_context : Runner {
     int lmax = 64;            // longest axis rounded up to 64 or 128 (kernel variant)
     hipStream_t cap_stream = nullptr;          // private stream that graph capture runs on
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // per phase: poll_every updates
-    hipGraphExec_t gexec_learned[2] = {nullptr, nullptr};   // learned updates, per Delta-buffer parity
-    int dpar = 0;                                            // parity of the D <-> D3 swaps
+    hipGraphExec_t gexec_learned = nullptr;                  // poll_every learned updates
     // learned spectral step (FP64): model, band sums, factors, spare Delta buffers
     bool learned = false;
     bool has_model = false;
@@ -101,9 +100,9 @@ struct lgf_context : Runner {
     double* s_dev = nullptr;
     double* x_dev = nullptr;
     double* ones_dev = nullptr;
-    C2<double>* D2 = nullptr;     // scaled + inverse-(z,t) spectrum of a candidate step
-    C2<double>* D3 = nullptr;     // (x,y)-transformed Delta of the candidate links
-    Bands bands{};
+    C2<double>* D2 = nullptr;     // the (x,y,z,t) spectrum of Delta of the current links
+    C2<double>* D3 = nullptr;     // scaled, inverse-(z,t) spectrum of a step (input of k_gauge)
+    int8_t* btab = nullptr;       // band of every spectrum position (D2 chunk layout)
     double counts_host[16] = {};
 };
 
@@ -236,15 +235,14 @@ int32_t one_update(lgf_context* c) { return c->learned ? learned_update(c, nullp
 // n updates for lgf_fix.  A full chunk of poll_every updates is captured once
 // per precision phase into a graph (the launch arguments never change) and
 // replayed; shorter chunks, profiling runs and no_graph contexts launch
-// kernel by kernel.  Learned updates alternate two Delta buffers, so their
-// graphs need an even chunk and are kept per buffer parity.
+// kernel by kernel.
 int32_t enqueue_chunk(lgf_context* c, int64_t n)
 {
-    if (c->profile || c->p.no_graph || n != c->p.poll_every || (c->learned && (n & 1))) {
+    if (c->profile || c->p.no_graph || n != c->p.poll_every) {
         for (int64_t k = 0; k < n; ++k) TRY(one_update(c));
         return LGF_OK;
     }
-    hipGraphExec_t& ex = c->learned ? c->gexec_learned[c->dpar] : c->gexec[c->phase];
+    hipGraphExec_t& ex = c->learned ? c->gexec_learned : c->gexec[c->phase];
     if (!ex) {
         if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         hipStream_t run = c->stream;
@@ -365,9 +363,14 @@ int32_t ensure_learned_buffers(lgf_context* c)
     HIPCHK(c, hipMalloc(&c->s_dev, sizeof(double) * 16));
     HIPCHK(c, hipMalloc(&c->x_dev, sizeof(double) * 16));
     HIPCHK(c, hipMalloc(&c->ones_dev, sizeof(double) * 16));
-    c->bytes += 2 * sizeof(C2<double>) * (size_t)delta_elems(g);
-    // bands: log-spaced in p^2 from the smallest nonzero p^2 to p2max; the
-    // number of modes in each is counted here with the kernels' formula
+    HIPCHK(c, hipMalloc(&c->btab, (size_t)g.V));
+    c->bytes += 2 * sizeof(C2<double>) * (size_t)delta_elems(g) + (size_t)g.V;
+    // Bands: 16 intervals of log p^2 from the smallest nonzero p^2 of the
+    // lattice to p2max, b = floor(16 ln(p^2 / pmin) / ln(p2max / pmin)) clipped
+    // to [0, 15], none for p = 0.  The band of every spectrum position is
+    // tabulated once, in the layout of one field of a Delta chunk (tile j of W
+    // plane positions, then (z, t) position, then the position in the tile);
+    // the mode counts come from the same table.
     double p2max = 0.0;
     const std::vector<double> pt = momentum_tables(c->p.dims, &p2max);
     double pmin = 1e300;
@@ -375,24 +378,30 @@ int32_t ensure_learned_buffers(lgf_context* c)
         const double sn = std::sin(M_PI / (double)c->p.dims[m]);
         pmin = std::fmin(pmin, 4.0 * sn * sn);
     }
-    c->bands = Bands{pmin, std::log(p2max / pmin)};
+    const double log_range = std::log(p2max / pmin);
     const int* L = c->p.dims;
     const double* tx = pt.data();
     const double* ty = tx + L[0];
     const double* tz = ty + L[1];
     const double* tt = tz + L[2];
+    const int W = g.W, NQ = g.NQ, n = NQ * W;
+    std::vector<int8_t> tab((size_t)g.V);
     double cnt[16] = {};
-    for (int t = 0; t < L[3]; ++t)
-        for (int z = 0; z < L[2]; ++z)
-            for (int y = 0; y < L[1]; ++y)
-                for (int x = 0; x < L[0]; ++x) {
-                    const double p2 = tx[x] + ty[y] + tz[z] + tt[t];
-                    if (!(p2 > 0.0)) continue;
-                    int b = (int)std::floor(16.0 * std::log(p2 / pmin) / c->bands.log_range);
-                    cnt[b < 0 ? 0 : (b > 15 ? 15 : b)] += 1.0;
-                }
+    for (int j = 0; j < g.NP / W; ++j)
+        for (int i = 0; i < n; ++i) {
+            const int pxy = j * W + (i & (W - 1)), qq = i / W;
+            const double p2 = tx[pxy % L[0]] + ty[pxy / L[0]] + tz[qq % L[2]] + tt[qq / L[2]];
+            int b = -1;
+            if (p2 > 0.0) {
+                b = (int)std::floor(16.0 * std::log(p2 / pmin) / log_range);
+                b = b < 0 ? 0 : (b > 15 ? 15 : b);
+                cnt[b] += 1.0;
+            }
+            tab[(size_t)j * n + i] = (int8_t)b;
+        }
     std::memcpy(c->counts_host, cnt, sizeof cnt);
     std::vector<double> ones(16, 1.0);
+    HIPCHK(c, hipMemcpy(c->btab, tab.data(), tab.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->counts16, cnt, sizeof cnt, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->ones_dev, ones.data(), sizeof(double) * 16, hipMemcpyHostToDevice));
     const size_t zl = std::max((size_t)g.NQ * g.W * sizeof(C2<double>), (size_t)16 * 512 * sizeof(double));
@@ -412,8 +421,8 @@ MlpDev model_ptrs(lgf_context* c, bool use_model)
     return MlpDev{c->mw, c->mw + 16 * 64, c->mw + 16 * 64 + 64 * 64, c->mb, c->mb + 64, c->mb + 128};
 }
 
-// Full 4D spectrum of Delta in D (in place), band sums, features and (with a
-// model) the factors s.
+// Full 4D spectrum of Delta (in D) into D2, band sums, features and (with a
+// model) the factors s.  D keeps Delta.
 template <int LMAX>
 int32_t enqueue_bands(lgf_context* c, bool use_model)
 {
@@ -421,17 +430,18 @@ int32_t enqueue_bands(lgf_context* c, bool use_model)
     const Geo& g = b.geo;
     const int nblk = (g.NP / g.W) * 4;
     const size_t zl = std::max((size_t)g.NQ * g.W * sizeof(C2<double>), (size_t)16 * 512 * sizeof(double));
-    TRY(launch(c, K_ZT_FWD, k_zt_fwd_bands<double, LMAX>, dim3(nblk), dim3(512), zl, g, b.D,
-               (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
-               (const double*)c->ptab, c->bands, c->band_partial, (const DevState*)c->st));
-    TRY(launch(c, K_BANDS_MLP, k_bands_mlp<>, dim3(1), dim3(64), 0, (const double*)c->band_partial, nblk,
+    TRY(launch(c, K_ZT_FWD, k_zt_fwd_bands<double, LMAX>, dim3(nblk), dim3(512), zl, g, (const C2<double>*)b.D,
+               c->D2, (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
+               (const int8_t*)c->btab, c->band_partial, (const DevState*)c->st));
+    TRY(launch(c, K_BANDS_MLP, k_bands_mlp<>, dim3(1), dim3(256), 0, (const double*)c->band_partial, nblk,
                (const double*)c->counts16, g.V, model_ptrs(c, use_model), c->s_dev, c->x_dev, (const DevState*)c->st));
     return LGF_OK;
 }
 
-// One update with per-band factors s from the spectrum in D: candidate
-// links into U[1 - cur] and their Delta into D3.  mode 2: a candidate (F and
-// theta recorded as trial values, nothing committed); mode 1: committed.
+// One update with per-band factors s from the spectrum in D2: the scaled
+// inverse into D3, g, the candidate links into U[1 - cur] and their Delta
+// into D.  mode 2: a candidate (F and theta recorded as trial values, nothing
+// committed); mode 1: committed.
 template <int NE, int LMAX>
 int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double* trace_slot)
 {
@@ -441,14 +451,14 @@ int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double*
     const C2<double>* twy = b.tw + b.tw_off[1];
     const size_t glds = 4 * g.NP * sizeof(C2<double>);
     TRY(launch(c, K_ZT_INV, k_zt_inv_scaled<double, LMAX>, dim3((g.NP / g.W) * 4), dim3(512),
-               (size_t)g.NQ * g.W * sizeof(C2<double>), g, (const C2<double>*)b.D, c->D2,
+               (size_t)g.NQ * g.W * sizeof(C2<double>), g, (const C2<double>*)c->D2, c->D3,
                (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
-               (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), c->bands, s,
+               (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), (const int8_t*)c->btab, s,
                (const DevState*)c->st));
     TRY(launch(c, K_GAUGE, k_gauge<double, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g,
-               (const C2<double>*)c->D2, b.g, b.G, twx, twy, (const DevState*)c->st));
+               (const C2<double>*)c->D3, b.g, b.G, twx, twy, (const DevState*)c->st));
     TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<double, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane),
-               glds + 2 * c->nth_plane * sizeof(double), g, b.U[0], b.U[1], (const C2<double>*)b.g, c->D3,
+               glds + 2 * c->nth_plane * sizeof(double), g, b.U[0], b.U[1], (const C2<double>*)b.g, b.D,
                c->partial, twx, twy, (const DevState*)c->st));
     TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
                trace_slot, mode));
@@ -469,20 +479,22 @@ int32_t scaled_update_any(lgf_context* c, const double* s, int mode, double* tr 
 }
 
 // One learned update (Delta of the current links in D, state current): the
-// network's factors give candidate links; they are kept if F grows,
-// otherwise the plain update is taken.  The choice is made on the device,
-// so updates can be queued (and captured) back to back.  Leaves Delta of
-// the new links in D.
+// network's factors give candidate links, kept if F grows.  The choice is
+// made on the device, so updates can be queued (and captured) back to back;
+// a rejected candidate holds the state until the host runs enqueue_fallback.
+// Leaves Delta of the new links in D.
 int32_t learned_update(lgf_context* c, double* trace_slot)
 {
     TRY(bands_any(c, true));
     TRY(scaled_update_any(c, c->s_dev, 2));
-    TRY(launch(c, K_STATE, k_decide_trial<>, dim3(1), dim3(1), 0, c->st, trace_slot));
-    TRY(scaled_update_any(c, c->ones_dev, 1, trace_slot));
-    TRY(launch(c, K_STATE, k_end_trial<>, dim3(1), dim3(1), 0, c->st));
-    std::swap(c->d.D, c->D3);
-    c->dpar ^= 1;
-    return LGF_OK;
+    return launch(c, K_STATE, k_decide_trial<>, dim3(1), dim3(1), 0, c->st, trace_slot);
+}
+
+// After a rejected candidate: the plain update from the spectrum in D2.
+int32_t enqueue_fallback(lgf_context* c, double* trace_slot)
+{
+    TRY(launch(c, K_STATE, k_fallback_begin<>, dim3(1), dim3(1), 0, c->st));
+    return scaled_update_any(c, c->ones_dev, 1, trace_slot);
 }
 
 // theta after one update with factors s, the links kept as they are.
@@ -706,12 +718,11 @@ int32_t lgf_destroy(lgf_ctx c)
     (void)hipFree(c->check);
     (void)hipFree(c->trace_dev);
     for (void* q : {(void*)c->mw, (void*)c->mb, (void*)c->band_partial, (void*)c->counts16, (void*)c->s_dev,
-                    (void*)c->x_dev, (void*)c->ones_dev, (void*)c->D2, (void*)c->D3})
+                    (void*)c->x_dev, (void*)c->ones_dev, (void*)c->D2, (void*)c->D3, (void*)c->btab})
         (void)hipFree(q);
     if (c->st_host) (void)hipHostFree(c->st_host);
     release_events(c);
-    for (auto& ex : c->gexec_learned)
-        if (ex) (void)hipGraphExecDestroy(ex);
+    if (c->gexec_learned) (void)hipGraphExecDestroy(c->gexec_learned);
     for (auto& ex : c->gexec)
         if (ex) (void)hipGraphExecDestroy(ex);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -902,7 +913,11 @@ int32_t lgf_step(lgf_ctx c, int64_t n, lgf_stats* trace)
     if (c->learned) {
         if (!c->has_model) return fail(c, LGF_E_STATE, "the learned step needs lgf_set_model first");
         TRY(ensure_learned_buffers(c));
-        for (int64_t k = 1; k <= n; ++k) TRY(learned_update(c, tr ? tr + 2 * k : nullptr));
+        for (int64_t k = 1; k <= n; ++k) {
+            TRY(learned_update(c, tr ? tr + 2 * k : nullptr));
+            TRY(sync_state(c));
+            if (c->st_host->fallback) TRY(enqueue_fallback(c, tr ? tr + 2 * k : nullptr));
+        }
     } else {
         for (int64_t k = 1; k <= n; ++k) TRY(update_any(c, tr ? tr + 2 * k : nullptr));
     }
@@ -937,9 +952,13 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
             if (!c->has_model) return fail(c, LGF_E_STATE, "the learned step needs lgf_set_model first");
             TRY(ensure_learned_buffers(c));
         }
-        while (!c->st_host->done && c->st_host->iter < c->p.max_iter) {
-            const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
-            TRY(enqueue_chunk(c, chunk));
+        while ((!c->st_host->done || c->st_host->fallback) && c->st_host->iter < c->p.max_iter) {
+            if (c->st_host->fallback) {
+                TRY(enqueue_fallback(c, nullptr));
+            } else {
+                const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
+                TRY(enqueue_chunk(c, chunk));
+            }
             TRY(sync_state(c));
         }
         if (c->st_host->nonfinite) {
@@ -987,9 +1006,7 @@ int32_t lgf_learned_factors(lgf_ctx c, double features[16], double s[16])
     TRY(bands_any(c, true));
     HIPCHK(c, hipMemcpyAsync(features, c->x_dev, sizeof(double) * 16, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(s, c->s_dev, sizeof(double) * 16, hipMemcpyDeviceToHost, c->stream));
-    TRY(sync_state(c));
-    c->delta_valid = false;          // D now holds the full spectrum
-    return LGF_OK;
+    return sync_state(c);            // D still holds Delta of the current links
 }
 
 int32_t lgf_linesearch_bands(lgf_ctx c, double features[16], double log_s[16])
@@ -1003,7 +1020,7 @@ int32_t lgf_linesearch_bands(lgf_ctx c, double features[16], double log_s[16])
     TRY(bands_any(c, false));
     HIPCHK(c, hipMemcpyAsync(features, c->x_dev, sizeof(double) * 16, hipMemcpyDeviceToHost, c->stream));
     TRY(sync_state(c));
-    c->delta_valid = false;          // D now holds the full spectrum
+    c->delta_valid = false;          // the trials below write their own Delta into D
     // one factor for all bands: golden-section search on ln s in [-2.3, 2.3]
     double best = 0.0;
     TRY(trial_theta(c, std::vector<double>(16, 1.0), &best));

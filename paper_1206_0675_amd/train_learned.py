@@ -1,15 +1,19 @@
 """Train the learned spectral step on the GPU.
 
-    python -m paper_1206_0675_amd.train_learned [--configs 256] [--out DIR]
+    python -m paper_1206_0675_amd.train_learned [--configs 256] [--rounds 2] [--out DIR]
 
-1. For each generated field (seeds 2000, 2001, ... of the seeded generator,
-   16^4, plaquette 0.6), run the plain FP64 method; every `--every`
-   iterations until theta < 1e-14, record the band features of Delta and the
-   log factors that minimise theta after one update (lgf_linesearch_bands, a
-   golden-section search on the GPU).
-2. Train the 16-64-64-16 network on these samples with the library's own
-   forward, backward and Adam kernels (lgf_mlp_train).
-3. Write the model blob and a JSON record of the run.
+1. Generate the training fields (seeds 2000, 2001, ... of the seeded
+   generator, 16^4, plaquette 0.6).
+2. Round 0: run the plain FP64 method on each; every `--every` iterations,
+   until theta < 1e-14, record the band features of Delta and the log factor
+   that minimises theta after one update (lgf_linesearch_bands, a
+   golden-section search on the GPU).  Train the 16-64-64-16 network on these
+   samples with the library's own forward, backward and Adam kernels
+   (lgf_mlp_train).
+3. Later rounds: collect the same way along the trajectories of the learned
+   step with the current network (the states it actually visits), add them
+   to the samples and train again.
+4. Write the model blob and a JSON record of the run.
 """
 from __future__ import annotations
 
@@ -56,11 +60,16 @@ def generate(dims, seeds, workers=8):
         return list(ex.map(synth.random_links, [dims] * len(seeds), seeds))
 
 
-def collect(dims, fields, every=3, theta_min=1e-14, lib=None, log=print):
+def collect(dims, fields, every=3, theta_min=1e-14, lib=None, log=print, blob=None):
+    """Samples along the plain trajectories, or along those of the learned
+    step with model `blob`."""
     X, Y = [], []
     mask = band_mask(dims)
+    kw = {} if blob is None else {"step": lgf.STEP_LEARNED}
     for k, U in enumerate(fields):
-        with lgf.Context(dims, lib=lib) as c:
+        with lgf.Context(dims, lib=lib, **kw) as c:
+            if blob is not None:
+                c.set_model(blob)
             c.load(U)
             it = 0
             while it < 200:
@@ -73,7 +82,7 @@ def collect(dims, fields, every=3, theta_min=1e-14, lib=None, log=print):
                     Y.append(ls)
                 c.step(1)
                 it += 1
-        if log and (k % 16 == 0 or k == len(fields) - 1):
+        if log and (k % 64 == 0 or k == len(fields) - 1):
             log(f"# collected {len(X)} samples from {k + 1} fields")
     X, Y = np.array(X), np.array(Y)
     M = np.broadcast_to(mask.astype(np.float64), X.shape).copy()
@@ -89,6 +98,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--rounds", type=int, default=2)
     ap.add_argument("--out", default=MODEL_DIR)
     args = ap.parse_args(argv)
     t0 = time.time()
@@ -96,20 +106,28 @@ def main(argv=None):
     fields = generate(dims, list(range(args.seed0, args.seed0 + args.configs)))
     print(f"# generated {len(fields)} fields in {time.time() - t0:.1f}s", flush=True)
     L = lgf.load_library()
-    X, Y, M = collect(dims, fields, args.every, lib=L, log=lambda m: print(m, flush=True))
-    t1 = time.time()
-    blob, trace = lgf.mlp_train(X, Y, M, steps=args.steps, batch=args.batch, seed=1, lr=args.lr, lib=L)
-    t2 = time.time()
-    pred = lgf.mlp_eval(blob, X, lib=L)
-    mse = float(np.sum(M * (pred - Y) ** 2) / np.sum(M))
+    say = lambda m: print(m, flush=True)    # noqa: E731
+    Xs, Ys, Ms, blob, trace, rounds = [], [], [], None, None, []
+    for r in range(args.rounds):
+        t1 = time.time()
+        X, Y, M = collect(dims, fields, args.every, lib=L, log=say, blob=blob)
+        Xs.append(X), Ys.append(Y), Ms.append(M)
+        X, Y, M = np.concatenate(Xs), np.concatenate(Ys), np.concatenate(Ms)
+        t2 = time.time()
+        blob, trace = lgf.mlp_train(X, Y, M, steps=args.steps, batch=args.batch, seed=1, lr=args.lr, lib=L)
+        pred = lgf.mlp_eval(blob, X, lib=L)
+        mse = float(np.sum(M * (pred - Y) ** 2) / np.sum(M))
+        rounds.append({"round": r, "samples": int(X.shape[0]), "train_mse": mse,
+                       "collect_seconds": round(t2 - t1, 1), "train_seconds": round(time.time() - t2, 2)})
+        say(f"# round {r}: {X.shape[0]} samples, train mse {mse:.4g}")
     base = float(np.sum(M * Y ** 2) / np.sum(M))        # the plain step (all log factors 0)
     os.makedirs(args.out, exist_ok=True)
     with open(os.path.join(args.out, "learned_step.bin"), "wb") as f:
         f.write(blob)
     rec = {"dims": list(dims), "seeds": [args.seed0, args.seed0 + args.configs - 1], "every": args.every,
            "samples": int(X.shape[0]), "steps": args.steps, "batch": args.batch, "lr": args.lr,
-           "train_mse": mse, "plain_step_mse": base, "loss_first": float(trace[0]), "loss_last": float(trace[-1]),
-           "collect_seconds": round(t1 - t0, 1), "train_seconds": round(t2 - t1, 2),
+           "train_mse": rounds[-1]["train_mse"], "plain_step_mse": base, "loss_first": float(trace[0]),
+           "loss_last": float(trace[-1]), "rounds": rounds, "seconds": round(time.time() - t0, 1),
            "mean_target_log_s": Y.mean(axis=0).round(4).tolist()}
     with open(os.path.join(args.out, "learned_step.json"), "w") as f:
         json.dump(rec, f, indent=1)
