@@ -75,8 +75,8 @@ extern "C" {
 /* step kind */
 #define LGF_STEP_PLAIN 0    /* eq. gx: (alpha/2) p2max/p2                                  */
 #define LGF_STEP_LEARNED 1  /* s_b (alpha/2) p2max/p2 with per-band factors s_b from the
-                               network set by lgf_set_model; an update that lowers F by
-                               more than 1e-14 is replaced by the plain one (FP64 only)     */
+                               network set by lgf_set_model; an update that does not
+                               increase F is replaced by the plain one (FP64 only)          */
 
 /* acceleration kernel */
 #define LGF_ACCEL_FOURIER 1  /* K(p) = p2max/p2, K(0) = 0 (eq. gx)                       */

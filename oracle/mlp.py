@@ -17,9 +17,8 @@ factors:
 
 Weights are stored in bfloat16 (round to nearest even from float32) and
 biases in float32; this reference evaluates the network in float64 on those
-exact values.  An update with factors s is accepted unless it lowers F by more
-than ACCEPT_TOL = 1e-14 (the level to which F is monotone for the plain step
-too); otherwise the plain update (s = 1) is taken.
+exact values.  An update with factors s is accepted only if it increases F;
+otherwise the plain update (s = 1) is taken.
 
 Training targets: the one factor s, common to all bands, that minimises theta
 after one update (theta is what the stop test reads, and it stays resolvable
@@ -38,7 +37,6 @@ from . import lgfo
 
 NB, H1, H2 = 16, 64, 64
 CLIP = 2.3
-ACCEPT_TOL = 1e-14
 SHAPES = [("W1", (NB, H1)), ("b1", (H1,)), ("W2", (H1, H2)), ("b2", (H2,)), ("W3", (H2, NB)), ("b3", (NB,))]
 NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)
 MAGIC = 0x4C47464D   # "LGFM"
@@ -153,15 +151,14 @@ def update_with(dims, U, s, alpha=0.08):
 
 
 def learned_step(dims, U, p: dict, alpha=0.08):
-    """(U', accepted, s, x): factors from the network; plain step if F drops
-    by more than ACCEPT_TOL."""
+    """(U', accepted, s, x): factors from the network; plain step if F drops."""
     V = int(np.prod(dims))
     F0, _, delta = lgfo.measure(dims, U)
     P, cnt = lgfo.band_powers(dims, delta)
     x = features(P, cnt, V)
     s = factors(p, x)
     U1 = update_with(dims, U, s, alpha)
-    if lgfo.measure(dims, U1)[0] >= F0 - ACCEPT_TOL:
+    if lgfo.measure(dims, U1)[0] > F0:
         return U1, True, s, x
     return update_with(dims, U, None, alpha), False, s, x
 

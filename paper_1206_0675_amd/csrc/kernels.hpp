@@ -881,18 +881,14 @@ __global__ void __launch_bounds__(256) k_bands_mlp(const double* __restrict__ ba
 }
 
 // Learned step, decided on the device: the candidate links (F, theta from
-// the trial reduction) become current unless they lower F by more than the
-// rounding margin kAcceptTol (F is monotone only to that level near
-// convergence, for the plain step too).  Otherwise `fallback`
+// the trial reduction) become current if they raise F.  Otherwise `fallback`
 // is raised and `done` held at 1, so the rest of a queued chunk does nothing,
 // until the host has run the plain update (k_fallback_begin first).
-constexpr double kAcceptTol = 1e-14;
-
 template <int UNUSED = 0>
 __global__ void k_decide_trial(DevState* st, double* trace)
 {
     if (st->done) return;
-    if (st->trial_F >= st->F - kAcceptTol) {
+    if (st->trial_F > st->F) {
         st->iter += 1;
         st->cur ^= 1;
         st->needs_measure = 0;

@@ -225,7 +225,7 @@ def test_emulated_learned_factors_and_update_match_oracle(E, oracle_lib):
         st = c.measure()
     F0 = oracle.measure(dims, U)[0]
     Uc = omlp.update_with(dims, U, s)
-    Uo = Uc if oracle.measure(dims, Uc)[0] >= F0 - omlp.ACCEPT_TOL else oracle.step(dims, U, 1)[0]
+    Uo = Uc if oracle.measure(dims, Uc)[0] > F0 else oracle.step(dims, U, 1)[0]
     assert np.max(np.abs(Ug - Uo)) <= 1e-12
 
 
@@ -258,7 +258,7 @@ def test_emulated_learned_steps_trace_match_oracle(E, oracle_lib):
         P, cnt = oracle.band_powers(dims, delta)
         assert np.max(np.abs(s / omlp.factors(p, omlp.features(P, cnt, synth.volume(dims))) - 1)) <= 1e-5
         Uc = omlp.update_with(dims, Uo, s)
-        if oracle.measure(dims, Uc)[0] >= F0 - omlp.ACCEPT_TOL:
+        if oracle.measure(dims, Uc)[0] > F0:
             Uo = Uc
         else:
             Uo, rejected = oracle.step(dims, Uo, 1)[0], rejected + 1

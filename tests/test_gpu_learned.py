@@ -44,7 +44,7 @@ def oracle_learned(dims, U, s):
     """The oracle's update for given factors s, with the accept rule."""
     F0 = oracle.measure(dims, U)[0]
     Uc = omlp.update_with(dims, U, s)
-    return Uc if oracle.measure(dims, Uc)[0] >= F0 - omlp.ACCEPT_TOL else oracle.step(dims, U, 1)[0]
+    return Uc if oracle.measure(dims, Uc)[0] > F0 else oracle.step(dims, U, 1)[0]
 
 
 def test_zero_model_is_plain(L):
