@@ -65,13 +65,24 @@ struct DevState {
     int64_t fallbacks;     // learned step: updates that fell back to the plain factors
 };
 
-// plane index handled by this block: consecutive planes stay on one XCD
-// (blocks are dealt to the 8 XCDs round robin), so the z neighbours a
-// block reads are in the same L2.
-__device__ __forceinline__ int plane_of_block(int b, int nq)
+// Plane handled by block b.  Blocks are dealt to the 8 XCDs round robin
+// (XCD b & 7, in order b >> 3 on it), and each XCD has its own L2.  The
+// transform reads g and the backward links of the z +- 1 and t +- 1 planes,
+// so each XCD gets a compact (z, t) slab (Lz/nz z by Lt/nt t, nz * nt = 8)
+// walked z fastest: the planes in flight on an XCD then cover a few t rows
+// of its slab, and the neighbour planes they read are in flight or were just
+// read there.  Other shapes keep the identity order.
+__host__ __device__ __forceinline__ int plane_of_block(int b, const Geo& geo)
 {
-    if ((nq & 7) != 0) return b;
-    return (b & 7) * (nq >> 3) + (b >> 3);
+    const int Lz = geo.L[2], Lt = geo.L[3];
+    const int nz = Lz >= 16 ? 4 : (Lz >= 8 ? 2 : 1);
+    const int nt = 8 / nz;
+    if (geo.NQ < 64 || Lt % nt != 0) return b;
+    const int zw = Lz / nz, tw = Lt / nt;
+    const int x = b & 7, l = b >> 3;
+    const int z = (x % nz) * zw + l % zw;
+    const int t = (x / nz) * tw + l / zw;
+    return t * Lz + z;
 }
 
 // ---------------------------------------------------------------------------
@@ -475,7 +486,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, C2<T>* U0, C2<T>* U1, 
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     const int cur = st->cur;
-    measure_plane<T, NE, APPLY_G, LMAX>(geo, plane_of_block(blockIdx.x, geo.NQ), cur ? U1 : U0, cur ? U0 : U1, g, D,
+    measure_plane<T, NE, APPLY_G, LMAX>(geo, plane_of_block(blockIdx.x, geo), cur ? U1 : U0, cur ? U0 : U1, g, D,
                                         partial, twx, twy, lds_raw,
                                         reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
 }
@@ -498,7 +509,7 @@ __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict_
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
-    gauge_plane<T, NE, ACC_G, LMAX>(geo, plane_of_block(blockIdx.x, geo.NQ), D, g, G, twx, twy,
+    gauge_plane<T, NE, ACC_G, LMAX>(geo, plane_of_block(blockIdx.x, geo), D, g, G, twx, twy,
                                     reinterpret_cast<C2<T>*>(lds_raw));
 }
 
