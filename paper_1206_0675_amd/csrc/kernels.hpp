@@ -68,14 +68,15 @@ struct DevState {
 // Plane handled by block b.  Blocks are dealt to the 8 XCDs round robin
 // (XCD b & 7, in order b >> 3 on it), and each XCD has its own L2.  The
 // transform reads g and the backward links of the z +- 1 and t +- 1 planes,
-// so each XCD gets a compact (z, t) slab (Lz/nz z by Lt/nt t, nz * nt = 8)
-// walked z fastest: the planes in flight on an XCD then cover a few t rows
-// of its slab, and the neighbour planes they read are in flight or were just
-// read there.  Other shapes keep the identity order.
+// so each XCD gets a (z, t) slab (Lz/nz z by Lt/nt t, nz * nt = 8) walked z
+// fastest, so that neighbour planes are read on the same XCD close together
+// in time.  Of the slab shapes timed at 32^4 (8 XCDs as 1, 2, 4 or 8 slabs
+// along z), nz = 8 (4 z by all t) was fastest.  Other shapes keep the
+// identity order.
 __host__ __device__ __forceinline__ int plane_of_block(int b, const Geo& geo)
 {
     const int Lz = geo.L[2], Lt = geo.L[3];
-    const int nz = Lz >= 16 ? 4 : (Lz >= 8 ? 2 : 1);
+    const int nz = Lz >= 8 ? 8 : Lz;
     const int nt = 8 / nz;
     if (geo.NQ < 64 || Lt % nt != 0) return b;
     const int zw = Lz / nz, tw = Lt / nt;
