@@ -225,16 +225,10 @@ __global__ void __launch_bounds__(256) k_field_identity(int64_t V, int64_t VS, C
 // theta terms, forward (x, y) FFT of the packed Delta into D.
 //   red: 2 * blockDim doubles of LDS; buf: 4 * NP complex of LDS.
 // ---------------------------------------------------------------------------
-// carry (streaming kernel only, else null): the algebra parts of the
-// transformed t links of the previous t plane, 4 * NP complex in LDS.  With
-// carry_in they replace the recomputation of U'_t(x - t) (the same value,
-// added in the same order); with carry_out this plane's are stored.  Each
-// thread reads and writes only its own sites.
 template <typename T, int NE, bool APPLY_G, int LMAX>
 __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ Uin, C2<T>* __restrict__ Uout,
                               const C2<T>* __restrict__ g, C2<T>* __restrict__ D, double* __restrict__ partial,
-                              const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy, double* red, C2<T>* buf,
-                              C2<T>* carry = nullptr, bool carry_in = false, bool carry_out = false)
+                              const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy, double* red, C2<T>* buf)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int Lx = geo.L[0], Ly = geo.L[1], Lz = geo.L[2], Lt = geo.L[3];
@@ -253,12 +247,9 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
         const int64_t s = q0 + p;
         const int64_t xp = q0 + y * Lx + ((x + 1) & (Lx - 1)), xm = q0 + y * Lx + ((x - 1) & (Lx - 1));
         const int64_t yp = q0 + (((y + 1) & (Ly - 1)) * Lx + x), ym = q0 + (((y - 1) & (Ly - 1)) * Lx + x);
-        Alg8<T> acc, cin;
+        Alg8<T> acc;
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc.c[c] = mk<T>(T(0), T(0));
-        if (carry_in)              // before this plane's own t links overwrite it
-#pragma unroll
-            for (int c = 0; c < 4; ++c) cin.c[c] = carry[c * NP + p];
         M3<T> gx;
         if (APPLY_G) load_mat<T, NE>(gx, g, VS, s);
         double f = 0.0;
@@ -272,25 +263,12 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
                 a_u_bdag<T, (NE == 6 ? 2 : 3)>(gx, u, gn, r);
                 store_mat<T, NE>(r, Uout + (int64_t)mu * NE * VS, VS, s);
                 u = r;
-                if (mu == 3 && carry_out) {
-                    Alg8<T> ct;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) ct.c[c] = mk<T>(T(0), T(0));
-                    alg_accumulate(ct, r, T(1));
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) carry[c * NP + p] = ct.c[c];
-                }
             }
             f += re_trace(u);
             alg_accumulate(acc, u, T(-1));
         }
 #pragma unroll 1
         for (int nu = 0; nu < 4; ++nu) {
-            if (nu == 3 && carry_in) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc.c[c] = acc.c[c] + cin.c[c];
-                continue;
-            }
             M3<T> u;
             const int64_t sb = nu == 0 ? xm : nu == 1 ? ym : nu == 2 ? qzm + p : qtm + p;
             load_mat<T, NE>(u, Uin + (int64_t)nu * NE * VS, VS, sb);
@@ -512,46 +490,6 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, C2<T>* U0, C2<T>* U1, 
     measure_plane<T, NE, APPLY_G, LMAX>(geo, plane_of_block(blockIdx.x, geo), cur ? U1 : U0, cur ? U0 : U1, g, D,
                                         partial, twx, twy, lds_raw,
                                         reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
-}
-
-// Transform + measure for S consecutive t planes of one z per block (block
-// -> (z, t0) by stream_of_block), carrying the t-link algebra from plane to
-// plane in LDS instead of re-reading U_t and g of the plane below.  LDS:
-// 2 * blockDim doubles, then 4 * NP complex (FFT buffer), then 4 * NP complex
-// (carry).
-__host__ __device__ __forceinline__ void stream_of_block(int b, const Geo& geo, int S, int* z, int* t0)
-{
-    const int Lz = geo.L[2], segs = geo.L[3] / S;
-    const int nb = Lz * segs;
-    if (Lz >= 8 && (nb & 7) == 0 && (nb >> 3) % (Lz >> 3) == 0) {
-        // XCD b & 7 takes z in [x Lz/8, (x+1) Lz/8) for every segment, z fastest
-        const int zw = Lz >> 3, x = b & 7, l = b >> 3;
-        *z = x * zw + l % zw;
-        *t0 = (l / zw) * S;
-    } else {
-        *z = b % Lz;
-        *t0 = (b / Lz) * S;
-    }
-}
-
-template <typename T, int NE, int LMAX>
-__global__ void __launch_bounds__(512) k_measure_stream(Geo geo, int S, C2<T>* U0, C2<T>* U1,
-                                                        const C2<T>* __restrict__ g, C2<T>* __restrict__ D,
-                                                        double* __restrict__ partial, const C2<T>* __restrict__ twx,
-                                                        const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
-{
-    if (st->done) return;
-    HIP_DYNAMIC_SHARED(double, lds_raw)
-    const int cur = st->cur;
-    int z, t0;
-    stream_of_block(blockIdx.x, geo, S, &z, &t0);
-    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x);
-    C2<T>* carry = buf + 4 * geo.NP;
-    for (int k = 0; k < S; ++k) {
-        measure_plane<T, NE, true, LMAX>(geo, (t0 + k) * geo.L[2] + z, cur ? U1 : U0, cur ? U0 : U1, g, D, partial,
-                                         twx, twy, lds_raw, buf, carry, k > 0, k + 1 < S);
-        __syncthreads();
-    }
 }
 
 template <typename T, int LMAX>

@@ -148,9 +148,6 @@ int32_t set_lds_attrs(lgf_context* c)
                                   hipFuncAttributeMaxDynamicSharedMemorySize, glds));
     HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt<T, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, zlds));
-    if (stream_len<T>(g) > 0)
-        HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure_stream<T, NE, LMAX>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)stream_lds<T>(g)));
     return LGF_OK;
 }
 
@@ -198,14 +195,9 @@ int32_t enqueue_update(lgf_context* c, double* trace_slot)
     else
         TRY(launch(c, K_GAUGE, k_gauge<T, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.g,
                    b.G, twx, twy, (const DevState*)c->st));
-    if (const int S = stream_len<T>(g))
-        TRY(launch(c, K_TRANSFORM_MEASURE, k_measure_stream<T, NE, LMAX>, dim3(g.NQ / S), dim3(stream_threads(g)),
-                   stream_lds<T>(g), g, S, b.U[0], b.U[1], (const C2<T>*)b.g, b.D, c->partial, twx, twy,
-                   (const DevState*)c->st));
-    else
-        TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<T, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane), mlds, g,
-                   b.U[0], b.U[1], (const C2<T>*)b.g, b.D, c->partial, twx, twy,
-                   (const DevState*)c->st));
+    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<T, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane), mlds, g,
+               b.U[0], b.U[1], (const C2<T>*)b.g, b.D, c->partial, twx, twy,
+               (const DevState*)c->st));
     TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
                trace_slot, 1));
     return LGF_OK;

@@ -206,25 +206,6 @@ Geo make_geo(const int32_t* dims, int tile_bytes = 64)
     return g;
 }
 
-// Streaming transform (k_measure_stream): threads per block, LDS, and the
-// number S of t planes per block (the largest power of two <= Lt that still
-// gives at least 256 blocks); 0 when it does not apply (fewer than 2 planes
-// per block, or the two plane buffers do not fit the LDS).
-inline int stream_threads(const Geo& g) { return g.NP >= 512 ? 512 : (g.NP >= 256 ? 256 : 128); }
-template <typename T>
-size_t stream_lds(const Geo& g)
-{
-    return 2 * (size_t)stream_threads(g) * sizeof(double) + 8 * (size_t)g.NP * sizeof(C2<T>);
-}
-template <typename T>
-int stream_len(const Geo& g)
-{
-    int S = 1;
-    while (2 * S <= g.L[3] && g.NQ / (2 * S) >= 256) S *= 2;
-    if (S < 2 || stream_lds<T>(g) > kMaxLds) return 0;
-    return S;
-}
-
 // Complex elements of the Delta buffer.
 inline int64_t delta_elems(const Geo& g) { return (int64_t)(g.NP / g.W) * 4 * g.DS; }
 
