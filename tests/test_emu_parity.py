@@ -48,6 +48,21 @@ def test_emulated_steps_match_oracle(E, oracle_lib, dims, kw):
     assert np.max(np.abs(tt / ot - 1)) <= 1e-12
 
 
+@pytest.mark.parametrize("dims, kw", [((4, 4, 32, 32), {}), ((4, 4, 16, 32), {"storage": 12}),
+                                      ((8, 4, 8, 64), {})])
+def test_emulated_large_zt_extent_matches_oracle(E, oracle_lib, dims, kw):
+    """Many (z, t) planes: the XCD-aware plane order over 8 slabs."""
+    U = synth.random_links(dims, 41)
+    o = oracle.opts(store12=kw.get("storage", 18) == 12)
+    with lgf.Context(dims, lib=E, **kw) as c:
+        c.load(U)
+        tf, tt = c.step(3, trace=True)
+        Ug = c.store()
+    Uo, of, ot, _ = oracle.step(dims, U, 3, o)
+    assert np.max(np.abs(Ug - Uo)) <= 1e-12
+    assert np.max(np.abs(tf - of) / of) <= 1e-12 and np.max(np.abs(tt - ot) / ot) <= 1e-12
+
+
 def test_emulated_fp32_error_is_single_precision(E, oracle_lib):
     dims = (8, 4, 8, 4)
     U = synth.random_links(dims, 2)
@@ -119,7 +134,8 @@ from paper_1206_0675_amd import lgf
 L = lgf.load_library({lib!r})
 for dims, kw in [((4, 4, 4, 4), {{"max_iter": 4}}), ((8, 4, 4, 8), {{"storage": 12, "max_iter": 4}}),
                  ((4, 8, 4, 4), {{"precision": 2, "poll_every": 4, "theta_switch": 1.0, "max_iter": 8}}),
-                 ((4, 4, 8, 4), {{"precision": 1, "track_gauge": 1, "max_iter": 4}})]:
+                 ((4, 4, 8, 4), {{"precision": 1, "track_gauge": 1, "max_iter": 4}}),
+                 ((4, 4, 32, 32), {{"storage": 12, "max_iter": 3}})]:
     ctx = lgf.Context(dims, lib=L, **kw)
     ctx.load(synth.random_links(dims, 5))
     ctx.step(2, trace=True)
