@@ -49,7 +49,7 @@ def alg_bytes(V, s, R):
 
 def source_digest():
     h = hashlib.sha256()
-    for f in ("su3.hpp", "fft.hpp", "kernels.hpp", "lgf.hip"):
+    for f in ("su3.hpp", "fft.hpp", "kernels.hpp", "runtime.hpp", "lgf.hip"):
         with open(os.path.join(ROOT, "paper_1206_0675_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -70,6 +70,40 @@ def measured_traffic(kernel, dims, storage):
     return e.get("bytes_per_launch")
 
 
+def shape_sweep(L, dims, R, U, args):
+    """Force each candidate launch shape through the autotuner's cache file
+    and time it like the main measurement."""
+    import tempfile
+    import torch
+    from paper_1206_0675_amd import lgf
+    cache = os.path.join(tempfile.mkdtemp(), "tune.txt")
+    os.environ["LGF_TUNE_CACHE"] = cache
+    with lgf.Context(dims, lib=L, storage=R, autotune=1) as ctx:
+        print(f"# autotuner pick (threads, tile bytes): {ctx.config()}", flush=True)
+    with open(cache) as fh:
+        key = fh.read().split()[0]
+    for nth in (64, 128, 256):
+        for tb in (32, 64, 128):
+            with open(cache, "w") as fh:
+                fh.write(f"{key} {nth} {tb}\n")
+            with lgf.Context(dims, lib=L, storage=R, autotune=1) as ctx:
+                ctx.load(U)
+                ctx.step(args.warmup)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.step(args.steps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            with lgf.Context(dims, lib=L, storage=R, autotune=1, profile=1) as ctx:
+                ctx.load(U)
+                ctx.step(args.warmup)
+                ctx.profile_reset()
+                ctx.step(args.steps)
+                prof = ctx.profile()
+            us = {k: round(ms / n * 1e3, 1) for k, (n, ms) in prof.items() if n}
+            print(f"threads {nth} tile_bytes {tb}: {args.steps / dt:.1f} iters/s, kernel us {us}", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +120,9 @@ def main():
                     help="for hardware counters: a few iterations, then one plain device copy of "
                          "--copy-mib MiB (a kernel of known traffic that scales FETCH_SIZE/WRITE_SIZE); no JSON")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--shape-sweep", action="store_true",
+                    help="time every launch shape the autotuner chooses from (threads per plane block x tile "
+                         "row bytes), one line each; no JSON")
     ap.add_argument("--gen-workers", type=int, default=1,
                     help="worker processes for input generation (fork + exec); leave at 1 under a profiler, "
                          "which sets up the GPU before this program starts")
@@ -108,7 +145,7 @@ def main():
     print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     model_path = os.path.join(ROOT, "paper_1206_0675_amd", "models", "learned_step.bin")
     learned_fields = []
-    if not (args.pmc_sample or args.no_extras) and args.learned_seeds > 0 and os.path.exists(model_path):
+    if not (args.pmc_sample or args.shape_sweep or args.no_extras) and args.learned_seeds > 0 and os.path.exists(model_path):
         t = time.time()
         learned_fields = [(seed, synth.random_links(LEARNED_DIMS, seed, workers=args.gen_workers))
                           for seed in range(3000, 3000 + args.learned_seeds)]
@@ -137,8 +174,13 @@ def main():
         print(f"# pmc sample: 5 iterations, then one copy of {args.copy_mib} MiB", file=sys.stderr, flush=True)
         return
 
+    if args.shape_sweep:
+        shape_sweep(L, dims, R, U, args)
+        return
+
     # ---- timed iterations (no profiling) -----------------------------------
     with lgf.Context(dims, lib=L, storage=R) as ctx:
+        launch_shape = dict(zip(("plane_threads", "tile_bytes"), ctx.config()))
         ctx.load(U)
         ctx.step(args.warmup)
         torch.cuda.synchronize()
@@ -258,7 +300,8 @@ def main():
         "learned_vs_plain": learned,
         "cpu_baseline": cpu,
         "context": {"paper_c2070_iters_per_s": PAPER_C2070_ITERS_PER_S,
-                    "device": torch.cuda.get_device_name(0), "source_digest": source_digest()},
+                    "device": torch.cuda.get_device_name(0), "source_digest": source_digest(),
+                    "launch_shape": launch_shape},
     }
     print(json.dumps(line), flush=True)
 

@@ -190,8 +190,9 @@ int32_t lgf_batch_load(lgf_batch_t b, int32_t i, const void *links, int32_t wher
 int32_t lgf_batch_fix(lgf_batch_t b, lgf_stats *out);
 int32_t lgf_batch_store(lgf_batch_t b, int32_t i, void *links, int32_t where);
 int32_t lgf_batch_store_gauge(lgf_batch_t b, int32_t i, void *G, int32_t where);
-/* The launch shape the batch runs with: threads per plane block and the
- * width (complex values) of the Delta tiles, after autotuning if requested. */
+/* The launch shape the batch runs with, after autotuning if requested:
+ * threads per plane block, and the bytes of one row of a (z, t) tile of the
+ * Delta layout (tile_bytes / sizeof(complex) plane positions per tile). */
 int32_t lgf_batch_config(lgf_batch_t b, int32_t *plane_threads, int32_t *tile_bytes);
 const char *lgf_batch_last_error(lgf_batch_t b);
 
@@ -262,6 +263,12 @@ int32_t lgf_mlp_eval(const void *blob, size_t bytes, const float *X, int64_t n, 
 int32_t lgf_profile_read(lgf_ctx ctx, int64_t *launches, double *total_ms, int32_t n, int32_t *count);
 int32_t lgf_profile_reset(lgf_ctx ctx);
 const char *lgf_kernel_name(int32_t k);
+
+/* The launch shape the context runs with (lgf_params.autotune picks it at
+ * lgf_create; the default is 256 threads, or the plane size if smaller, and
+ * 128-byte tiles): threads per plane block, and the bytes of one row of a
+ * (z, t) tile of the Delta layout.  Either pointer may be NULL. */
+int32_t lgf_config(lgf_ctx ctx, int32_t *plane_threads, int32_t *tile_bytes);
 
 /* Bytes of device memory the context holds. */
 int32_t lgf_device_bytes(lgf_ctx ctx, int64_t *bytes);

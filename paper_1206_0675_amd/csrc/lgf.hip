@@ -15,7 +15,10 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -86,6 +89,7 @@ struct lgf_context : Runner {
     int64_t bytes = 0;
     double c0 = 0.0;          // (alpha/2) p2max / V
     int nth_plane = 256;
+    int tile_bytes = kDefaultTileBytes;   // bytes of one (z, t) tile row: W = tile_bytes / sizeof(complex)
     int lmax = 64;            // longest axis rounded up to 64 or 128 (kernel variant)
     hipStream_t cap_stream = nullptr;          // private stream that graph capture runs on
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // per phase: poll_every updates
@@ -338,6 +342,135 @@ void fill_stats(lgf_context* c, lgf_stats* out, int32_t status, double t0)
     out->seconds = t0 > 0 ? now_s() - t0 : 0.0;
     out->phase = c->phase;
     out->status = status;
+}
+
+// ---------------------------------------------------------------------------
+// launch shape: threads per plane block and (z, t) tile width
+// ---------------------------------------------------------------------------
+int32_t set_all_lds(lgf_context* c)
+{
+    for (int lm : {64, 128}) {
+        if (c->use64)
+            TRY(c->NE == 9 ? (lm == 64 ? set_lds_attrs<double, 9, 64>(c) : set_lds_attrs<double, 9, 128>(c))
+                           : (lm == 64 ? set_lds_attrs<double, 6, 64>(c) : set_lds_attrs<double, 6, 128>(c)));
+        if (c->use32)
+            TRY(c->NE == 9 ? (lm == 64 ? set_lds_attrs<float, 9, 64>(c) : set_lds_attrs<float, 9, 128>(c))
+                           : (lm == 64 ? set_lds_attrs<float, 6, 64>(c) : set_lds_attrs<float, 6, 128>(c)));
+    }
+    return LGF_OK;
+}
+
+// Rebuild the geometry for nth threads per plane block and tile_bytes-wide
+// (z, t) tiles.  D was sized for every tile choice.  Only called from
+// lgf_create, before the learned-step tables (laid out by tile) exist.
+int32_t configure(lgf_context* c, int nth, int tile_bytes)
+{
+    if ((c->use64 && !shape_fits<double>(c->p.dims, nth)) || (c->use32 && !shape_fits<float>(c->p.dims, nth)))
+        return fail(c, LGF_E_INVALID_ARG, "launch shape does not fit this lattice");
+    c->nth_plane = nth;
+    c->tile_bytes = tile_bytes;
+    if (c->use64) {
+        c->d.geo = make_geo<double>(c->p.dims, tile_bytes);
+        if (delta_elems(c->d.geo) > c->d.d_cap) return fail(c, LGF_E_STATE, "Delta buffer too small for the tile");
+    }
+    if (c->use32) {
+        c->f.geo = make_geo<float>(c->p.dims, tile_bytes);
+        if (delta_elems(c->f.geo) > c->f.d_cap) return fail(c, LGF_E_STATE, "Delta buffer too small for the tile");
+    }
+    TRY(set_all_lds(c));
+    for (auto& ex : c->gexec)
+        if (ex) {
+            (void)hipGraphExecDestroy(ex);
+            ex = nullptr;
+        }
+    c->delta_valid = false;
+    return LGF_OK;
+}
+
+template <typename T, int NE>
+int32_t identity_links(lgf_context* c)
+{
+    Bufs<T>& b = bufs<T>(c);
+    const dim3 gr((unsigned)blocks_for(b.geo.V, 256));
+    for (int mu = 0; mu < 4; ++mu)
+        TRY(launch(c, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, b.geo.V, b.geo.VS,
+                   b.U[0] + (int64_t)mu * NE * b.geo.VS));
+    return enqueue_identity_G<T>(c);
+}
+
+std::string tune_key(const lgf_context* c)
+{
+    const int* d = c->p.dims;
+    const std::string k = "single/p" + std::to_string(c->p.precision) + "/s" + std::to_string(c->p.storage) + "/" +
+                          std::to_string(d[0]) + "x" + std::to_string(d[1]) + "x" + std::to_string(d[2]) + "x" +
+                          std::to_string(d[3]);
+    return std::to_string(std::hash<std::string>{}(k));
+}
+
+// Time each candidate launch shape on identity links (the kernels do the
+// same work whatever the values; the state's stop test is off) in the
+// context's first precision phase, and keep the fastest.  The choice is
+// cached per shape in the file named by $LGF_TUNE_CACHE, if set.
+int32_t autotune(lgf_context* c)
+{
+    const char* cache = std::getenv("LGF_TUNE_CACHE");
+    const std::string key = tune_key(c);
+    if (cache) {
+        std::ifstream in(cache);
+        std::string k;
+        int nth, tb;
+        while (in >> k >> nth >> tb)
+            if (k == key) return configure(c, nth, tb);
+    }
+    if (c->phase == 1) TRY(c->NE == 9 ? (identity_links<double, 9>(c)) : (identity_links<double, 6>(c)));
+    else TRY(c->NE == 9 ? (identity_links<float, 9>(c)) : (identity_links<float, 6>(c)));
+    const int np = c->p.dims[0] * c->p.dims[1];
+    std::vector<std::pair<int, int>> cand;
+    for (int nth : {64, 128, 256})
+        if (nth <= std::max(64, np) && (!c->use64 || shape_fits<double>(c->p.dims, nth)) &&
+            (!c->use32 || shape_fits<float>(c->p.dims, nth)))
+            for (int tb : kTileChoices) cand.push_back({nth, tb});
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, LGF_E_DEVICE, "hipEventCreate failed");
+    }
+    float best = 1e30f;
+    std::pair<int, int> pick{c->nth_plane, c->tile_bytes};
+    const int saved_profile = c->profile;
+    c->profile = 0;
+    int32_t rc = LGF_OK;
+    for (auto& cd : cand) {
+        if ((rc = configure(c, cd.first, cd.second)) != LGF_OK) break;
+        if ((rc = launch(c, K_STATE, k_state_init, dim3(1), dim3(1), 0, c->st, c->phase)) != LGF_OK) break;
+        if ((rc = measure_any(c, nullptr)) != LGF_OK) break;
+        for (int k = 0; k < 2 && rc == LGF_OK; ++k) rc = update_any(c, nullptr);
+        if (rc != LGF_OK) break;
+        (void)hipEventRecord(e0, c->stream);
+        for (int k = 0; k < 6 && rc == LGF_OK; ++k) rc = update_any(c, nullptr);
+        if (rc != LGF_OK) break;
+        (void)hipEventRecord(e1, c->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(c, LGF_E_DEVICE, "tuning run failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            pick = cd;
+        }
+    }
+    c->profile = saved_profile;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TRY(rc);
+    if (cache) {
+        std::ofstream out(cache, std::ios::app);
+        out << key << " " << pick.first << " " << pick.second << "\n";
+    }
+    return configure(c, pick.first, pick.second);
 }
 
 int32_t check_ctx(lgf_context* c, bool need_loaded)
@@ -662,8 +795,8 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
         }
         c->own_stream = true;
     }
-    if (use64 && (rc = alloc_bufs<double>(c, p->dims, c->NE, c->track, 64, c->d, c->bytes)) != LGF_OK) return bail(rc);
-    if (use32 && (rc = alloc_bufs<float>(c, p->dims, c->NE, c->track, 64, c->f, c->bytes)) != LGF_OK) return bail(rc);
+    if (use64 && (rc = alloc_bufs<double>(c, p->dims, c->NE, c->track, kDefaultTileBytes, c->d, c->bytes)) != LGF_OK) return bail(rc);
+    if (use32 && (rc = alloc_bufs<float>(c, p->dims, c->NE, c->track, kDefaultTileBytes, c->f, c->bytes)) != LGF_OK) return bail(rc);
     const Geo& g = use64 ? c->d.geo : c->f.geo;
     if (p->precision == LGF_MIXED) {
         const size_t link = sizeof(C2<double>) * (size_t)4 * c->NE * c->d.geo.VS;
@@ -687,18 +820,8 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
     }
     std::memset(c->st_host, 0, sizeof(DevState));
     if (hipMalloc(&c->check, sizeof(unsigned long long) * 3) != hipSuccess) { c->err = "hipMalloc check"; return bail(LGF_E_OUT_OF_MEMORY); }
-    for (int lm : {64, 128}) {
-        if (use64) {
-            rc = c->NE == 9 ? (lm == 64 ? set_lds_attrs<double, 9, 64>(c) : set_lds_attrs<double, 9, 128>(c))
-                            : (lm == 64 ? set_lds_attrs<double, 6, 64>(c) : set_lds_attrs<double, 6, 128>(c));
-            if (rc != LGF_OK) return bail(rc);
-        }
-        if (use32) {
-            rc = c->NE == 9 ? (lm == 64 ? set_lds_attrs<float, 9, 64>(c) : set_lds_attrs<float, 9, 128>(c))
-                            : (lm == 64 ? set_lds_attrs<float, 6, 64>(c) : set_lds_attrs<float, 6, 128>(c));
-            if (rc != LGF_OK) return bail(rc);
-        }
-    }
+    if ((rc = set_all_lds(c)) != LGF_OK) return bail(rc);
+    if (p->autotune && (rc = autotune(c)) != LGF_OK) return bail(rc);
     if ((rc = launch(c, K_STATE, k_state_init, dim3(1), dim3(1), 0, c->st, c->phase)) != LGF_OK) return bail(rc);
     if ((rc = sync_state(c)) != LGF_OK) return bail(rc);
     *out = c;
@@ -1069,6 +1192,14 @@ int32_t lgf_profile_reset(lgf_ctx c)
         c->prof_n[k] = 0;
         c->prof_ms[k] = 0.0;
     }
+    return LGF_OK;
+}
+
+int32_t lgf_config(lgf_ctx c, int32_t* plane_threads, int32_t* tile_bytes)
+{
+    if (!c) return LGF_E_INVALID_ARG;
+    if (plane_threads) *plane_threads = c->nth_plane;
+    if (tile_bytes) *tile_bytes = c->tile_bytes;
     return LGF_OK;
 }
 

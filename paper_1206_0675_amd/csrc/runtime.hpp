@@ -212,6 +212,11 @@ inline int64_t delta_elems(const Geo& g) { return (int64_t)(g.NP / g.W) * 4 * g.
 // Tile widths (bytes) a geometry may be rebuilt with after allocation.
 constexpr int kTileChoices[3] = {32, 64, 128};
 
+// Default tile width of a single-lattice context: 128 bytes is one cache line
+// of every (z, t) tile row, so the plane kernels write and read whole lines
+// of Delta (fastest of the three choices at 32^4 in FP64 and 12 reals).
+constexpr int kDefaultTileBytes = 128;
+
 // Delta capacity that holds the layout of every tile choice (smaller tiles
 // mean more chunks and so more padding).
 template <typename T>

@@ -89,6 +89,7 @@ def load_library(path: str | None = None):
         "lgf_profile_reset": ([V], I32),
         "lgf_kernel_name": ([I32], C.c_char_p),
         "lgf_device_bytes": ([V, C.POINTER(I64)], I32),
+        "lgf_config": ([V, C.POINTER(I32), C.POINTER(I32)], I32),
         "lgf_strerror": ([I32], C.c_char_p),
         "lgf_last_error": ([V], C.c_char_p),
         "lgf_batch_create": ([P, I32, C.POINTER(C.c_int32 * 4), ctx_p], I32),
@@ -270,6 +271,12 @@ class Context:
         b = C.c_int64()
         self._check(self.lib.lgf_device_bytes(self.h, C.byref(b)))
         return b.value
+
+    def config(self):
+        """(threads per plane block, tile bytes) the context runs with."""
+        a, b = C.c_int32(), C.c_int32()
+        self._check(self.lib.lgf_config(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
 
 class Batch:

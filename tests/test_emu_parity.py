@@ -135,7 +135,8 @@ L = lgf.load_library({lib!r})
 for dims, kw in [((4, 4, 4, 4), {{"max_iter": 4}}), ((8, 4, 4, 8), {{"storage": 12, "max_iter": 4}}),
                  ((4, 8, 4, 4), {{"precision": 2, "poll_every": 4, "theta_switch": 1.0, "max_iter": 8}}),
                  ((4, 4, 8, 4), {{"precision": 1, "track_gauge": 1, "max_iter": 4}}),
-                 ((4, 4, 32, 32), {{"storage": 12, "max_iter": 3}})]:
+                 ((4, 4, 32, 32), {{"storage": 12, "max_iter": 3}}),
+                 ((16, 8, 4, 4), {{"storage": 12, "autotune": 1, "max_iter": 3}})]:
     ctx = lgf.Context(dims, lib=L, **kw)
     ctx.load(synth.random_links(dims, 5))
     ctx.step(2, trace=True)
@@ -191,6 +192,36 @@ def test_emulated_batch_mixed_autotuned(E, oracle_lib):
             assert np.max(np.abs(oracle.transform(d, U, G) - b.store(i))) <= 1e-12
     outs, sts, rc = lgf.fix_batch(Us, lib=E, poll_every=4)
     assert rc == lgf.OK and all(s.theta < 1e-15 for s in sts)
+
+
+def test_emulated_single_autotune_and_forced_shapes(E, oracle_lib, tmp_path, monkeypatch):
+    """lgf_params.autotune on a single lattice picks one of the candidate
+    launch shapes and caches it; a cached shape is taken as is; every shape
+    gives bit-identical links (the arithmetic per element does not depend on
+    the launch shape), equal to the oracle's."""
+    dims = (16, 8, 4, 4)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LGF_TUNE_CACHE", str(cache))
+    U = synth.random_links(dims, 5)
+    with lgf.Context(dims, lib=E, storage=12, autotune=1) as c:
+        picked = c.config()
+    key, nth, tb = cache.read_text().split()
+    assert (int(nth), int(tb)) == picked and picked[0] in (64, 128) and picked[1] in (32, 64, 128)
+    Uo = oracle.step(dims, U, 3)[0]
+    ref = None
+    for shape in [(n, t) for n in (64, 128) for t in (32, 64, 128)]:
+        cache.write_text(f"{key} {shape[0]} {shape[1]}\n")
+        with lgf.Context(dims, lib=E, storage=12, autotune=1) as c:
+            assert c.config() == shape
+            c.load(U)
+            c.step(3)
+            out = c.store()
+        assert np.max(np.abs(out - Uo)) <= 1e-12
+        if ref is None:
+            ref = out
+        assert np.array_equal(out, ref), shape
+    with lgf.Context(dims, lib=E, storage=12) as c:
+        assert c.config() == (128, 128)
 
 
 # ---------------------------------------------------------------------------

@@ -288,3 +288,34 @@ def test_graph_replay_matches_eager(L):
             sg = g.fix()
             assert sg.iter == se.iter and sg.F == se.F and sg.theta == se.theta
             assert np.array_equal(g.store(), ref)
+
+
+@pytest.mark.parametrize("dims, kw", [((32, 32, 8, 8), {"storage": 12}), ((16, 16, 16, 16), {"precision": lgf.MIXED})])
+def test_autotuned_shape_gives_the_same_links(L, oracle_lib, dims, kw, tmp_path, monkeypatch):
+    """The autotuner's pick, and a forced (64 threads, 32-byte tile) shape,
+    give exactly the links of the default launch shape; FP64 links match the
+    oracle."""
+    monkeypatch.setenv("LGF_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    U = links(dims, 3)
+    announce(f"autotune {dims} {kw}")
+    outs = []
+    with lgf.Context(dims, lib=L, autotune=1, **kw) as c:
+        cfg = c.config()
+        assert cfg[0] in (64, 128, 256) and cfg[1] in (32, 64, 128)
+        c.load(U)
+        c.step(4)
+        outs.append(c.store())
+    key = (tmp_path / "tune.txt").read_text().split()[0]
+    (tmp_path / "tune.txt").write_text(f"{key} 64 32\n")
+    with lgf.Context(dims, lib=L, autotune=1, **kw) as c:
+        assert c.config() == (64, 32)
+        c.load(U)
+        c.step(4)
+        outs.append(c.store())
+    with lgf.Context(dims, lib=L, **kw) as c:
+        c.load(U)
+        c.step(4)
+        outs.append(c.store())
+    assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[2])
+    if not kw.get("precision"):
+        assert rel(outs[2], oracle.step(dims, U, 4)[0]) <= 1e-12
