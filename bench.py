@@ -35,15 +35,16 @@ PAPER_C2070_ITERS_PER_S = 16.35    # 32^4, DP, 12-real, texture, ECC off (Table 
 def alg_bytes(V, s, R):
     """Algorithmic HBM bytes: per iteration and per launch of each kernel.
 
-    Per site and iteration: links read and written once (8R reals), g written
-    and read once (2R), the packed Delta (8 reals) written once, read and
-    written once by the (z, t) pass, and read once for g (32 reals).
+    Per site and iteration: links read and written once (8R reals); the
+    packed Delta (8 reals) written once, read and written once by the (z, t)
+    pass, and read once for g (32 reals); g, kept as its 8-real generator,
+    written once and read once (16 reals).
     """
     return {
-        "iteration": V * s * (8 * R + 2 * R + 32),
-        "transform_measure": V * s * (4 * R + 4 * R + R + 8),
+        "iteration": V * s * (8 * R + 32 + 16),
+        "transform_measure": V * s * (4 * R + 4 * R + 8 + 8),
         "zt_fft_scale": V * s * 16,
-        "gauge": V * s * (8 + R),
+        "gauge": V * s * (8 + 8),
     }
 
 

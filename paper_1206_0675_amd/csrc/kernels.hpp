@@ -8,9 +8,10 @@
 //                       the forward 2D FFT over each (x, y) plane in LDS.
 //   k_zt                forward 2D FFT over (z, t), multiply by
 //                       (alpha/2) p2max / (p^2 V) (eq. gx), inverse (z, t).
-//   k_gauge             inverse 2D FFT over (x, y) and
-//                       g = reunit(1 + (alpha/2) dtilde), stored for the
-//                       next k_measure (optionally G <- g G).
+//   k_gauge             inverse 2D FFT over (x, y); dtilde (scaled by
+//                       alpha/2) is stored in site order for the next
+//                       k_measure, which rebuilds g = reunit(1 + dtilde)
+//                       wherever it reads g (optionally G <- g G here).
 //   k_reduce            F and theta from per-plane partial sums, in a fixed
 //                       order; sets the convergence flag.
 // Every kernel returns at once when the device flag `done` is set, so
@@ -251,7 +252,7 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc.c[c] = mk<T>(T(0), T(0));
         M3<T> gx;
-        if (APPLY_G) load_mat<T, NE>(gx, g, VS, s);
+        if (APPLY_G) load_gauge<T, NE>(gx, g, VS, s);
         double f = 0.0;
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
@@ -259,7 +260,7 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
             load_mat<T, NE>(u, Uin + (int64_t)mu * NE * VS, VS, s);
             if (APPLY_G) {
                 M3<T> gn, r;
-                load_mat<T, NE>(gn, g, VS, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
+                load_gauge<T, NE>(gn, g, VS, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
                 a_u_bdag<T, (NE == 6 ? 2 : 3)>(gx, u, gn, r);
                 store_mat<T, NE>(r, Uout + (int64_t)mu * NE * VS, VS, s);
                 u = r;
@@ -274,7 +275,7 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
             load_mat<T, NE>(u, Uin + (int64_t)nu * NE * VS, VS, sb);
             if (APPLY_G) {
                 M3<T> gb, r;
-                load_mat<T, NE>(gb, g, VS, sb);
+                load_gauge<T, NE>(gb, g, VS, sb);
                 a_u_bdag<T, (NE == 6 ? 2 : 3)>(gb, u, gx, r);
                 u = r;
             }
@@ -386,8 +387,9 @@ __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, co
 }
 
 // ---------------------------------------------------------------------------
-// a5(x, y) + a6 (+ a8) for one plane q: inverse (x, y) FFT,
-// g = reunit(1 + dtilde) in FP64, optionally G <- reunit(g G).
+// a5(x, y) + a6 (+ a8) for one plane q: inverse (x, y) FFT; dtilde is
+// stored as the generator of g = reunit(1 + dtilde) (load_gauge rebuilds g
+// in FP64 where it is read); optionally G <- reunit(g G).
 // ---------------------------------------------------------------------------
 template <typename T, int NE, bool ACC_G, int LMAX>
 __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, C2<T>* __restrict__ g,
@@ -406,14 +408,15 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
     fft_inv<T, LMAX>(buf, geo.L[0], Lines{geo.logL[1], 2, geo.L[0], NP, 1}, twx, tid, nth);
     const int64_t q0 = (int64_t)q * NP;
     for (int p = tid; p < NP; p += nth) {
-        C2<double> c[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) c[k] = mk<double>((double)buf[k * NP + p].x, (double)buf[k * NP + p].y);
-        M3<double> m;
-        one_plus_alg_reunit(c, m);
         const int64_t s = q0 + p;
-        store_mat<T, NE>(cast_mat<T>(m), g, VS, s);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g[k * VS + s] = buf[k * NP + p];      // g kept as its generator
         if (ACC_G) {
+            C2<double> c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = mk<double>((double)buf[k * NP + p].x, (double)buf[k * NP + p].y);
+            M3<double> m;
+            one_plus_alg_reunit(c, m);
             M3<T> Gt;
             load_mat<T, NE>(Gt, G, VS, s);
             M3<double> Gd = cast_mat<double>(Gt), r;

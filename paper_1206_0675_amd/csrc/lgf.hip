@@ -4,7 +4,8 @@
 //   U[2]  links, structure of arrays, NE complex per link (ping-pong: the
 //         transform reads U[cur] and writes U[1-cur]; the neighbour reads of
 //         the fused kernel need the old links intact)
-//   g     the gauge transformation of the iteration in flight
+//   g     the gauge transformation of the iteration in flight, kept as its
+//         generator dtilde (4 complex per site) and rebuilt where read
 //   D     the packed Delta field (4 complex per site) in the tiled layout
 //   G     the accumulated gauge (when tracked)
 //   tw    FFT twiddles W_L^k for the four extents

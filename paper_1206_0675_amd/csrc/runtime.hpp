@@ -164,7 +164,7 @@ inline double now_s()
 template <typename T>
 struct Bufs {
     C2<T>* U[2] = {nullptr, nullptr};
-    C2<T>* g = nullptr;
+    C2<T>* g = nullptr;      // g = reunit(1 + dtilde) as dtilde: 4 complex per site
     C2<T>* D = nullptr;
     C2<T>* G = nullptr;
     C2<T>* tw = nullptr;     // Lx + Ly + Lz + Lt entries
@@ -282,9 +282,10 @@ int32_t alloc_bufs(Runner* c, const int32_t* dims, int NE, bool track, int tile_
     const size_t dbytes = sizeof(C2<T>) * (size_t)b.d_cap;
     HIPCHK(c, hipMalloc(&b.U[0], link));
     HIPCHK(c, hipMalloc(&b.U[1], link));
-    HIPCHK(c, hipMalloc(&b.g, field));
+    const size_t gen = sizeof(C2<T>) * (size_t)4 * VS;     // g as its 4 packed generator fields
+    HIPCHK(c, hipMalloc(&b.g, gen));
     HIPCHK(c, hipMalloc(&b.D, dbytes));
-    bytes += 2 * link + field + dbytes;
+    bytes += 2 * link + gen + dbytes;
     if (track) {
         HIPCHK(c, hipMalloc(&b.G, field));
         bytes += field;
