@@ -113,8 +113,8 @@ int32_t build_tables(lgf_batch* b)
         c.c0 = b->m[i].c0;
         c.accel = b->p.accel == LGF_ACCEL_FOURIER;
         for (int j = 0; j < (g.NP / g.W) * 4; ++j) zt.push_back(((uint32_t)i << kItemShift) | (uint32_t)j);
-        lm = std::max(lm, 4 * (size_t)g.NP * sizeof(C2<T>) + 2 * (size_t)b->nth_plane * sizeof(double));
-        lg = std::max(lg, 4 * (size_t)g.NP * sizeof(C2<T>));
+        lm = std::max(lm, (size_t)plane_lds_elems(g) * sizeof(C2<T>) + 2 * (size_t)b->nth_plane * sizeof(double));
+        lg = std::max(lg, (size_t)plane_lds_elems(g) * sizeof(C2<T>));
         lz = std::max(lz, (size_t)g.NQ * g.W * sizeof(C2<T>));
     }
     BatchCfg<T>*& dc = dcfg<T>(b);

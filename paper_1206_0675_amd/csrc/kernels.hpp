@@ -41,7 +41,17 @@ struct Geo {
                     // (which would map them onto the same cache sets and channels)
     int64_t DS;     // stride between the (tile, field) chunks of the Delta layout:
                     // NQ * W plus a pad, for the same reason
+    int RP, NPP;    // LDS copy of an (x, y) plane: row pitch Lx + 1 and field
+                    // pitch Ly * RP (complex); the extra element per row moves
+                    // consecutive rows to other banks for the x-axis FFT passes
 };
+
+// Complex elements of LDS for the four fields of one (x, y) plane.
+__host__ __device__ __forceinline__ int plane_lds_elems(const Geo& g) { return 4 * g.NPP; }
+__host__ __device__ __forceinline__ int plane_lds_index(const Geo& g, int c, int p)
+{
+    return c * g.NPP + (p >> g.logL[0]) * g.RP + (p & (g.L[0] - 1));
+}
 
 // Per-configuration state on the device.  The host reads it back only at
 // poll points; kernels of an iteration skip a configuration whose `done` is
@@ -224,7 +234,7 @@ __global__ void __launch_bounds__(256) k_field_identity(int64_t V, int64_t VS, C
 // ---------------------------------------------------------------------------
 // a1 + a2 + a3(x, y) for one (z, t) plane q: gauge transform, Delta, F and
 // theta terms, forward (x, y) FFT of the packed Delta into D.
-//   red: 2 * blockDim doubles of LDS; buf: 4 * NP complex of LDS.
+//   red: 2 * blockDim doubles of LDS; buf: plane_lds_elems(geo) complex of LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int NE, bool APPLY_G, int LMAX>
 __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ Uin, C2<T>* __restrict__ Uout,
@@ -284,7 +294,7 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
         fsum += f;
         tsum += alg_norm2(acc);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) buf[c * NP + p] = acc.c[c];
+        for (int c = 0; c < 4; ++c) buf[plane_lds_index(geo, c, p)] = acc.c[c];
     }
     double fb, tb;
     block_sum2(fsum, tsum, red, tid, nth, &fb, &tb);
@@ -293,12 +303,13 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
         partial[2 * q + 1] = tb;
     }
     // forward FFT along x, then y, of the four fields
-    fft_fwd<T, LMAX>(buf, Lx, Lines{geo.logL[1], 2, Lx, NP, 1}, twx, tid, nth);
-    fft_fwd<T, LMAX>(buf, Ly, Lines{geo.logL[0], 2, 1, NP, Lx}, twy, tid, nth);
+    fft_fwd<T, LMAX>(buf, Lx, Lines{geo.logL[1], 2, geo.RP, geo.NPP, 1}, twx, tid, nth);
+    fft_fwd<T, LMAX>(buf, Ly, Lines{geo.logL[0], 2, 1, geo.NPP, geo.RP}, twy, tid, nth);
     const int W = geo.W;
     for (int i = tid; i < 4 * NP; i += nth) {
         const int c = i >> geo.logNP, p = i & (NP - 1);
-        D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))] = buf[i];
+        D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))] =
+            buf[plane_lds_index(geo, c, p)];
     }
 }
 
@@ -401,20 +412,23 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
     const int64_t VS = geo.VS;
     for (int i = tid; i < 4 * NP; i += nth) {
         const int c = i >> geo.logNP, p = i & (NP - 1);
-        buf[i] = D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))];
+        buf[plane_lds_index(geo, c, p)] = D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))];
     }
     __syncthreads();
-    fft_inv<T, LMAX>(buf, geo.L[1], Lines{geo.logL[0], 2, 1, NP, geo.L[0]}, twy, tid, nth);
-    fft_inv<T, LMAX>(buf, geo.L[0], Lines{geo.logL[1], 2, geo.L[0], NP, 1}, twx, tid, nth);
+    fft_inv<T, LMAX>(buf, geo.L[1], Lines{geo.logL[0], 2, 1, geo.NPP, geo.RP}, twy, tid, nth);
+    fft_inv<T, LMAX>(buf, geo.L[0], Lines{geo.logL[1], 2, geo.RP, geo.NPP, 1}, twx, tid, nth);
     const int64_t q0 = (int64_t)q * NP;
     for (int p = tid; p < NP; p += nth) {
         const int64_t s = q0 + p;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) g[k * VS + s] = buf[k * NP + p];      // g kept as its generator
+        for (int k = 0; k < 4; ++k) g[k * VS + s] = buf[plane_lds_index(geo, k, p)];   // g kept as its generator
         if (ACC_G) {
             C2<double> c[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) c[k] = mk<double>((double)buf[k * NP + p].x, (double)buf[k * NP + p].y);
+            for (int k = 0; k < 4; ++k) {
+                const C2<T> v = buf[plane_lds_index(geo, k, p)];
+                c[k] = mk<double>((double)v.x, (double)v.y);
+            }
             M3<double> m;
             one_plus_alg_reunit(c, m);
             M3<T> Gt;

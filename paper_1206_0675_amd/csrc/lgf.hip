@@ -140,8 +140,8 @@ template <typename T, int NE, int LMAX>
 int32_t set_lds_attrs(lgf_context* c)
 {
     const Geo& g = bufs<T>(c).geo;
-    const int mlds = (int)(4 * g.NP * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double));
-    const int glds = (int)(4 * g.NP * sizeof(C2<T>));
+    const int mlds = (int)(plane_lds_elems(g) * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double));
+    const int glds = (int)(plane_lds_elems(g) * sizeof(C2<T>));
     const int zlds = (int)((size_t)g.NQ * g.W * sizeof(C2<T>));
     HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, false, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, mlds));
@@ -165,7 +165,7 @@ int32_t enqueue_measure(lgf_context* c, double* trace_slot)
 {
     Bufs<T>& b = bufs<T>(c);
     const Geo& g = b.geo;
-    const size_t lds = 4 * g.NP * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double);
+    const size_t lds = plane_lds_elems(g) * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double);
     TRY(launch(c, K_MEASURE, k_measure<T, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), lds, g,
                b.U[0], b.U[1], (const C2<T>*)nullptr, b.D, c->partial,
                (const C2<T>*)(b.tw + b.tw_off[0]), (const C2<T>*)(b.tw + b.tw_off[1]), (const DevState*)c->st));
@@ -187,7 +187,7 @@ int32_t enqueue_update(lgf_context* c, double* trace_slot)
     Bufs<T>& b = bufs<T>(c);
     const Geo& g = b.geo;
     const size_t zlds = (size_t)g.NQ * g.W * sizeof(C2<T>);
-    const size_t glds = 4 * g.NP * sizeof(C2<T>);
+    const size_t glds = plane_lds_elems(g) * sizeof(C2<T>);
     const size_t mlds = glds + 2 * c->nth_plane * sizeof(double);
     const C2<T>* twx = b.tw + b.tw_off[0];
     const C2<T>* twy = b.tw + b.tw_off[1];
@@ -583,7 +583,7 @@ int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double*
     const Geo& g = b.geo;
     const C2<double>* twx = b.tw + b.tw_off[0];
     const C2<double>* twy = b.tw + b.tw_off[1];
-    const size_t glds = 4 * g.NP * sizeof(C2<double>);
+    const size_t glds = plane_lds_elems(g) * sizeof(C2<double>);
     TRY(launch(c, K_ZT_INV, k_zt_inv_scaled<double, LMAX>, dim3((g.NP / g.W) * 4), dim3(512),
                (size_t)g.NQ * g.W * sizeof(C2<double>), g, (const C2<double>*)c->D2, c->D3,
                (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),

@@ -201,6 +201,8 @@ Geo make_geo(const int32_t* dims, int tile_bytes = 64)
     while (W > 1 && (size_t)W * g.NQ * sizeof(C2<T>) > kMaxLdsZt) W >>= 1;
     g.W = W;
     g.logW = ilog2(W);
+    g.RP = g.L[0] + 1;
+    g.NPP = g.L[1] * g.RP;
     g.VS = g.V + (int64_t)(kComponentPadBytes / sizeof(C2<T>));
     g.DS = (int64_t)g.NQ * W + (int64_t)(kChunkPadBytes / sizeof(C2<T>));
     return g;
@@ -230,8 +232,8 @@ int64_t delta_capacity(const int32_t* dims, int tile_bytes)
 template <typename T>
 bool shape_fits(const int32_t* dims, int nth)
 {
-    const size_t np = (size_t)dims[0] * dims[1], nq = (size_t)dims[2] * dims[3];
-    if (4 * np * sizeof(C2<T>) + 2 * nth * sizeof(double) > kMaxLds) return false;
+    const size_t npp = (size_t)(dims[0] + 1) * dims[1], nq = (size_t)dims[2] * dims[3];   // padded plane in LDS
+    if (4 * npp * sizeof(C2<T>) + 2 * nth * sizeof(double) > kMaxLds) return false;
     if (nq * sizeof(C2<T>) > kMaxLdsZt) return false;
     return true;
 }
