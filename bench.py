@@ -12,7 +12,9 @@ HBM.  Printed as one JSON line:
                  algorithmic bytes per launch / its mean duration from HIP
                  events on the library's stream in a second, profiled pass
   time_to_theta  wall time of lgf_fix to theta < 1e-15 for FP64 (12- and
-                 18-real) and mixed FP32/FP64, from freshly loaded links
+                 18-real) and mixed FP32/FP64, from freshly loaded links:
+                 best of three fixes on one context (the first, which also
+                 captures the context's graphs, is reported beside it)
   cpu_baseline   the FP64 oracle on this host's cores, a bounded sample
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -35,16 +37,18 @@ PAPER_C2070_ITERS_PER_S = 16.35    # 32^4, DP, 12-real, texture, ECC off (Table 
 def alg_bytes(V, s, R):
     """Algorithmic HBM bytes: per iteration and per launch of each kernel.
 
-    Per site and iteration: links read and written once (8R reals); the
-    packed Delta (8 reals) written once, read and written once by the (z, t)
-    pass, and read once for g (32 reals); g, kept as its 8-real generator,
-    written once and read once (16 reals).
+    The links are G U0 G^dag(x+mu), formed where needed from the loaded links
+    U0 and the accumulated gauge G and never stored.  Per site and iteration:
+    U0 read once (4R reals) and G read once (R) by the transform; the packed
+    Delta (8 reals) written once, read and written once by the (z, t) pass,
+    and read once by the gauge kernel (32 reals); G read and written once by
+    the gauge kernel (2R).
     """
     return {
-        "iteration": V * s * (8 * R + 32 + 16),
-        "transform_measure": V * s * (4 * R + 4 * R + 8 + 8),
+        "iteration": V * s * (7 * R + 32),
+        "transform_measure": V * s * (4 * R + R + 8),
         "zt_fft_scale": V * s * 16,
-        "gauge": V * s * (8 + 8),
+        "gauge": V * s * (8 + 2 * R),
     }
 
 
@@ -222,12 +226,15 @@ def main():
                           ("mixed_12real", dict(storage=12, precision=lgf.MIXED)),
                           ("mixed_18real", dict(storage=18, precision=lgf.MIXED))):
             with lgf.Context(dims, lib=L, poll_every=8, **kw) as ctx:
-                ctx.load(U)
-                ctx.measure()
-                torch.cuda.synchronize()
-                s = ctx.fix()
-            extras[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "iters_fp32": s.iter_fp32,
-                             "F": s.F, "theta": s.theta}
+                runs = []
+                for _ in range(3):         # the first fix also captures the context's graphs
+                    ctx.load(U)
+                    ctx.measure()
+                    torch.cuda.synchronize()
+                    runs.append(ctx.fix())
+            s = min(runs, key=lambda r: r.seconds)
+            extras[label] = {"seconds": round(s.seconds, 5), "first_seconds": round(runs[0].seconds, 5),
+                             "iters": s.iter, "iters_fp32": s.iter_fp32, "F": s.F, "theta": s.theta}
 
     # ---- learned vs plain step: time to theta < 1e-15 on 32^3 x 64 ----------
     learned = None
@@ -242,10 +249,13 @@ def main():
                 with lgf.Context(ld, lib=L, storage=12, poll_every=8, **kw) as ctx:
                     if kw:
                         ctx.set_model(blob)
-                    ctx.load(Ul)
-                    ctx.measure()
-                    torch.cuda.synchronize()
-                    s = ctx.fix()
+                    tries = []
+                    for _ in range(2):     # the first fix also captures the context's graphs
+                        ctx.load(Ul)
+                        ctx.measure()
+                        torch.cuda.synchronize()
+                        tries.append(ctx.fix())
+                    s = min(tries, key=lambda r: r.seconds)
                 rec[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "fallbacks": s.fallbacks, "F": s.F,
                               "theta": s.theta}
             rec["F_diff"] = abs(rec["learned"]["F"] - rec["plain"]["F"])

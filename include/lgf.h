@@ -89,8 +89,8 @@ typedef struct lgf_params {
     int32_t storage;        /* LGF_STORE18 | LGF_STORE12                                 */
     int32_t step;           /* LGF_STEP_PLAIN                                            */
     int32_t accel;          /* LGF_ACCEL_FOURIER | LGF_ACCEL_NONE                        */
-    int32_t track_gauge;    /* 1: accumulate G = ... g2 g1 so that U = G U0 G^dag(x+mu)
-                               (always on in LGF_MIXED); needed by lgf_store_gauge      */
+    int32_t track_gauge;    /* ignored: the accumulated G = ... g2 g1 (U = G U0 G^dag(x+mu))
+                               is always kept; the iteration is carried in it          */
     int32_t profile;        /* 1: time every kernel launch with HIP events               */
     double alpha;           /* step size, paper: 0.08                                    */
     double theta_stop;      /* stop when theta < theta_stop, paper: 1e-15                */
@@ -146,12 +146,15 @@ int32_t lgf_destroy(lgf_ctx ctx);
  * until the next successful load). */
 int32_t lgf_load_links(lgf_ctx ctx, const void *links, int32_t where);
 
-/* Copy the current links out in canonical FP64. */
+/* Copy the current links G(x) U0(x) G^dag(x+mu) out in canonical FP64
+ * (formed on the device from the loaded links and the accumulated gauge). */
 int32_t lgf_store_links(lgf_ctx ctx, void *links, int32_t where);
 
 /* Accumulated gauge transformation G (18 doubles per site), such that the
- * current links are G(x) U0(x) G^dag(x+mu) for the loaded links U0.  Needs
- * track_gauge or LGF_MIXED.  lgf_load_gauge replaces G (checkpoint resume). */
+ * current links are G(x) U0(x) G^dag(x+mu) for the loaded links U0.
+ * lgf_load_gauge replaces G, so the links become G U0 G^dag(x+mu) for the
+ * links last loaded: loading the same U0 and a stored G resumes a run bit
+ * for bit (checkpoint = U0 + G).  G must be SU(3) to the precision in use. */
 int32_t lgf_store_gauge(lgf_ctx ctx, void *G, int32_t where);
 int32_t lgf_load_gauge(lgf_ctx ctx, const void *G, int32_t where);
 

@@ -1,16 +1,17 @@
 // Batched gauge fixing (lgf_batch_* in include/lgf.h): many lattices of
 // different shapes iterated together.
 //
-// Each member owns the buffers of a single-lattice context (links ping-pong,
-// g, packed Delta, accumulated gauge, in FP32 and/or FP64) plus a device
-// state.  One batch iteration is a fixed sequence of launches, each covering
+// Each member owns the buffers of a single-lattice context (its loaded
+// links U0, the accumulated gauge G as a pair of buffers, packed Delta, in
+// FP32 and/or FP64) plus a device state.  As for a single lattice, the links
+// are G U0 G^dag(x+mu), formed where needed and never stored.  One batch iteration is a fixed sequence of launches, each covering
 // every member through a work list of (member, plane) or (member, tile,
 // field) items walked by a persistent grid:
-//   [mixed]  promote G, rebuild U64 = G U0 G^dag, enter FP64 (members whose
-//            FP32 phase just ended)
+//   [mixed]  promote G to FP64 and enter FP64 (members whose FP32 phase
+//            just ended); the FP64 links are G U0 G^dag from the loaded links
 //   per precision phase P in use:
 //            measure + reduce (members that need Delta of fresh links),
-//            (z,t) pass, (x,y)-inverse + g, transform + measure, reduce
+//            (z,t) pass, (x,y)-inverse + G update, transform + measure, reduce
 // Kernels skip members that are done, in the other phase, or mid-switch, so
 // one iteration applies at most one gauge transformation to each member and
 // members converge and change precision independently.  poll_every
@@ -40,7 +41,6 @@ struct lgf_batch : Runner {
     struct Member {
         Bufs<double> d;
         Bufs<float> f;
-        C2<double>* U0 = nullptr;
         double* ptab = nullptr;
         double* partial = nullptr;
         double c0 = 0.0;
@@ -55,7 +55,6 @@ struct lgf_batch : Runner {
     uint32_t* items_zt64 = nullptr;
     uint32_t* items_zt32 = nullptr;
     int n_plane = 0, n_zt64 = 0, n_zt32 = 0;
-    C2<double>** dU0 = nullptr;
     unsigned long long* check = nullptr;
     int nth_plane = 256, tile_bytes = 64, ncu = 256;
     size_t lds_m[2] = {0, 0}, lds_g[2] = {0, 0}, lds_z[2] = {0, 0};   // [0] FP32, [1] FP64
@@ -101,11 +100,10 @@ int32_t build_tables(lgf_batch* b)
         if (delta_elems(g) > bf.d_cap) return fail(b, LGF_E_STATE, "Delta buffer too small for this tile width");
         BatchCfg<T>& c = host[i];
         c.geo = g;
-        c.U[0] = bf.U[0];
-        c.U[1] = bf.U[1];
-        c.g = bf.g;
+        c.U = bf.U;
+        c.G[0] = bf.G;
+        c.G[1] = bf.Gb;
         c.D = bf.D;
-        c.G = bf.G;
         for (int k = 0; k < 4; ++k) c.tw[k] = bf.tw + bf.tw_off[k];
         c.ptab = b->m[i].ptab;
         c.partial = b->m[i].partial;
@@ -203,8 +201,6 @@ int32_t iteration_t(lgf_batch* b)
         const dim3 gp(grid_for(b, b->n_plane, 4));
         TRY(launch(b, K_SWITCH, kb_promote<NE>, gp, dim3(256), 0, (const BatchCfg<float>*)b->c32,
                    (const BatchCfg<double>*)b->c64, (const uint32_t*)b->items_plane, b->n_plane));
-        TRY(launch(b, K_SWITCH, kb_switch<NE>, gp, dim3(256), 0, (const BatchCfg<double>*)b->c64,
-                   (const C2<double>* const*)b->dU0, (const uint32_t*)b->items_plane, b->n_plane));
         TRY(launch(b, K_STATE, kb_switch_done<>, dim3((unsigned)blocks_for(b->n, 64)), dim3(64), 0,
                    (const BatchCfg<double>*)b->c64, b->n));
     }
@@ -274,7 +270,7 @@ int32_t identity_member(lgf_batch* b, int i)
     const dim3 gr((unsigned)blocks_for(V, 256));
     for (int mu = 0; mu < 4; ++mu)
         TRY(launch(b, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, V, bf.geo.VS,
-                   bf.U[0] + (int64_t)mu * NE * bf.geo.VS));
+                   bf.U + (int64_t)mu * NE * bf.geo.VS));
     return launch(b, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, V, bf.geo.VS, bf.G);
 }
 
@@ -378,8 +374,8 @@ int32_t store_member(lgf_batch* b, int i, double* dst)
 {
     Bufs<T>& bf = mbufs<T>(b->m[i]);
     const int64_t V = bf.geo.V;
-    return launch(b, K_STORE, k_store<T, NE>, dim3((unsigned)blocks_for(4 * V, 256)), dim3(256), 0, V, bf.geo.VS,
-                  (const C2<T>*)bf.U[b->st_host[i].cur], dst);
+    return launch(b, K_STORE, k_store_gauged<T, NE>, dim3((unsigned)blocks_for(4 * V, 256)), dim3(256), 0, bf.geo,
+                  (const C2<T>*)bf.U, (const C2<T>*)(b->st_host[i].cur ? bf.Gb : bf.G), dst);
 }
 
 template <typename T, int NE>
@@ -388,7 +384,7 @@ int32_t store_member_gauge(lgf_batch* b, int i, double* dst)
     Bufs<T>& bf = mbufs<T>(b->m[i]);
     const int64_t V = bf.geo.V;
     return launch(b, K_FIELD, k_field_store<T, NE>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V, bf.geo.VS,
-                  (const C2<T>*)bf.G, dst);
+                  (const C2<T>*)(b->st_host[i].cur ? bf.Gb : bf.G), dst);
 }
 
 int32_t check_member(lgf_batch* b, int i)
@@ -409,7 +405,6 @@ int32_t lgf_batch_destroy(lgf_batch_t b)
     for (auto& mm : b->m) {
         free_bufs(mm.d);
         free_bufs(mm.f);
-        (void)hipFree(mm.U0);
         (void)hipFree(mm.ptab);
         (void)hipFree(mm.partial);
     }
@@ -420,7 +415,6 @@ int32_t lgf_batch_destroy(lgf_batch_t b)
     (void)hipFree(b->items_plane);
     (void)hipFree(b->items_zt64);
     (void)hipFree(b->items_zt32);
-    (void)hipFree(b->dU0);
     (void)hipFree(b->check);
     release_events(b);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -503,20 +497,13 @@ int32_t lgf_batch_create(const lgf_params* p, int32_t n, const int32_t (*dims)[4
     std::memset(b->st_host, 0, sizeof(DevState) * n);
     if (hipMalloc(&b->check, sizeof(unsigned long long) * 3) != hipSuccess) { b->err = "hipMalloc check"; return bail(LGF_E_OUT_OF_MEMORY); }
     std::vector<uint32_t> plane_items;
-    std::vector<C2<double>*> u0(n, nullptr);
     for (int i = 0; i < n; ++i) {
         auto& mm = b->m[i];
         const int32_t* d = b->dims[i].data();
-        if (use64) BTRY(alloc_bufs<double>(b, d, b->NE, true, b->tile_bytes, mm.d, b->bytes));
-        if (use32) BTRY(alloc_bufs<float>(b, d, b->NE, true, b->tile_bytes, mm.f, b->bytes));
+        if (use64) BTRY(alloc_bufs<double>(b, d, b->NE, b->tile_bytes, mm.d, b->bytes));
+        if (use32) BTRY(alloc_bufs<float>(b, d, b->NE, b->tile_bytes, mm.f, b->bytes));
         const int64_t V = (int64_t)d[0] * d[1] * d[2] * d[3];
         const int NQ = d[2] * d[3];
-        if (b->mixed) {
-            const size_t link = sizeof(C2<double>) * (size_t)4 * b->NE * mm.d.geo.VS;
-            if (hipMalloc(&mm.U0, link) != hipSuccess) { b->err = "hipMalloc U0"; return bail(LGF_E_OUT_OF_MEMORY); }
-            b->bytes += link;
-            u0[i] = mm.U0;
-        }
         double p2max = 0.0;
         const std::vector<double> pt = momentum_tables(d, &p2max);
         mm.c0 = 0.5 * p->alpha * (p->accel == LGF_ACCEL_FOURIER ? p2max : 1.0) / (double)V;
@@ -533,13 +520,6 @@ int32_t lgf_batch_create(const lgf_params* p, int32_t n, const int32_t (*dims)[4
         hipMemcpy(b->items_plane, plane_items.data(), sizeof(uint32_t) * plane_items.size(), hipMemcpyHostToDevice) != hipSuccess) {
         b->err = "work list";
         return bail(LGF_E_DEVICE);
-    }
-    if (b->mixed) {
-        if (hipMalloc(&b->dU0, sizeof(C2<double>*) * n) != hipSuccess ||
-            hipMemcpy(b->dU0, u0.data(), sizeof(C2<double>*) * n, hipMemcpyHostToDevice) != hipSuccess) {
-            b->err = "U0 table";
-            return bail(LGF_E_DEVICE);
-        }
     }
     BTRY(configure(b, 256, 64));
     if (p->autotune) BTRY(autotune(b));
@@ -580,12 +560,12 @@ int32_t lgf_batch_load(lgf_batch_t b, int32_t i, const void* links, int32_t wher
     do {
         if (hipMemsetAsync(b->check, 0, sizeof(chk), b->stream) != hipSuccess) { rc = fail(b, LGF_E_DEVICE, "memset"); break; }
         if (b->mixed) {
-            rc = b->NE == 9 ? load_member<double, 9>(b, i, s, mm.U0) : load_member<double, 6>(b, i, s, mm.U0);
-            if (rc == LGF_OK) rc = b->NE == 9 ? load_member<float, 9>(b, i, s, mm.f.U[0]) : load_member<float, 6>(b, i, s, mm.f.U[0]);
+            rc = b->NE == 9 ? load_member<double, 9>(b, i, s, mm.d.U) : load_member<double, 6>(b, i, s, mm.d.U);
+            if (rc == LGF_OK) rc = b->NE == 9 ? load_member<float, 9>(b, i, s, mm.f.U) : load_member<float, 6>(b, i, s, mm.f.U);
         } else if (b->use64) {
-            rc = b->NE == 9 ? load_member<double, 9>(b, i, s, mm.d.U[0]) : load_member<double, 6>(b, i, s, mm.d.U[0]);
+            rc = b->NE == 9 ? load_member<double, 9>(b, i, s, mm.d.U) : load_member<double, 6>(b, i, s, mm.d.U);
         } else {
-            rc = b->NE == 9 ? load_member<float, 9>(b, i, s, mm.f.U[0]) : load_member<float, 6>(b, i, s, mm.f.U[0]);
+            rc = b->NE == 9 ? load_member<float, 9>(b, i, s, mm.f.U) : load_member<float, 6>(b, i, s, mm.f.U);
         }
         if (rc != LGF_OK) break;
         const dim3 gr((unsigned)blocks_for(V, 256));

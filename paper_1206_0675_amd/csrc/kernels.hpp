@@ -2,18 +2,20 @@
 // (Algorithm 1 of Cardoso, Silva, Bicudo, Oliveira, arXiv:1206.0675) on a
 // 4D periodic lattice, for gfx950.
 //
+// The gauge transformations of the iteration compose (Section 2): after n
+// steps the links are G U0 G^dag(x+mu) with G = g_n ... g_1 for the loaded
+// links U0.  The state kept in memory is U0 and G (reunitarised each step);
+// the links themselves are formed where they are needed and never stored.
 // One iteration is three launches plus a one-block reduction:
-//   k_measure<APPLY_G>  U' = g U g^dag(x+mu) (Section 2), Delta(x) of U'
-//                       packed to 8 reals, per-site F and theta terms, and
-//                       the forward 2D FFT over each (x, y) plane in LDS.
-//   k_zt                forward 2D FFT over (z, t), multiply by
-//                       (alpha/2) p2max / (p^2 V) (eq. gx), inverse (z, t).
-//   k_gauge             inverse 2D FFT over (x, y); dtilde (scaled by
-//                       alpha/2) is stored in site order for the next
-//                       k_measure, which rebuilds g = reunit(1 + dtilde)
-//                       wherever it reads g (optionally G <- g G here).
-//   k_reduce            F and theta from per-plane partial sums, in a fixed
-//                       order; sets the convergence flag.
+//   k_zt        forward 2D FFT over (z, t) of Delta, multiply by
+//               (alpha/2) p2max / (p^2 V) (eq. gx), inverse (z, t).
+//   k_gauge     inverse 2D FFT over (x, y), g = reunit(1 + dtilde) and
+//               G[1 - cur] = reunit(g G[cur]).
+//   k_measure   U' = G U0 G^dag(x+mu) for the new G, Delta(x) of U' packed
+//               to 8 reals, per-site F and theta terms, and the forward 2D
+//               FFT over each (x, y) plane in LDS.
+//   k_reduce    F and theta from per-plane partial sums, in a fixed order;
+//               sets the convergence flag and makes G[1 - cur] current.
 // Every kernel returns at once when the device flag `done` is set, so
 // iterations queued past convergence cost only their launches.
 //
@@ -65,7 +67,7 @@ struct DevState {
     double theta_switch;   // batched mixed runs: leave FP32 once theta < theta_switch
     int32_t done;
     int32_t nonfinite;
-    int32_t cur;           // the current links are in U[cur]; the update writes U[1 - cur]
+    int32_t cur;           // the current gauge is G[cur]; the update writes G[1 - cur]
     int32_t phase;         // 0: FP32 arithmetic, 1: FP64
     int32_t needs_measure; // Delta, F, theta of the current links are not computed yet
     int32_t switch_pending;// batched mixed runs: FP32 phase finished, rebuild in FP64
@@ -180,20 +182,34 @@ __global__ void __launch_bounds__(256) k_load(int64_t V, int64_t VS, const doubl
     }
 }
 
-// SoA links of type T -> canonical FP64, third row rebuilt when NE = 6.
+// Canonical FP64 links G(x) Uref_mu(x) G^dag(x+mu) from reference links and
+// the accumulated gauge: the same arithmetic as the links k_measure forms, so
+// the stored links are bit for bit the ones measured.
 template <typename T, int NE>
-__global__ void __launch_bounds__(256) k_store(int64_t V, int64_t VS, const C2<T>* __restrict__ U,
-                                               double* __restrict__ dst)
+__global__ void __launch_bounds__(256) k_store_gauged(Geo geo, const C2<T>* __restrict__ Uref,
+                                                      const C2<T>* __restrict__ G, double* __restrict__ dst)
 {
-    const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (li >= 4 * V) return;
+    const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;    // site * 4 + mu
+    if (li >= 4 * geo.V) return;
     const int64_t s = li >> 2;
     const int mu = (int)(li & 3);
-    M3<T> m;
-    load_mat<T, NE>(m, U + (int64_t)mu * NE * VS, VS, s);
+    int64_t rem = s;
+    int c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k] = (int)(rem & (geo.L[k] - 1));
+        rem >>= geo.logL[k];
+    }
+    c[mu] = (c[mu] + 1) & (geo.L[mu] - 1);
+    const int64_t sn = (((int64_t)c[3] * geo.L[2] + c[2]) * geo.L[1] + c[1]) * geo.L[0] + c[0];
+    M3<T> a, u, b, r;
+    load_mat<T, NE>(a, G, geo.VS, s);
+    load_mat<T, NE>(u, Uref + (int64_t)mu * NE * geo.VS, geo.VS, s);
+    load_mat<T, NE>(b, G, geo.VS, sn);
+    a_u_bdag<T, (NE == 6 ? 2 : 3)>(a, u, b, r);
     C2<double>* p = reinterpret_cast<C2<double>*>(dst) + li * 9;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) p[e] = mk<double>((double)m.e[e].x, (double)m.e[e].y);
+    for (int e = 0; e < 9; ++e) p[e] = mk<double>((double)r.e[e].x, (double)r.e[e].y);
 }
 
 // per-site matrix field (g or G): canonical FP64 [s][3][3] <-> SoA
@@ -233,13 +249,16 @@ __global__ void __launch_bounds__(256) k_field_identity(int64_t V, int64_t VS, C
 
 // ---------------------------------------------------------------------------
 // a1 + a2 + a3(x, y) for one (z, t) plane q: gauge transform, Delta, F and
-// theta terms, forward (x, y) FFT of the packed Delta into D.
+// theta terms, forward (x, y) FFT of the packed Delta into D.  The links
+// are U'_mu(x) = G(x) Uref_mu(x) G^dag(x+mu) for the reference (loaded) links
+// Uref and the accumulated gauge G; they are formed here, for the plane's
+// own links and the backward neighbours, and never stored.
 //   red: 2 * blockDim doubles of LDS; buf: plane_lds_elems(geo) complex of LDS.
 // ---------------------------------------------------------------------------
-template <typename T, int NE, bool APPLY_G, int LMAX>
-__device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ Uin, C2<T>* __restrict__ Uout,
-                              const C2<T>* __restrict__ g, C2<T>* __restrict__ D, double* __restrict__ partial,
-                              const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy, double* red, C2<T>* buf)
+template <typename T, int NE, int LMAX>
+__device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ Uref, const C2<T>* __restrict__ G,
+                              C2<T>* __restrict__ D, double* __restrict__ partial, const C2<T>* __restrict__ twx,
+                              const C2<T>* __restrict__ twy, double* red, C2<T>* buf)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int Lx = geo.L[0], Ly = geo.L[1], Lz = geo.L[2], Lt = geo.L[3];
@@ -262,34 +281,25 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc.c[c] = mk<T>(T(0), T(0));
         M3<T> gx;
-        if (APPLY_G) load_gauge<T, NE>(gx, g, VS, s);
+        load_mat<T, NE>(gx, G, VS, s);
         double f = 0.0;
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
-            M3<T> u;
-            load_mat<T, NE>(u, Uin + (int64_t)mu * NE * VS, VS, s);
-            if (APPLY_G) {
-                M3<T> gn, r;
-                load_gauge<T, NE>(gn, g, VS, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
-                a_u_bdag<T, (NE == 6 ? 2 : 3)>(gx, u, gn, r);
-                store_mat<T, NE>(r, Uout + (int64_t)mu * NE * VS, VS, s);
-                u = r;
-            }
-            f += re_trace(u);
-            alg_accumulate(acc, u, T(-1));
+            M3<T> u, gn, r;
+            load_mat<T, NE>(u, Uref + (int64_t)mu * NE * VS, VS, s);
+            load_mat<T, NE>(gn, G, VS, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
+            a_u_bdag<T, (NE == 6 ? 2 : 3)>(gx, u, gn, r);
+            f += re_trace(r);
+            alg_accumulate(acc, r, T(-1));
         }
 #pragma unroll 1
         for (int nu = 0; nu < 4; ++nu) {
-            M3<T> u;
+            M3<T> u, gb, r;
             const int64_t sb = nu == 0 ? xm : nu == 1 ? ym : nu == 2 ? qzm + p : qtm + p;
-            load_mat<T, NE>(u, Uin + (int64_t)nu * NE * VS, VS, sb);
-            if (APPLY_G) {
-                M3<T> gb, r;
-                load_gauge<T, NE>(gb, g, VS, sb);
-                a_u_bdag<T, (NE == 6 ? 2 : 3)>(gb, u, gx, r);
-                u = r;
-            }
-            alg_accumulate(acc, u, T(1));
+            load_mat<T, NE>(u, Uref + (int64_t)nu * NE * VS, VS, sb);
+            load_mat<T, NE>(gb, G, VS, sb);
+            a_u_bdag<T, (NE == 6 ? 2 : 3)>(gb, u, gx, r);
+            alg_accumulate(acc, r, T(1));
         }
         fsum += f;
         tsum += alg_norm2(acc);
@@ -398,13 +408,12 @@ __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, co
 }
 
 // ---------------------------------------------------------------------------
-// a5(x, y) + a6 (+ a8) for one plane q: inverse (x, y) FFT; dtilde is
-// stored as the generator of g = reunit(1 + dtilde) (load_gauge rebuilds g
-// in FP64 where it is read); optionally G <- reunit(g G).
+// a5(x, y) + a6 + a8 for one plane q: inverse (x, y) FFT,
+// g = reunit(1 + dtilde) and Gout = reunit(g Gin), both in FP64.
 // ---------------------------------------------------------------------------
-template <typename T, int NE, bool ACC_G, int LMAX>
-__device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, C2<T>* __restrict__ g,
-                            C2<T>* __restrict__ G, const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
+template <typename T, int NE, int LMAX>
+__device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, const C2<T>* __restrict__ Gin,
+                            C2<T>* __restrict__ Gout, const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
                             C2<T>* buf)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -420,9 +429,7 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
     const int64_t q0 = (int64_t)q * NP;
     for (int p = tid; p < NP; p += nth) {
         const int64_t s = q0 + p;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) g[k * VS + s] = buf[plane_lds_index(geo, k, p)];   // g kept as its generator
-        if (ACC_G) {
+        {
             C2<double> c[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -432,7 +439,7 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
             M3<double> m;
             one_plus_alg_reunit(c, m);
             M3<T> Gt;
-            load_mat<T, NE>(Gt, G, VS, s);
+            load_mat<T, NE>(Gt, Gin, VS, s);
             M3<double> Gd = cast_mat<double>(Gt), r;
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -441,7 +448,7 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
                     r.e[3 * i + k] =
                         cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
             reunit(r);
-            store_mat<T, NE>(cast_mat<T>(r), G, VS, s);
+            store_mat<T, NE>(cast_mat<T>(r), Gout, VS, s);
         }
     }
 }
@@ -495,18 +502,21 @@ __device__ __forceinline__ void reduce_state(const double* __restrict__ partial,
 // ===========================================================================
 // single-configuration kernels (one lattice per launch)
 // ===========================================================================
-template <typename T, int NE, bool APPLY_G, int LMAX>
-__global__ void __launch_bounds__(256) k_measure(Geo geo, C2<T>* U0, C2<T>* U1, const C2<T>* __restrict__ g,
-                                                 C2<T>* __restrict__ D, double* __restrict__ partial,
-                                                 const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
-                                                 const DevState* __restrict__ st)
+// The links are never stored: they are G(x) Uref(x) G^dag(x+mu) for the
+// reference links Uref (those loaded) and the accumulated gauge G, kept in a
+// pair of buffers.  next = 0 measures the current G (G[cur]); next = 1 the
+// one k_gauge has just formed (G[1 - cur]).
+template <typename T, int NE, int LMAX>
+__global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restrict__ Uref, const C2<T>* G0,
+                                                 const C2<T>* G1, int next, C2<T>* __restrict__ D,
+                                                 double* __restrict__ partial, const C2<T>* __restrict__ twx,
+                                                 const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
-    const int cur = st->cur;
-    measure_plane<T, NE, APPLY_G, LMAX>(geo, plane_of_block(blockIdx.x, geo), cur ? U1 : U0, cur ? U0 : U1, g, D,
-                                        partial, twx, twy, lds_raw,
-                                        reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
+    const C2<T>* G = (st->cur ^ next) ? G1 : G0;
+    measure_plane<T, NE, LMAX>(geo, plane_of_block(blockIdx.x, geo), Uref, G, D, partial, twx, twy, lds_raw,
+                               reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
 }
 
 template <typename T, int LMAX>
@@ -520,15 +530,17 @@ __global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, cons
                       reinterpret_cast<C2<T>*>(lds_raw));
 }
 
-template <typename T, int NE, bool ACC_G, int LMAX>
-__global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict__ D, C2<T>* __restrict__ g,
-                                               C2<T>* __restrict__ G, const C2<T>* __restrict__ twx,
-                                               const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
+// G[1 - cur] <- reunit(g G[cur]) with g = reunit(1 + dtilde) from D.
+template <typename T, int NE, int LMAX>
+__global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict__ D, C2<T>* G0, C2<T>* G1,
+                                               const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
+                                               const DevState* __restrict__ st)
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
-    gauge_plane<T, NE, ACC_G, LMAX>(geo, plane_of_block(blockIdx.x, geo), D, g, G, twx, twy,
-                                    reinterpret_cast<C2<T>*>(lds_raw));
+    const int cur = st->cur;
+    gauge_plane<T, NE, LMAX>(geo, plane_of_block(blockIdx.x, geo), D, cur ? G1 : G0, cur ? G0 : G1, twx, twy,
+                             reinterpret_cast<C2<T>*>(lds_raw));
 }
 
 template <int UNUSED = 0>
@@ -559,43 +571,11 @@ __device__ __forceinline__ void promote_site(int64_t VS32, int64_t VS64, int64_t
 }
 
 template <int NE>
-__device__ __forceinline__ void switch_link(const Geo& geo, int mu, int64_t s, const C2<double>* __restrict__ U0,
-                                            const C2<double>* __restrict__ G, C2<double>* __restrict__ U)
-{
-    const int64_t VS = geo.VS;
-    int64_t rem = s;
-    int c[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        c[k] = (int)(rem & (geo.L[k] - 1));
-        rem >>= geo.logL[k];
-    }
-    c[mu] = (c[mu] + 1) & (geo.L[mu] - 1);
-    const int64_t sn = (((int64_t)c[3] * geo.L[2] + c[2]) * geo.L[1] + c[1]) * geo.L[0] + c[0];
-    M3<double> a, u, b, r;
-    load_mat<double, NE>(a, G, VS, s);
-    load_mat<double, NE>(u, U0 + (int64_t)mu * NE * VS, VS, s);
-    load_mat<double, NE>(b, G, VS, sn);
-    a_u_bdag<double, (NE == 6 ? 2 : 3)>(a, u, b, r);
-    store_mat<double, NE>(r, U + (int64_t)mu * NE * VS, VS, s);
-}
-
-template <int NE>
 __global__ void __launch_bounds__(256) k_promote_gauge(int64_t V, int64_t VS32, int64_t VS64,
                                                        const C2<float>* __restrict__ G32, C2<double>* __restrict__ G64)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < V) promote_site<NE>(VS32, VS64, s, G32, G64);
-}
-
-template <int NE>
-__global__ void __launch_bounds__(256) k_switch(Geo geo, const C2<double>* __restrict__ U0,
-                                                const C2<double>* __restrict__ G, C2<double>* __restrict__ U)
-{
-    const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (li >= 4 * geo.V) return;
-    const int mu = (int)(li / geo.V);
-    switch_link<NE>(geo, mu, li - (int64_t)mu * geo.V, U0, G, U);
 }
 
 // ===========================================================================
@@ -610,10 +590,9 @@ __global__ void __launch_bounds__(256) k_switch(Geo geo, const C2<double>* __res
 template <typename T>
 struct BatchCfg {
     Geo geo;
-    C2<T>* U[2];
-    C2<T>* g;
+    const C2<T>* U;         // reference (loaded) links; the links are G U G^dag(x+mu)
+    C2<T>* G[2];            // accumulated gauge, G[cur] current
     C2<T>* D;
-    C2<T>* G;
     const C2<T>* tw[4];
     const double* ptab;
     double* partial;
@@ -632,7 +611,9 @@ __device__ __forceinline__ bool batch_active(const DevState* st, int phase, int 
     return gate == 0 ? st->needs_measure != 0 : st->needs_measure == 0;
 }
 
-template <typename T, int NE, bool APPLY_G, int LMAX>
+// NEXT = false: measure the links of the current gauge G[cur] (members that
+// need a measure); NEXT = true: those of the gauge k_gauge just formed.
+template <typename T, int NE, bool NEXT, int LMAX>
 __global__ void __launch_bounds__(256) kb_measure(const BatchCfg<T>* __restrict__ cfgs, const uint32_t* __restrict__ items,
                                                   int nitems, int phase)
 {
@@ -640,12 +621,11 @@ __global__ void __launch_bounds__(256) kb_measure(const BatchCfg<T>* __restrict_
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const uint32_t w = items[it];
         const BatchCfg<T>& bc = cfgs[w >> kItemShift];
-        if (!batch_active(bc.st, phase, APPLY_G ? 1 : 0)) continue;
-        const int cur = bc.st->cur;
+        if (!batch_active(bc.st, phase, NEXT ? 1 : 0)) continue;
+        const int sel = bc.st->cur ^ (NEXT ? 1 : 0);
         __syncthreads();
-        measure_plane<T, NE, APPLY_G, LMAX>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), cur ? bc.U[1] : bc.U[0],
-                                            cur ? bc.U[0] : bc.U[1], bc.g, bc.D, bc.partial, bc.tw[0], bc.tw[1],
-                                            lds_raw, reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
+        measure_plane<T, NE, LMAX>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), bc.U, bc.G[sel], bc.D, bc.partial,
+                                   bc.tw[0], bc.tw[1], lds_raw, reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
     }
 }
 
@@ -675,8 +655,9 @@ __global__ void __launch_bounds__(256) kb_gauge(const BatchCfg<T>* __restrict__ 
         const BatchCfg<T>& bc = cfgs[w >> kItemShift];
         if (!batch_active(bc.st, phase, 1)) continue;
         __syncthreads();
-        gauge_plane<T, NE, true, LMAX>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), bc.D, bc.g, bc.G, bc.tw[0],
-                                       bc.tw[1], reinterpret_cast<C2<T>*>(lds_raw));
+        const int cur = bc.st->cur;
+        gauge_plane<T, NE, LMAX>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), bc.D, bc.G[cur], bc.G[cur ^ 1],
+                                 bc.tw[0], bc.tw[1], reinterpret_cast<C2<T>*>(lds_raw));
     }
 }
 
@@ -691,8 +672,8 @@ __global__ void __launch_bounds__(256) kb_reduce(const BatchCfg<T>* __restrict__
 }
 
 // Mixed runs: the FP32 phase of a configuration ended (switch_pending).
-// Step 1: G64 = reunit(G32); step 2: U64 = G64 U0 G64^dag(x+mu) into U64[0];
-// step 3: FP64 phase, links in U[0], Delta to be measured.
+// Step 1: G64[0] = reunit(G32[cur]); step 2: FP64 phase with cur = 0, whose
+// links are G64 U0 G64^dag(x+mu) for the loaded FP64 links, to be measured.
 template <int NE>
 __global__ void __launch_bounds__(256) kb_promote(const BatchCfg<float>* __restrict__ c32,
                                                   const BatchCfg<double>* __restrict__ c64,
@@ -705,22 +686,7 @@ __global__ void __launch_bounds__(256) kb_promote(const BatchCfg<float>* __restr
         const Geo& geo = c64[cfg].geo;
         const int64_t q0 = (int64_t)(w & ((1u << kItemShift) - 1)) * geo.NP;
         for (int p = threadIdx.x; p < geo.NP; p += blockDim.x)
-            promote_site<NE>(c32[cfg].geo.VS, geo.VS, q0 + p, c32[cfg].G, c64[cfg].G);
-    }
-}
-
-template <int NE>
-__global__ void __launch_bounds__(256) kb_switch(const BatchCfg<double>* __restrict__ c64, const C2<double>* const* U0,
-                                                 const uint32_t* __restrict__ items, int nitems)
-{
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint32_t w = items[it];
-        const int cfg = (int)(w >> kItemShift);
-        const BatchCfg<double>& bc = c64[cfg];
-        if (!bc.st->switch_pending || bc.st->done) continue;
-        const int64_t q0 = (int64_t)(w & ((1u << kItemShift) - 1)) * bc.geo.NP;
-        for (int i = threadIdx.x; i < 4 * bc.geo.NP; i += blockDim.x)
-            switch_link<NE>(bc.geo, i / bc.geo.NP, q0 + i % bc.geo.NP, U0[cfg], bc.G, bc.U[0]);
+            promote_site<NE>(c32[cfg].geo.VS, geo.VS, q0 + p, c32[cfg].G[c64[cfg].st->cur], c64[cfg].G[0]);
     }
 }
 

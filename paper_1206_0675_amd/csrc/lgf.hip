@@ -1,13 +1,12 @@
 // Host runtime and C ABI (include/lgf.h) of the gauge-fixing library.
 //
 // A context owns, per arithmetic precision T in use:
-//   U[2]  links, structure of arrays, NE complex per link (ping-pong: the
-//         transform reads U[cur] and writes U[1-cur]; the neighbour reads of
-//         the fused kernel need the old links intact)
-//   g     the gauge transformation of the iteration in flight, kept as its
-//         generator dtilde (4 complex per site) and rebuilt where read
+//   U[0]  the loaded (reference) links U0, structure of arrays, NE complex
+//         per link; never overwritten by the iteration
+//   G, Gb the accumulated gauge G = reunit(g_n ... reunit(g_2 g_1)), a pair
+//         of buffers with G[cur] current: the links are G U0 G^dag(x+mu),
+//         formed where they are needed and never stored
 //   D     the packed Delta field (4 complex per site) in the tiled layout
-//   G     the accumulated gauge (when tracked)
 //   tw    FFT twiddles W_L^k for the four extents
 // plus FP64 tables of the lattice momenta, the per-plane partial sums, and a
 // small device state (iteration, F, theta, stop flag, current buffer) that
@@ -78,7 +77,6 @@ struct lgf_context : Runner {
     bool delta_valid = false; // D and the state hold Delta, F, theta of the current links
     Bufs<double> d;
     Bufs<float> f;
-    C2<double>* U0 = nullptr; // LGF_MIXED: the links as loaded, FP64
     double* ptab = nullptr;
     double* partial = nullptr;
     DevState* st = nullptr;
@@ -143,13 +141,9 @@ int32_t set_lds_attrs(lgf_context* c)
     const int mlds = (int)(plane_lds_elems(g) * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double));
     const int glds = (int)(plane_lds_elems(g) * sizeof(C2<T>));
     const int zlds = (int)((size_t)g.NQ * g.W * sizeof(C2<T>));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, false, LMAX>),
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, mlds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, true, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, mlds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<T, NE, false, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, glds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<T, NE, true, LMAX>),
+    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<T, NE, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, glds));
     HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt<T, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, zlds));
@@ -159,15 +153,16 @@ int32_t set_lds_attrs(lgf_context* c)
 // ----------------------------------------------------------------------------
 // one iteration, enqueued
 // ----------------------------------------------------------------------------
-// Delta, F, theta of U[cur] with no update (the first line of Algorithm 1).
+// Delta, F, theta of the current links G[cur] U0 G[cur]^dag(x+mu) with no
+// update (the first line of Algorithm 1).
 template <typename T, int NE, int LMAX>
 int32_t enqueue_measure(lgf_context* c, double* trace_slot)
 {
     Bufs<T>& b = bufs<T>(c);
     const Geo& g = b.geo;
     const size_t lds = plane_lds_elems(g) * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double);
-    TRY(launch(c, K_MEASURE, k_measure<T, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), lds, g,
-               b.U[0], b.U[1], (const C2<T>*)nullptr, b.D, c->partial,
+    TRY(launch(c, K_MEASURE, k_measure<T, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane), lds, g,
+               (const C2<T>*)b.U, (const C2<T>*)b.G, (const C2<T>*)b.Gb, 0, b.D, c->partial,
                (const C2<T>*)(b.tw + b.tw_off[0]), (const C2<T>*)(b.tw + b.tw_off[1]), (const DevState*)c->st));
     TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
                trace_slot, 0));
@@ -176,9 +171,10 @@ int32_t enqueue_measure(lgf_context* c, double* trace_slot)
 }
 
 // filter, g, transform, Delta/F/theta of the new links (the loop body of
-// Algorithm 1).  The transform reads U[cur] and writes U[1 - cur] with cur
-// taken from the device state, which the reduction flips; when the stop flag
-// is set every kernel returns at once.  The launch arguments do not change
+// Algorithm 1).  The links are G U0 G^dag(x+mu) for the loaded links U0 and
+// the accumulated gauge G: k_gauge forms G[1 - cur] = reunit(g G[cur]) and
+// k_measure measures the links it gives; the reduction flips cur.  No link is
+// written.  When the stop flag is set every kernel returns at once.  The launch arguments do not change
 // from one iteration to the next, so a chunk of iterations can be captured
 // once in a graph and replayed.
 template <typename T, int NE, int LMAX>
@@ -194,14 +190,10 @@ int32_t enqueue_update(lgf_context* c, double* trace_slot)
     TRY(launch(c, K_ZT, k_zt<T, LMAX>, dim3((g.NP / g.W) * 4), dim3(512), zlds, g, b.D,
                (const C2<T>*)(b.tw + b.tw_off[2]), (const C2<T>*)(b.tw + b.tw_off[3]), (const double*)c->ptab,
                c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), (const DevState*)c->st));
-    if (c->track)
-        TRY(launch(c, K_GAUGE, k_gauge<T, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.g,
-                   b.G, twx, twy, (const DevState*)c->st));
-    else
-        TRY(launch(c, K_GAUGE, k_gauge<T, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.g,
-                   b.G, twx, twy, (const DevState*)c->st));
-    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<T, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane), mlds, g,
-               b.U[0], b.U[1], (const C2<T>*)b.g, b.D, c->partial, twx, twy,
+    TRY(launch(c, K_GAUGE, k_gauge<T, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.G,
+               b.Gb, twx, twy, (const DevState*)c->st));
+    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<T, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane), mlds, g,
+               (const C2<T>*)b.U, (const C2<T>*)b.G, (const C2<T>*)b.Gb, 1, b.D, c->partial, twx, twy,
                (const DevState*)c->st));
     TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
                trace_slot, 1));
@@ -274,12 +266,21 @@ int32_t enqueue_chunk(lgf_context* c, int64_t n)
 }
 
 
+// The current gauge G[cur] (the host copy of the state is current after
+// every call).
+template <typename T>
+C2<T>* g_cur(lgf_context* c)
+{
+    Bufs<T>& b = bufs<T>(c);
+    return c->st_host->cur ? b.Gb : b.G;
+}
+
 template <typename T, int NE>
 int32_t enqueue_store(lgf_context* c, double* dst)
 {
     Bufs<T>& b = bufs<T>(c);
-    return launch(c, K_STORE, k_store<T, NE>, dim3((unsigned)blocks_for(4 * b.geo.V, 256)), dim3(256), 0,
-                  b.geo.V, b.geo.VS, (const C2<T>*)b.U[c->st_host->cur], dst);
+    return launch(c, K_STORE, k_store_gauged<T, NE>, dim3((unsigned)blocks_for(4 * b.geo.V, 256)), dim3(256), 0,
+                  b.geo, (const C2<T>*)b.U, (const C2<T>*)g_cur<T>(c), dst);
 }
 
 int32_t store_any(lgf_context* c, double* dst)
@@ -301,7 +302,6 @@ template <typename T>
 int32_t enqueue_identity_G(lgf_context* c)
 {
     Bufs<T>& b = bufs<T>(c);
-    if (!b.G) return LGF_OK;
     const int64_t V = b.geo.V;
     if (c->NE == 9)
         return launch(c, K_FIELD, k_field_identity<T, 9>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V,
@@ -310,17 +310,15 @@ int32_t enqueue_identity_G(lgf_context* c)
                   b.geo.VS, b.G);
 }
 
-// LGF_MIXED: leave FP32.  G64 = reunit(G32); U64 = G64 U0 G64^dag(x+mu).
+// LGF_MIXED: leave FP32.  G64[0] = reunit(G32[cur]); the FP64 phase then
+// forms G64 U0 G64^dag(x+mu) from the loaded FP64 links (the state's cur is
+// reset to 0 with the phase).
 template <int NE>
 int32_t enqueue_switch(lgf_context* c)
 {
     const Geo& g = c->d.geo;
-    TRY(launch(c, K_SWITCH, k_promote_gauge<NE>, dim3((unsigned)blocks_for(g.V, 256)), dim3(256), 0, g.V,
-               c->f.geo.VS, g.VS,
-               (const C2<float>*)c->f.G, c->d.G));
-    TRY(launch(c, K_SWITCH, k_switch<NE>, dim3((unsigned)blocks_for(4 * g.V, 256)), dim3(256), 0, g,
-               (const C2<double>*)c->U0, (const C2<double>*)c->d.G, c->d.U[0]));
-    return LGF_OK;
+    return launch(c, K_SWITCH, k_promote_gauge<NE>, dim3((unsigned)blocks_for(g.V, 256)), dim3(256), 0, g.V,
+                  c->f.geo.VS, g.VS, (const C2<float>*)g_cur<float>(c), c->d.G);
 }
 
 
@@ -395,7 +393,7 @@ int32_t identity_links(lgf_context* c)
     const dim3 gr((unsigned)blocks_for(b.geo.V, 256));
     for (int mu = 0; mu < 4; ++mu)
         TRY(launch(c, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, b.geo.V, b.geo.VS,
-                   b.U[0] + (int64_t)mu * NE * b.geo.VS));
+                   b.U + (int64_t)mu * NE * b.geo.VS));
     return enqueue_identity_G<T>(c);
 }
 
@@ -573,8 +571,8 @@ int32_t enqueue_bands(lgf_context* c, bool use_model)
 }
 
 // One update with per-band factors s from the spectrum in D2: the scaled
-// inverse into D3, g, the candidate links into U[1 - cur] and their Delta
-// into D.  mode 2: a candidate (F and theta recorded as trial values, nothing
+// inverse into D3, the candidate gauge G[1 - cur] = reunit(g G[cur]), and the
+// Delta of the links it gives into D.  mode 2: a candidate (F and theta recorded as trial values, nothing
 // committed); mode 1: committed.
 template <int NE, int LMAX>
 int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double* trace_slot)
@@ -589,11 +587,11 @@ int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double*
                (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
                (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), (const int8_t*)c->btab, s,
                (const DevState*)c->st));
-    TRY(launch(c, K_GAUGE, k_gauge<double, NE, false, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g,
-               (const C2<double>*)c->D3, b.g, b.G, twx, twy, (const DevState*)c->st));
-    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<double, NE, true, LMAX>, dim3(g.NQ), dim3(c->nth_plane),
-               glds + 2 * c->nth_plane * sizeof(double), g, b.U[0], b.U[1], (const C2<double>*)b.g, b.D,
-               c->partial, twx, twy, (const DevState*)c->st));
+    TRY(launch(c, K_GAUGE, k_gauge<double, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g,
+               (const C2<double>*)c->D3, b.G, b.Gb, twx, twy, (const DevState*)c->st));
+    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<double, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane),
+               glds + 2 * c->nth_plane * sizeof(double), g, (const C2<double>*)b.U, (const C2<double>*)b.G,
+               (const C2<double>*)b.Gb, 1, b.D, c->partial, twx, twy, (const DevState*)c->st));
     TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
                trace_slot, mode));
     return LGF_OK;
@@ -774,7 +772,7 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
     c->NE = p->storage == LGF_STORE12 ? 6 : 9;
     c->use64 = use64;
     c->use32 = use32;
-    c->track = p->track_gauge != 0 || p->precision == LGF_MIXED;
+    c->track = true;          // G is the state: the links are G U0 G^dag(x+mu)
     c->phase = use64 && !use32 ? 1 : 0;
     c->nth_plane = nth;
     for (int m = 0; m < 4; ++m)
@@ -796,14 +794,11 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
         }
         c->own_stream = true;
     }
-    if (use64 && (rc = alloc_bufs<double>(c, p->dims, c->NE, c->track, kDefaultTileBytes, c->d, c->bytes)) != LGF_OK) return bail(rc);
-    if (use32 && (rc = alloc_bufs<float>(c, p->dims, c->NE, c->track, kDefaultTileBytes, c->f, c->bytes)) != LGF_OK) return bail(rc);
+    if (use64 && (rc = alloc_bufs<double>(c, p->dims, c->NE, kDefaultTileBytes, c->d, c->bytes)) != LGF_OK)
+        return bail(rc);
+    if (use32 && (rc = alloc_bufs<float>(c, p->dims, c->NE, kDefaultTileBytes, c->f, c->bytes)) != LGF_OK)
+        return bail(rc);
     const Geo& g = use64 ? c->d.geo : c->f.geo;
-    if (p->precision == LGF_MIXED) {
-        const size_t link = sizeof(C2<double>) * (size_t)4 * c->NE * c->d.geo.VS;
-        if (hipMalloc(&c->U0, link) != hipSuccess) { c->err = "hipMalloc U0"; return bail(LGF_E_OUT_OF_MEMORY); }
-        c->bytes += link;
-    }
     double p2max = 0.0;
     const std::vector<double> pt = momentum_tables(p->dims, &p2max);
     c->c0 = 0.5 * p->alpha * (p->accel == LGF_ACCEL_FOURIER ? p2max : 1.0) / (double)g.V;
@@ -835,7 +830,6 @@ int32_t lgf_destroy(lgf_ctx c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_bufs(c->d);
     free_bufs(c->f);
-    (void)hipFree(c->U0);
     (void)hipFree(c->ptab);
     (void)hipFree(c->partial);
     (void)hipFree(c->st);
@@ -880,12 +874,12 @@ int32_t lgf_load_links(lgf_ctx c, const void* links, int32_t where)
             break;
         }
         if (c->p.precision == LGF_MIXED) {
-            rc = c->NE == 9 ? enqueue_load<double, 9>(c, s, c->U0) : enqueue_load<double, 6>(c, s, c->U0);
-            if (rc == LGF_OK) rc = c->NE == 9 ? enqueue_load<float, 9>(c, s, c->f.U[0]) : enqueue_load<float, 6>(c, s, c->f.U[0]);
+            rc = c->NE == 9 ? enqueue_load<double, 9>(c, s, c->d.U) : enqueue_load<double, 6>(c, s, c->d.U);
+            if (rc == LGF_OK) rc = c->NE == 9 ? enqueue_load<float, 9>(c, s, c->f.U) : enqueue_load<float, 6>(c, s, c->f.U);
         } else if (c->p.precision == LGF_FP64) {
-            rc = c->NE == 9 ? enqueue_load<double, 9>(c, s, c->d.U[0]) : enqueue_load<double, 6>(c, s, c->d.U[0]);
+            rc = c->NE == 9 ? enqueue_load<double, 9>(c, s, c->d.U) : enqueue_load<double, 6>(c, s, c->d.U);
         } else {
-            rc = c->NE == 9 ? enqueue_load<float, 9>(c, s, c->f.U[0]) : enqueue_load<float, 6>(c, s, c->f.U[0]);
+            rc = c->NE == 9 ? enqueue_load<float, 9>(c, s, c->f.U) : enqueue_load<float, 6>(c, s, c->f.U);
         }
         if (rc != LGF_OK) break;
         if (c->use64 && (rc = enqueue_identity_G<double>(c)) != LGF_OK) break;
@@ -947,7 +941,6 @@ int32_t lgf_store_links(lgf_ctx c, void* links, int32_t where)
 int32_t lgf_store_gauge(lgf_ctx c, void* G, int32_t where)
 {
     TRY(check_ctx(c, true));
-    if (!c->track) return fail(c, LGF_E_STATE, "gauge not tracked (set track_gauge)");
     if (!G || (where != LGF_HOST && where != LGF_DEVICE)) return fail(c, LGF_E_INVALID_ARG, "bad G/where");
     const int64_t V = (c->use64 ? c->d.geo : c->f.geo).V;
     const size_t nbytes = sizeof(double) * 18 * (size_t)V;
@@ -956,11 +949,11 @@ int32_t lgf_store_gauge(lgf_ctx c, void* G, int32_t where)
     int32_t rc;
     const dim3 grid((unsigned)blocks_for(V, 256));
     if (c->phase == 1)
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<double, 9>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)c->d.G, dst)
-                        : launch(c, K_FIELD, k_field_store<double, 6>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)c->d.G, dst);
+        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<double, 9>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)g_cur<double>(c), dst)
+                        : launch(c, K_FIELD, k_field_store<double, 6>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)g_cur<double>(c), dst);
     else
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<float, 9>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)c->f.G, dst)
-                        : launch(c, K_FIELD, k_field_store<float, 6>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)c->f.G, dst);
+        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<float, 9>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)g_cur<float>(c), dst)
+                        : launch(c, K_FIELD, k_field_store<float, 6>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)g_cur<float>(c), dst);
     if (rc == LGF_OK && where == LGF_HOST &&
         hipMemcpyAsync(G, dst, nbytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
         rc = fail(c, LGF_E_DEVICE, "hipMemcpyAsync G out");
@@ -975,7 +968,6 @@ int32_t lgf_store_gauge(lgf_ctx c, void* G, int32_t where)
 int32_t lgf_load_gauge(lgf_ctx c, const void* G, int32_t where)
 {
     TRY(check_ctx(c, true));
-    if (!c->track) return fail(c, LGF_E_STATE, "gauge not tracked (set track_gauge)");
     if (!G || (where != LGF_HOST && where != LGF_DEVICE)) return fail(c, LGF_E_INVALID_ARG, "bad G/where");
     const int64_t V = (c->use64 ? c->d.geo : c->f.geo).V;
     const size_t nbytes = sizeof(double) * 18 * (size_t)V;
@@ -989,12 +981,13 @@ int32_t lgf_load_gauge(lgf_ctx c, const void* G, int32_t where)
     }
     int32_t rc;
     const dim3 grid((unsigned)blocks_for(V, 256));
+    c->delta_valid = false;                 // the links G U0 G^dag(x+mu) change with G
     if (c->phase == 1)
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<double, 9>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, c->d.G)
-                        : launch(c, K_FIELD, k_field_load<double, 6>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, c->d.G);
+        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<double, 9>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, g_cur<double>(c))
+                        : launch(c, K_FIELD, k_field_load<double, 6>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, g_cur<double>(c));
     else
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<float, 9>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, c->f.G)
-                        : launch(c, K_FIELD, k_field_load<float, 6>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, c->f.G);
+        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<float, 9>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, g_cur<float>(c))
+                        : launch(c, K_FIELD, k_field_load<float, 6>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, g_cur<float>(c));
     if (rc == LGF_OK) rc = sync_state(c);
     if (where == LGF_HOST) {
         (void)hipStreamSynchronize(c->stream);

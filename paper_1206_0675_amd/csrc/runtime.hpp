@@ -163,10 +163,10 @@ inline double now_s()
 // Device buffers of one lattice in precision T.
 template <typename T>
 struct Bufs {
-    C2<T>* U[2] = {nullptr, nullptr};
-    C2<T>* g = nullptr;      // g = reunit(1 + dtilde) as dtilde: 4 complex per site
+    C2<T>* U = nullptr;      // reference (loaded) links; the links are G U G^dag(x+mu)
     C2<T>* D = nullptr;
-    C2<T>* G = nullptr;
+    C2<T>* G = nullptr;      // accumulated gauge, a pair of buffers: G[cur] is G if cur = 0,
+    C2<T>* Gb = nullptr;     // else Gb
     C2<T>* tw = nullptr;     // Lx + Ly + Lz + Lt entries
     int64_t d_cap = 0;       // complex elements allocated for D
     Geo geo{};
@@ -273,8 +273,10 @@ inline std::vector<double> momentum_tables(const int32_t* dims, double* p2max)
     return pt;
 }
 
+// Buffers of one lattice: the reference links, the gauge pair, Delta (sized
+// for every tile choice) and the twiddles.
 template <typename T>
-int32_t alloc_bufs(Runner* c, const int32_t* dims, int NE, bool track, int tile_bytes, Bufs<T>& b, int64_t& bytes)
+int32_t alloc_bufs(Runner* c, const int32_t* dims, int NE, int tile_bytes, Bufs<T>& b, int64_t& bytes)
 {
     b.geo = make_geo<T>(dims, tile_bytes);
     const int64_t VS = b.geo.VS;
@@ -282,16 +284,11 @@ int32_t alloc_bufs(Runner* c, const int32_t* dims, int NE, bool track, int tile_
     const size_t field = sizeof(C2<T>) * (size_t)NE * VS;
     b.d_cap = delta_capacity<T>(dims, tile_bytes);
     const size_t dbytes = sizeof(C2<T>) * (size_t)b.d_cap;
-    HIPCHK(c, hipMalloc(&b.U[0], link));
-    HIPCHK(c, hipMalloc(&b.U[1], link));
-    const size_t gen = sizeof(C2<T>) * (size_t)4 * VS;     // g as its 4 packed generator fields
-    HIPCHK(c, hipMalloc(&b.g, gen));
+    HIPCHK(c, hipMalloc(&b.U, link));
+    HIPCHK(c, hipMalloc(&b.G, field));
+    HIPCHK(c, hipMalloc(&b.Gb, field));
     HIPCHK(c, hipMalloc(&b.D, dbytes));
-    bytes += 2 * link + gen + dbytes;
-    if (track) {
-        HIPCHK(c, hipMalloc(&b.G, field));
-        bytes += field;
-    }
+    bytes += link + 2 * field + dbytes;
     std::vector<C2<T>> tw = twiddles<T>(dims, b.tw_off);
     HIPCHK(c, hipMalloc(&b.tw, sizeof(C2<T>) * tw.size()));
     HIPCHK(c, hipMemcpy(b.tw, tw.data(), sizeof(C2<T>) * tw.size(), hipMemcpyHostToDevice));
@@ -301,11 +298,10 @@ int32_t alloc_bufs(Runner* c, const int32_t* dims, int NE, bool track, int tile_
 template <typename T>
 void free_bufs(Bufs<T>& b)
 {
-    (void)hipFree(b.U[0]);
-    (void)hipFree(b.U[1]);
-    (void)hipFree(b.g);
+    (void)hipFree(b.U);
     (void)hipFree(b.D);
     (void)hipFree(b.G);
+    (void)hipFree(b.Gb);
     (void)hipFree(b.tw);
     b = Bufs<T>();
 }

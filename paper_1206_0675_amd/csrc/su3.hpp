@@ -233,24 +233,4 @@ __device__ __forceinline__ M3<TO> cast_mat(const M3<TI>& a)
     return r;
 }
 
-// The gauge transformation g = reunit(1 + dtilde) is kept in memory as its
-// four packed generator fields dtilde (8 reals per site, whatever the link
-// storage) and rebuilt where it is read, by the same FP64 projection.  The
-// result is the matrix a stored g would give: rows 1 and 2 rounded to T, and
-// for the 12-real form row 3 rebuilt from them in T.
-template <typename T, int NE>
-__device__ __forceinline__ void load_gauge(M3<T>& m, const C2<T>* __restrict__ base, int64_t stride, int64_t s)
-{
-    C2<double> c[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const C2<T> v = base[k * stride + s];
-        c[k] = mk<double>((double)v.x, (double)v.y);
-    }
-    M3<double> md;
-    one_plus_alg_reunit(c, md);
-    m = cast_mat<T>(md);
-    if (NE == 6) rebuild_row3(m);
-}
-
 }  // namespace lgf

@@ -92,17 +92,22 @@ def test_emulated_fix_and_mixed(E, oracle_lib):
 
 
 def test_emulated_checkpoint_resume(E, oracle_lib):
+    """A checkpoint is the loaded links and G: loading both resumes the run
+    bit for bit, and the links are G U0 G^dag(x+mu) from the moment G is
+    loaded."""
     dims = (4, 8, 4, 4)
     U = synth.random_links(dims, 4)
-    a = lgf.Context(dims, lib=E, track_gauge=1)
+    a = lgf.Context(dims, lib=E)
     a.load(U)
     a.step(4)
     U4, G4 = a.store(), a.store_gauge()
     a.step(3)
     ref = a.store()
-    b = lgf.Context(dims, lib=E, track_gauge=1)
-    b.load(U4)
+    b = lgf.Context(dims, lib=E)
+    b.load(U)
     b.load_gauge(G4)
+    assert np.array_equal(b.store(), U4)
+    assert np.max(np.abs(oracle.transform(dims, U, G4) - U4)) <= 1e-13
     b.step(3)
     assert np.array_equal(b.store(), ref)
     assert np.max(np.abs(b.store_gauge() - a.store_gauge())) == 0.0
@@ -134,7 +139,7 @@ from paper_1206_0675_amd import lgf
 L = lgf.load_library({lib!r})
 for dims, kw in [((4, 4, 4, 4), {{"max_iter": 4}}), ((8, 4, 4, 8), {{"storage": 12, "max_iter": 4}}),
                  ((4, 8, 4, 4), {{"precision": 2, "poll_every": 4, "theta_switch": 1.0, "max_iter": 8}}),
-                 ((4, 4, 8, 4), {{"precision": 1, "track_gauge": 1, "max_iter": 4}}),
+                 ((4, 4, 8, 4), {{"precision": 1, "max_iter": 4}}),
                  ((4, 4, 32, 32), {{"storage": 12, "max_iter": 3}}),
                  ((16, 8, 4, 4), {{"storage": 12, "autotune": 1, "max_iter": 3}})]:
     ctx = lgf.Context(dims, lib=L, **kw)
@@ -142,8 +147,7 @@ for dims, kw in [((4, 4, 4, 4), {{"max_iter": 4}}), ((8, 4, 4, 8), {{"storage": 
     ctx.step(2, trace=True)
     ctx.fix(raise_on_error=False)
     ctx.store()
-    if kw.get("precision") or kw.get("track_gauge"):
-        ctx.load_gauge(ctx.store_gauge())
+    ctx.load_gauge(ctx.store_gauge())
     ctx.close()
 print("ASAN-CLEAN")
 """
