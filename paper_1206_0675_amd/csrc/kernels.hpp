@@ -423,33 +423,56 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
         const int c = i >> geo.logNP, p = i & (NP - 1);
         buf[plane_lds_index(geo, c, p)] = D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))];
     }
+    // G of each thread's first PF sites, loaded into registers here so that
+    // the loads complete while the FFT runs in LDS
+    const int64_t q0 = (int64_t)q * NP;
+    constexpr int PF = (NE == 9 && sizeof(T) == 8) ? 2 : 4;
+    C2<T> gpre[PF][NE];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int p = tid + k * nth;
+        if (p < NP) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) gpre[k][e] = Gin[e * VS + q0 + p];
+        }
+    }
     __syncthreads();
     fft_inv<T, LMAX>(buf, geo.L[1], Lines{geo.logL[0], 2, 1, geo.NPP, geo.RP}, twy, tid, nth);
     fft_inv<T, LMAX>(buf, geo.L[0], Lines{geo.logL[1], 2, geo.RP, geo.NPP, 1}, twx, tid, nth);
-    const int64_t q0 = (int64_t)q * NP;
-    for (int p = tid; p < NP; p += nth) {
-        const int64_t s = q0 + p;
-        {
-            C2<double> c[4];
+    auto update = [&](int p, const M3<T>& Gt) {
+        C2<double> c[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const C2<T> v = buf[plane_lds_index(geo, k, p)];
-                c[k] = mk<double>((double)v.x, (double)v.y);
-            }
-            M3<double> m;
-            one_plus_alg_reunit(c, m);
-            M3<T> Gt;
-            load_mat<T, NE>(Gt, Gin, VS, s);
-            M3<double> Gd = cast_mat<double>(Gt), r;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    r.e[3 * i + k] =
-                        cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
-            reunit(r);
-            store_mat<T, NE>(cast_mat<T>(r), Gout, VS, s);
+        for (int k = 0; k < 4; ++k) {
+            const C2<T> v = buf[plane_lds_index(geo, k, p)];
+            c[k] = mk<double>((double)v.x, (double)v.y);
         }
+        M3<double> m;
+        one_plus_alg_reunit(c, m);
+        M3<double> Gd = cast_mat<double>(Gt), r;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                r.e[3 * i + k] =
+                    cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
+        reunit(r);
+        store_mat<T, NE>(cast_mat<T>(r), Gout, VS, q0 + p);
+    };
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int p = tid + k * nth;
+        if (p < NP) {
+            M3<T> Gt;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) Gt.e[e] = gpre[k][e];
+            if (NE == 6) rebuild_row3(Gt);
+            update(p, Gt);
+        }
+    }
+    for (int p = tid + PF * nth; p < NP; p += nth) {
+        M3<T> Gt;
+        load_mat<T, NE>(Gt, Gin, VS, q0 + p);
+        update(p, Gt);
     }
 }
 
