@@ -15,6 +15,9 @@ HBM.  Printed as one JSON line:
                  18-real) and mixed FP32/FP64, from freshly loaded links:
                  best of three fixes on one context (the first, which also
                  captures the context's graphs, is reported beside it)
+  mixed_16       16^4, seeds 1-4: plain FP64 against FP32 bulk + FP64 finish
+  batch          64 lattices of three shapes in one lgf_batch (mixed), against
+                 the same lattices fixed one by one in single contexts
   cpu_baseline   the FP64 oracle on this host's cores, a bounded sample
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -73,6 +76,73 @@ def measured_traffic(kernel, dims, storage):
     if not e or e.get("source_digest") != source_digest():
         return None
     return e.get("bytes_per_launch")
+
+
+MIXED16_DIMS = (16, 16, 16, 16)
+
+
+def batch_workload():
+    """64 lattices of three shapes (24 x 8^4, 24 x 16^3 x 32, 16 x 16^4); lattice i
+    has eps = 0.2 + 0.3 i / 63 and seed 1000 + i."""
+    shapes = [(8, 8, 8, 8)] * 24 + [(16, 16, 16, 32)] * 24 + [(16, 16, 16, 16)] * 16
+    return shapes, [0.2 + 0.3 * i / 63 for i in range(64)]
+
+
+def fix_best(ctx, U, tries, torch):
+    """Best of `tries` fixes from freshly loaded links (the first also
+    captures the context's graphs)."""
+    runs = []
+    for _ in range(tries):
+        ctx.load(U)
+        ctx.measure()
+        torch.cuda.synchronize()
+        runs.append(ctx.fix())
+    return min(runs, key=lambda r: r.seconds), runs[0]
+
+
+def mixed_16(L, fields, torch):
+    """16^4, four seeds: plain FP64 against FP32 bulk + FP64 finish."""
+    from paper_1206_0675_amd import lgf
+    out = []
+    for seed, U in fields:
+        rec = {"seed": seed}
+        for label, kw in (("fp64", {}), ("mixed", {"precision": lgf.MIXED})):
+            with lgf.Context(MIXED16_DIMS, lib=L, storage=12, poll_every=8, **kw) as ctx:
+                s, _ = fix_best(ctx, U, 3, torch)
+            rec[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "iters_fp32": s.iter_fp32, "F": s.F,
+                          "theta": s.theta}
+        rec["F_mixed_minus_fp64"] = rec["mixed"]["F"] - rec["fp64"]["F"]
+        out.append(rec)
+    return out
+
+
+def batch_run(L, shapes, Us, torch):
+    """The batch of 64 in one lgf_batch (mixed, 12-real, autotuned) against the
+    same lattices fixed one by one in single contexts."""
+    from paper_1206_0675_amd import lgf
+    with lgf.Batch(shapes, lib=L, precision=lgf.MIXED, storage=12, poll_every=8, autotune=1) as b:
+        best = None
+        for _ in range(2):                 # the first fix also captures the graph
+            for i, U in enumerate(Us):
+                b.load(i, U)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = b.fix()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        cfg = b.config()
+    ok = all(x.status == lgf.OK and x.theta < 1e-15 for x in st)
+    single = 0.0
+    for d, U in zip(shapes, Us):
+        with lgf.Context(d, lib=L, precision=lgf.MIXED, storage=12, poll_every=8) as ctx:
+            s, _ = fix_best(ctx, U, 2, torch)
+            single += s.seconds
+    sites = sum(d[0] * d[1] * d[2] * d[3] for d in shapes)
+    return {"configs": len(shapes), "sites": sites, "all_converged": ok, "seconds": round(best, 5),
+            "configs_per_s": round(len(shapes) / best, 2), "iters_total": int(sum(x.iter for x in st)),
+            "single_contexts_seconds": round(single, 5), "speedup_vs_single": round(single / best, 3),
+            "launch_shape": {"plane_threads": cfg[0], "tile_bytes": cfg[1]}}
 
 
 def shape_sweep(L, dims, R, U, args):
@@ -155,6 +225,17 @@ def main():
         learned_fields = [(seed, synth.random_links(LEARNED_DIMS, seed, workers=args.gen_workers))
                           for seed in range(3000, 3000 + args.learned_seeds)]
         print(f"# generated {len(learned_fields)} fields {LEARNED_DIMS} in {time.time() - t:.1f}s", file=sys.stderr,
+              flush=True)
+
+    extra_inputs = not (args.pmc_sample or args.shape_sweep or args.no_extras)
+    mixed16 = []
+    batch_in = None
+    if extra_inputs:
+        t = time.time()
+        mixed16 = [(seed, synth.random_links(MIXED16_DIMS, seed)) for seed in (1, 2, 3, 4)]
+        shapes, eps = batch_workload()
+        batch_in = (shapes, [synth.random_links(d, 1000 + i, eps=e) for i, (d, e) in enumerate(zip(shapes, eps))])
+        print(f"# generated the 16^4 seeds and the batch of {len(shapes)} in {time.time() - t:.1f}s", file=sys.stderr,
               flush=True)
 
     import torch
@@ -267,6 +348,13 @@ def main():
         learned = {"dims": list(ld), "storage": 12, "runs": runs, "plain_seconds": round(tp, 5),
                    "learned_seconds": round(tl, 5), "speedup": round(tp / tl, 4) if tl > 0 else None}
 
+    # ---- 16^4 mixed precision, and the batch of 64 ----------------------------
+    m16 = mixed_16(L, mixed16, torch) if mixed16 else None
+    batch = batch_run(L, batch_in[0], batch_in[1], torch) if batch_in else None
+    if batch:
+        print(f"# batch of {batch['configs']}: {batch['seconds']:.4f} s, {batch['configs_per_s']} configs/s, "
+              f"{batch['speedup_vs_single']}x one by one", file=sys.stderr, flush=True)
+
     # ---- CPU baseline: the FP64 oracle on this host -------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -309,6 +397,8 @@ def main():
         "kernels": kernels,
         "time_to_theta": extras,
         "learned_vs_plain": learned,
+        "mixed_16": m16,
+        "batch": batch,
         "cpu_baseline": cpu,
         "context": {"paper_c2070_iters_per_s": PAPER_C2070_ITERS_PER_S,
                     "device": torch.cuda.get_device_name(0), "source_digest": source_digest(),
