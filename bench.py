@@ -41,17 +41,18 @@ def alg_bytes(V, s, R):
     """Algorithmic HBM bytes: per iteration and per launch of each kernel.
 
     The links are G U0 G^dag(x+mu), formed where needed from the loaded links
-    U0 and the accumulated gauge G and never stored.  Per site and iteration:
-    U0 read once (4R reals) and G read once (R) by the transform; the packed
-    Delta (8 reals) written once, read and written once by the (z, t) pass,
-    and read once by the gauge kernel (32 reals); G read and written once by
-    the gauge kernel (2R).
+    U0 (R reals per link) and the accumulated gauge G (kept as two rows, 12
+    reals per site, for either link storage) and never stored.  Per site and
+    iteration: U0 read once (4R) and G read once (12) by the transform; the
+    packed Delta (8 reals) written once, read and written once by the (z, t)
+    pass, and read once by the gauge kernel (32 reals); G read and written
+    once by the gauge kernel (24).
     """
     return {
-        "iteration": V * s * (7 * R + 32),
-        "transform_measure": V * s * (4 * R + R + 8),
+        "iteration": V * s * (4 * R + 12 + 32 + 24),
+        "transform_measure": V * s * (4 * R + 12 + 8),
         "zt_fft_scale": V * s * 16,
-        "gauge": V * s * (8 + 2 * R),
+        "gauge": V * s * (8 + 24),
     }
 
 

@@ -271,7 +271,7 @@ int32_t identity_member(lgf_batch* b, int i)
     for (int mu = 0; mu < 4; ++mu)
         TRY(launch(b, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, V, bf.geo.VS,
                    bf.U + (int64_t)mu * NE * bf.geo.VS));
-    return launch(b, K_FIELD, k_field_identity<T, NE>, gr, dim3(256), 0, V, bf.geo.VS, bf.G);
+    return launch(b, K_FIELD, k_field_identity<T, kGE>, gr, dim3(256), 0, V, bf.geo.VS, bf.G);
 }
 
 int32_t identity_all(lgf_batch* b)
@@ -383,7 +383,7 @@ int32_t store_member_gauge(lgf_batch* b, int i, double* dst)
 {
     Bufs<T>& bf = mbufs<T>(b->m[i]);
     const int64_t V = bf.geo.V;
-    return launch(b, K_FIELD, k_field_store<T, NE>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V, bf.geo.VS,
+    return launch(b, K_FIELD, k_field_store<T, kGE>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V, bf.geo.VS,
                   (const C2<T>*)(b->st_host[i].cur ? bf.Gb : bf.G), dst);
 }
 
@@ -570,11 +570,9 @@ int32_t lgf_batch_load(lgf_batch_t b, int32_t i, const void* links, int32_t wher
         if (rc != LGF_OK) break;
         const dim3 gr((unsigned)blocks_for(V, 256));
         if (b->use64)
-            rc = b->NE == 9 ? launch(b, K_FIELD, k_field_identity<double, 9>, gr, dim3(256), 0, V, mm.d.geo.VS, mm.d.G)
-                            : launch(b, K_FIELD, k_field_identity<double, 6>, gr, dim3(256), 0, V, mm.d.geo.VS, mm.d.G);
+            rc = launch(b, K_FIELD, k_field_identity<double, kGE>, gr, dim3(256), 0, V, mm.d.geo.VS, mm.d.G);
         if (rc == LGF_OK && b->use32)
-            rc = b->NE == 9 ? launch(b, K_FIELD, k_field_identity<float, 9>, gr, dim3(256), 0, V, mm.f.geo.VS, mm.f.G)
-                            : launch(b, K_FIELD, k_field_identity<float, 6>, gr, dim3(256), 0, V, mm.f.geo.VS, mm.f.G);
+            rc = launch(b, K_FIELD, k_field_identity<float, kGE>, gr, dim3(256), 0, V, mm.f.geo.VS, mm.f.G);
         if (rc != LGF_OK) break;
         const DevState s0 = initial_state(b, false);
         if (hipMemcpyAsync(b->st + i, &s0, sizeof(DevState), hipMemcpyHostToDevice, b->stream) != hipSuccess ||

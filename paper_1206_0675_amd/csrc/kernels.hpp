@@ -48,6 +48,11 @@ struct Geo {
                     // consecutive rows to other banks for the x-axis FFT passes
 };
 
+// The accumulated gauge G is reunitarised at every step, so its third row is
+// (row 1 x row 2)^* (the same rebuild the projection ends with): G is kept as
+// its first two rows, kGE complex per site, whatever the link storage.
+constexpr int kGE = 6;
+
 // Complex elements of LDS for the four fields of one (x, y) plane.
 __host__ __device__ __forceinline__ int plane_lds_elems(const Geo& g) { return 4 * g.NPP; }
 __host__ __device__ __forceinline__ int plane_lds_index(const Geo& g, int c, int p)
@@ -203,9 +208,9 @@ __global__ void __launch_bounds__(256) k_store_gauged(Geo geo, const C2<T>* __re
     c[mu] = (c[mu] + 1) & (geo.L[mu] - 1);
     const int64_t sn = (((int64_t)c[3] * geo.L[2] + c[2]) * geo.L[1] + c[1]) * geo.L[0] + c[0];
     M3<T> a, u, b, r;
-    load_mat<T, NE>(a, G, geo.VS, s);
+    load_mat<T, kGE>(a, G, geo.VS, s);
     load_mat<T, NE>(u, Uref + (int64_t)mu * NE * geo.VS, geo.VS, s);
-    load_mat<T, NE>(b, G, geo.VS, sn);
+    load_mat<T, kGE>(b, G, geo.VS, sn);
     a_u_bdag<T, (NE == 6 ? 2 : 3)>(a, u, b, r);
     C2<double>* p = reinterpret_cast<C2<double>*>(dst) + li * 9;
 #pragma unroll
@@ -281,13 +286,13 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc.c[c] = mk<T>(T(0), T(0));
         M3<T> gx;
-        load_mat<T, NE>(gx, G, VS, s);
+        load_mat<T, kGE>(gx, G, VS, s);
         double f = 0.0;
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             M3<T> u, gn, r;
             load_mat<T, NE>(u, Uref + (int64_t)mu * NE * VS, VS, s);
-            load_mat<T, NE>(gn, G, VS, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
+            load_mat<T, kGE>(gn, G, VS, mu == 0 ? xp : mu == 1 ? yp : mu == 2 ? qzp + p : qtp + p);
             a_u_bdag<T, (NE == 6 ? 2 : 3)>(gx, u, gn, r);
             f += re_trace(r);
             alg_accumulate(acc, r, T(-1));
@@ -297,7 +302,7 @@ __device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ U
             M3<T> u, gb, r;
             const int64_t sb = nu == 0 ? xm : nu == 1 ? ym : nu == 2 ? qzm + p : qtm + p;
             load_mat<T, NE>(u, Uref + (int64_t)nu * NE * VS, VS, sb);
-            load_mat<T, NE>(gb, G, VS, sb);
+            load_mat<T, kGE>(gb, G, VS, sb);
             a_u_bdag<T, (NE == 6 ? 2 : 3)>(gb, u, gx, r);
             alg_accumulate(acc, r, T(1));
         }
@@ -426,14 +431,14 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
     // G of each thread's first PF sites, loaded into registers here so that
     // the loads complete while the FFT runs in LDS
     const int64_t q0 = (int64_t)q * NP;
-    constexpr int PF = (NE == 9 && sizeof(T) == 8) ? 2 : 4;
-    C2<T> gpre[PF][NE];
+    constexpr int PF = 4;
+    C2<T> gpre[PF][kGE];
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
         const int p = tid + k * nth;
         if (p < NP) {
 #pragma unroll
-            for (int e = 0; e < NE; ++e) gpre[k][e] = Gin[e * VS + q0 + p];
+            for (int e = 0; e < kGE; ++e) gpre[k][e] = Gin[e * VS + q0 + p];
         }
     }
     __syncthreads();
@@ -456,7 +461,7 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
                 r.e[3 * i + k] =
                     cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
         reunit(r);
-        store_mat<T, NE>(cast_mat<T>(r), Gout, VS, q0 + p);
+        store_mat<T, kGE>(cast_mat<T>(r), Gout, VS, q0 + p);
     };
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
@@ -464,14 +469,14 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
         if (p < NP) {
             M3<T> Gt;
 #pragma unroll
-            for (int e = 0; e < NE; ++e) Gt.e[e] = gpre[k][e];
-            if (NE == 6) rebuild_row3(Gt);
+            for (int e = 0; e < kGE; ++e) Gt.e[e] = gpre[k][e];
+            rebuild_row3(Gt);
             update(p, Gt);
         }
     }
     for (int p = tid + PF * nth; p < NP; p += nth) {
         M3<T> Gt;
-        load_mat<T, NE>(Gt, Gin, VS, q0 + p);
+        load_mat<T, kGE>(Gt, Gin, VS, q0 + p);
         update(p, Gt);
     }
 }
@@ -587,10 +592,10 @@ __device__ __forceinline__ void promote_site(int64_t VS32, int64_t VS64, int64_t
                                              C2<double>* __restrict__ G64)
 {
     M3<float> a;
-    load_mat<float, NE>(a, G32, VS32, s);
+    load_mat<float, kGE>(a, G32, VS32, s);
     M3<double> m = cast_mat<double>(a);
     reunit(m);
-    store_mat<double, NE>(m, G64, VS64, s);
+    store_mat<double, kGE>(m, G64, VS64, s);
 }
 
 template <int NE>

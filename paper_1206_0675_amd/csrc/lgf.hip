@@ -303,10 +303,7 @@ int32_t enqueue_identity_G(lgf_context* c)
 {
     Bufs<T>& b = bufs<T>(c);
     const int64_t V = b.geo.V;
-    if (c->NE == 9)
-        return launch(c, K_FIELD, k_field_identity<T, 9>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V,
-                      b.geo.VS, b.G);
-    return launch(c, K_FIELD, k_field_identity<T, 6>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V,
+    return launch(c, K_FIELD, k_field_identity<T, kGE>, dim3((unsigned)blocks_for(V, 256)), dim3(256), 0, V,
                   b.geo.VS, b.G);
 }
 
@@ -949,11 +946,9 @@ int32_t lgf_store_gauge(lgf_ctx c, void* G, int32_t where)
     int32_t rc;
     const dim3 grid((unsigned)blocks_for(V, 256));
     if (c->phase == 1)
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<double, 9>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)g_cur<double>(c), dst)
-                        : launch(c, K_FIELD, k_field_store<double, 6>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)g_cur<double>(c), dst);
+        rc = launch(c, K_FIELD, k_field_store<double, kGE>, grid, dim3(256), 0, V, c->d.geo.VS, (const C2<double>*)g_cur<double>(c), dst);
     else
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_store<float, 9>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)g_cur<float>(c), dst)
-                        : launch(c, K_FIELD, k_field_store<float, 6>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)g_cur<float>(c), dst);
+        rc = launch(c, K_FIELD, k_field_store<float, kGE>, grid, dim3(256), 0, V, c->f.geo.VS, (const C2<float>*)g_cur<float>(c), dst);
     if (rc == LGF_OK && where == LGF_HOST &&
         hipMemcpyAsync(G, dst, nbytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
         rc = fail(c, LGF_E_DEVICE, "hipMemcpyAsync G out");
@@ -983,11 +978,9 @@ int32_t lgf_load_gauge(lgf_ctx c, const void* G, int32_t where)
     const dim3 grid((unsigned)blocks_for(V, 256));
     c->delta_valid = false;                 // the links G U0 G^dag(x+mu) change with G
     if (c->phase == 1)
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<double, 9>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, g_cur<double>(c))
-                        : launch(c, K_FIELD, k_field_load<double, 6>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, g_cur<double>(c));
+        rc = launch(c, K_FIELD, k_field_load<double, kGE>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, g_cur<double>(c));
     else
-        rc = c->NE == 9 ? launch(c, K_FIELD, k_field_load<float, 9>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, g_cur<float>(c))
-                        : launch(c, K_FIELD, k_field_load<float, 6>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, g_cur<float>(c));
+        rc = launch(c, K_FIELD, k_field_load<float, kGE>, grid, dim3(256), 0, V, c->f.geo.VS, (const double*)src, g_cur<float>(c));
     if (rc == LGF_OK) rc = sync_state(c);
     if (where == LGF_HOST) {
         (void)hipStreamSynchronize(c->stream);

@@ -281,7 +281,7 @@ int32_t alloc_bufs(Runner* c, const int32_t* dims, int NE, int tile_bytes, Bufs<
     b.geo = make_geo<T>(dims, tile_bytes);
     const int64_t VS = b.geo.VS;
     const size_t link = sizeof(C2<T>) * (size_t)4 * NE * VS;
-    const size_t field = sizeof(C2<T>) * (size_t)NE * VS;
+    const size_t field = sizeof(C2<T>) * (size_t)kGE * VS;      // G: two rows
     b.d_cap = delta_capacity<T>(dims, tile_bytes);
     const size_t dbytes = sizeof(C2<T>) * (size_t)b.d_cap;
     HIPCHK(c, hipMalloc(&b.U, link));
