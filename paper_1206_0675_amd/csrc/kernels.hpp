@@ -483,8 +483,9 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
 
 // ---------------------------------------------------------------------------
 // a7: F = sum/(12V), theta = sum/(3V) over the per-plane partials in plane
-// order (one block).  counts_update: the partials are of freshly transformed
-// links, so the update is counted and the link buffers swap roles.
+// order (one block).  counts_update: the partials are of the links of the
+// gauge just formed, so the update is counted and that gauge becomes current
+// (cur flips).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void reduce_state(const double* __restrict__ partial, int nq, int64_t V, DevState* st,
                              double* __restrict__ trace, int counts_update, double* red)

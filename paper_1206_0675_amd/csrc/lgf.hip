@@ -744,8 +744,8 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
         return fail(nullptr, LGF_E_INVALID_ARG, "storage must be LGF_STORE18 or LGF_STORE12");
     if (p->step != LGF_STEP_PLAIN && p->step != LGF_STEP_LEARNED)
         return fail(nullptr, LGF_E_INVALID_ARG, "unknown step kind");
-    if (p->step == LGF_STEP_LEARNED && (p->precision != LGF_FP64 || p->track_gauge))
-        return fail(nullptr, LGF_E_INVALID_ARG, "the learned step runs in FP64 without gauge tracking");
+    if (p->step == LGF_STEP_LEARNED && p->precision != LGF_FP64)
+        return fail(nullptr, LGF_E_INVALID_ARG, "the learned step runs in FP64");
     if (p->accel != LGF_ACCEL_FOURIER && p->accel != LGF_ACCEL_NONE)
         return fail(nullptr, LGF_E_INVALID_ARG, "accel must be LGF_ACCEL_FOURIER or LGF_ACCEL_NONE");
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(nullptr, LGF_E_INVALID_ARG, "alpha must be > 0");

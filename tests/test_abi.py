@@ -106,6 +106,13 @@ def test_create_rejects_params_before_touching_the_device(L, field, value):
     assert e.value.code == lgf.E_INVALID_ARG
 
 
+@pytest.mark.parametrize("precision", [lgf.FP32, lgf.MIXED])
+def test_learned_step_needs_fp64(L, precision):
+    with pytest.raises(lgf.LgfError) as e:
+        lgf.Context((8, 8, 8, 8), lib=L, step=lgf.STEP_LEARNED, precision=precision)
+    assert e.value.code == lgf.E_INVALID_ARG
+
+
 def test_error_strings(L):
     for code in range(0, -10, -1):
         assert L.lgf_strerror(code) != b"unknown status"
