@@ -196,6 +196,9 @@ def main():
                     help="for hardware counters: a few iterations, then one plain device copy of "
                          "--copy-mib MiB (a kernel of known traffic that scales FETCH_SIZE/WRITE_SIZE); no JSON")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--batch-sample", action="store_true",
+                    help="run only the batch of 64 (one lgf_batch fix, then the lattices one by one) and print "
+                         "its JSON; for profiling")
     ap.add_argument("--shape-sweep", action="store_true",
                     help="time every launch shape the autotuner chooses from (threads per plane block x tile "
                          "row bytes), one line each; no JSON")
@@ -217,23 +220,25 @@ def main():
     dims = tuple(args.dims)
     V = synth.volume(dims)
     t = time.time()
-    U = synth.random_links(dims, args.seed, workers=args.gen_workers)
-    print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    U = None
+    if not args.batch_sample:
+        U = synth.random_links(dims, args.seed, workers=args.gen_workers)
+        print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
     model_path = os.path.join(ROOT, "paper_1206_0675_amd", "models", "learned_step.bin")
     learned_fields = []
-    if not (args.pmc_sample or args.shape_sweep or args.no_extras) and args.learned_seeds > 0 and os.path.exists(model_path):
+    if not (args.pmc_sample or args.shape_sweep or args.batch_sample or args.no_extras) and args.learned_seeds > 0 and os.path.exists(model_path):
         t = time.time()
         learned_fields = [(seed, synth.random_links(LEARNED_DIMS, seed, workers=args.gen_workers))
                           for seed in range(3000, 3000 + args.learned_seeds)]
         print(f"# generated {len(learned_fields)} fields {LEARNED_DIMS} in {time.time() - t:.1f}s", file=sys.stderr,
               flush=True)
 
-    extra_inputs = not (args.pmc_sample or args.shape_sweep or args.no_extras)
+    extra_inputs = not (args.pmc_sample or args.shape_sweep or args.no_extras) or args.batch_sample
     mixed16 = []
     batch_in = None
     if extra_inputs:
         t = time.time()
-        mixed16 = [(seed, synth.random_links(MIXED16_DIMS, seed)) for seed in (1, 2, 3, 4)]
+        mixed16 = [] if args.batch_sample else [(seed, synth.random_links(MIXED16_DIMS, seed)) for seed in (1, 2, 3, 4)]
         shapes, eps = batch_workload()
         batch_in = (shapes, [synth.random_links(d, 1000 + i, eps=e) for i, (d, e) in enumerate(zip(shapes, eps))])
         print(f"# generated the 16^4 seeds and the batch of {len(shapes)} in {time.time() - t:.1f}s", file=sys.stderr,
@@ -263,6 +268,9 @@ def main():
 
     if args.shape_sweep:
         shape_sweep(L, dims, R, U, args)
+        return
+    if args.batch_sample:
+        print(json.dumps(batch_run(L, batch_in[0], batch_in[1], torch)), flush=True)
         return
 
     # ---- timed iterations (no profiling) -----------------------------------
