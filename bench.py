@@ -57,10 +57,16 @@ def alg_bytes(V, s, R):
 
 
 def source_digest():
+    """Hash of the kernel and launch sources with comments and blank space
+    removed: it changes when the code that was measured changes."""
+    import re
     h = hashlib.sha256()
     for f in ("su3.hpp", "fft.hpp", "kernels.hpp", "runtime.hpp", "lgf.hip"):
-        with open(os.path.join(ROOT, "paper_1206_0675_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1206_0675_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -919,7 +919,7 @@ int32_t lgf_store_links(lgf_ctx c, void* links, int32_t where)
     if (!links || (where != LGF_HOST && where != LGF_DEVICE)) return fail(c, LGF_E_INVALID_ARG, "bad links/where");
     const int64_t V = (c->phase == 1 ? c->d.geo : c->f.geo).V;
     const size_t nbytes = sizeof(double) * 72 * (size_t)V;
-    TRY(sync_state(c));   // the current link buffer is known from the device state
+    TRY(sync_state(c));   // the current gauge buffer is known from the device state
     if (where == LGF_DEVICE) {
         TRY(store_any(c, static_cast<double*>(links)));
         return sync_state(c);
