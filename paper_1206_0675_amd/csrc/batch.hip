@@ -199,7 +199,7 @@ int32_t iteration_t(lgf_batch* b)
 {
     if (b->mixed) {
         const dim3 gp(grid_for(b, b->n_plane, 4));
-        TRY(launch(b, K_SWITCH, kb_promote<NE>, gp, dim3(256), 0, (const BatchCfg<float>*)b->c32,
+        TRY(launch(b, K_SWITCH, kb_promote<>, gp, dim3(256), 0, (const BatchCfg<float>*)b->c32,
                    (const BatchCfg<double>*)b->c64, (const uint32_t*)b->items_plane, b->n_plane));
         TRY(launch(b, K_STATE, kb_switch_done<>, dim3((unsigned)blocks_for(b->n, 64)), dim3(64), 0,
                    (const BatchCfg<double>*)b->c64, b->n));

@@ -588,7 +588,6 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
 // FP64 (so the result lies exactly on the gauge orbit of the input); the
 // promoted gauge is stored as G64.
 // ---------------------------------------------------------------------------
-template <int NE>
 __device__ __forceinline__ void promote_site(int64_t VS32, int64_t VS64, int64_t s, const C2<float>* __restrict__ G32,
                                              C2<double>* __restrict__ G64)
 {
@@ -599,12 +598,12 @@ __device__ __forceinline__ void promote_site(int64_t VS32, int64_t VS64, int64_t
     store_mat<double, kGE>(m, G64, VS64, s);
 }
 
-template <int NE>
+template <int UNUSED = 0>
 __global__ void __launch_bounds__(256) k_promote_gauge(int64_t V, int64_t VS32, int64_t VS64,
                                                        const C2<float>* __restrict__ G32, C2<double>* __restrict__ G64)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < V) promote_site<NE>(VS32, VS64, s, G32, G64);
+    if (s < V) promote_site(VS32, VS64, s, G32, G64);
 }
 
 // ===========================================================================
@@ -703,7 +702,7 @@ __global__ void __launch_bounds__(256) kb_reduce(const BatchCfg<T>* __restrict__
 // Mixed runs: the FP32 phase of a configuration ended (switch_pending).
 // Step 1: G64[0] = reunit(G32[cur]); step 2: FP64 phase with cur = 0, whose
 // links are G64 U0 G64^dag(x+mu) for the loaded FP64 links, to be measured.
-template <int NE>
+template <int UNUSED = 0>
 __global__ void __launch_bounds__(256) kb_promote(const BatchCfg<float>* __restrict__ c32,
                                                   const BatchCfg<double>* __restrict__ c64,
                                                   const uint32_t* __restrict__ items, int nitems)
@@ -715,7 +714,7 @@ __global__ void __launch_bounds__(256) kb_promote(const BatchCfg<float>* __restr
         const Geo& geo = c64[cfg].geo;
         const int64_t q0 = (int64_t)(w & ((1u << kItemShift) - 1)) * geo.NP;
         for (int p = threadIdx.x; p < geo.NP; p += blockDim.x)
-            promote_site<NE>(c32[cfg].geo.VS, geo.VS, q0 + p, c32[cfg].G[c64[cfg].st->cur], c64[cfg].G[0]);
+            promote_site(c32[cfg].geo.VS, geo.VS, q0 + p, c32[cfg].G[c64[cfg].st->cur], c64[cfg].G[0]);
     }
 }
 

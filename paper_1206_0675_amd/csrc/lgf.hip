@@ -72,7 +72,6 @@ struct lgf_context : Runner {
     bool own_stream = false;
     int phase = 1;            // 1: FP64 arithmetic, 0: FP32
     bool use64 = false, use32 = false;
-    bool track = false;
     bool loaded = false;
     bool delta_valid = false; // D and the state hold Delta, F, theta of the current links
     Bufs<double> d;
@@ -310,11 +309,10 @@ int32_t enqueue_identity_G(lgf_context* c)
 // LGF_MIXED: leave FP32.  G64[0] = reunit(G32[cur]); the FP64 phase then
 // forms G64 U0 G64^dag(x+mu) from the loaded FP64 links (the state's cur is
 // reset to 0 with the phase).
-template <int NE>
 int32_t enqueue_switch(lgf_context* c)
 {
     const Geo& g = c->d.geo;
-    return launch(c, K_SWITCH, k_promote_gauge<NE>, dim3((unsigned)blocks_for(g.V, 256)), dim3(256), 0, g.V,
+    return launch(c, K_SWITCH, k_promote_gauge<>, dim3((unsigned)blocks_for(g.V, 256)), dim3(256), 0, g.V,
                   c->f.geo.VS, g.VS, (const C2<float>*)g_cur<float>(c), c->d.G);
 }
 
@@ -769,7 +767,6 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
     c->NE = p->storage == LGF_STORE12 ? 6 : 9;
     c->use64 = use64;
     c->use32 = use32;
-    c->track = true;          // G is the state: the links are G U0 G^dag(x+mu)
     c->phase = use64 && !use32 ? 1 : 0;
     c->nth_plane = nth;
     for (int m = 0; m < 4; ++m)
@@ -1082,7 +1079,7 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
         if (!fp32_mixed) break;
         // FP32 phase done: rebuild the links in FP64 on the orbit of the input
         c->iter_fp32 = c->st_host->iter;
-        TRY(c->NE == 9 ? enqueue_switch<9>(c) : enqueue_switch<6>(c));
+        TRY(enqueue_switch(c));
         TRY(launch(c, K_STATE, k_state_phase, dim3(1), dim3(1), 0, c->st, 1));
         c->phase = 1;
         c->delta_valid = false;

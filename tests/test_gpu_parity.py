@@ -95,7 +95,7 @@ def test_one_and_ten_steps(L, oracle_lib, dims, kw):
 def test_fix_final_F(L, oracle_lib, dims, seed):
     U = links(dims, seed)
     announce(f"fix {dims} seed {seed}")
-    with lgf.Context(dims, lib=L, track_gauge=1, poll_every=8) as ctx:
+    with lgf.Context(dims, lib=L, poll_every=8) as ctx:
         ctx.load(U)
         s = ctx.fix()
         Ug, G = ctx.store(), ctx.store_gauge()
