@@ -1,6 +1,6 @@
 """Train the learned spectral step on the GPU.
 
-    python -m paper_1206_0675_amd.train_learned [--configs 256] [--rounds 2] [--out DIR]
+    python -m paper_1206_0675_amd.train_learned [--configs 256] [--rounds 1] [--out DIR]
 
 1. Generate the training fields (seeds 2000, 2001, ... of the seeded
    generator, 16^4, plaquette 0.6).
@@ -10,9 +10,11 @@
    golden-section search on the GPU).  Train the 16-64-64-16 network on these
    samples with the library's own forward, backward and Adam kernels
    (lgf_mlp_train).
-3. Later rounds: collect the same way along the trajectories of the learned
-   step with the current network (the states it actually visits), add them
-   to the samples and train again.
+3. Later rounds (--rounds > 1, off by default): collect the same way along
+   the trajectories of the learned step with the current network, add them to
+   the samples and train again.  On 32^3 x 64 a one-round network needed
+   43-48 iterations with one fallback per run; a two-round one 44-49 with 7-13
+   fallbacks, and a three-round one 68-85.
 4. Write the model blob and a JSON record of the run.
 """
 from __future__ import annotations
@@ -98,7 +100,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--rounds", type=int, default=2)
+    ap.add_argument("--rounds", type=int, default=1)
     ap.add_argument("--out", default=MODEL_DIR)
     args = ap.parse_args(argv)
     t0 = time.time()
