@@ -215,8 +215,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported. "
-              "A multi-GPU layout is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
+              "there is no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import synth
