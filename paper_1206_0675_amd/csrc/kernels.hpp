@@ -60,6 +60,26 @@ __host__ __device__ __forceinline__ int plane_lds_index(const Geo& g, int c, int
     return c * g.NPP + (p >> g.logL[0]) * g.RP + (p & (g.L[0] - 1));
 }
 
+// buf[di(i)] = src[si(i)] for i < n, spread over the block.  Each thread
+// issues U loads before its first LDS write, so U memory round trips overlap
+// (a loop of single copies waits out one round trip per element).
+template <int U, typename T, typename SrcIdx, typename DstIdx>
+__device__ __forceinline__ void gather_to_lds(C2<T>* buf, const C2<T>* __restrict__ src, int n, int tid, int nth,
+                                              SrcIdx si, DstIdx di)
+{
+    int i = tid;
+    for (; i + (U - 1) * nth < n; i += U * nth) {
+        C2<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = src[si(i + u * nth)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) buf[di(i + u * nth)] = v[u];
+    }
+    for (; i < n; i += nth) buf[di(i)] = src[si(i)];
+}
+
+__device__ __forceinline__ int ident_index(int i) { return i; }
+
 // Per-configuration state on the device.  The host reads it back only at
 // poll points; kernels of an iteration skip a configuration whose `done` is
 // set, so iterations queued past convergence do nothing.
@@ -394,7 +414,7 @@ __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, co
     const int tid = threadIdx.x, nth = blockDim.x;
     const int W = geo.W, NQ = geo.NQ, n = NQ * W;
     C2<T>* src = D + (int64_t)(j * 4 + c) * geo.DS;
-    for (int i = tid; i < n; i += nth) buf[i] = src[i];
+    gather_to_lds<8>(buf, src, n, tid, nth, ident_index, ident_index);
     __syncthreads();
     const int Lz = geo.L[2];
     const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
@@ -424,10 +444,13 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
     const int tid = threadIdx.x, nth = blockDim.x;
     const int NP = geo.NP, W = geo.W;
     const int64_t VS = geo.VS;
-    for (int i = tid; i < 4 * NP; i += nth) {
-        const int c = i >> geo.logNP, p = i & (NP - 1);
-        buf[plane_lds_index(geo, c, p)] = D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))];
-    }
+    gather_to_lds<8>(
+        buf, D, 4 * NP, tid, nth,
+        [&](int i) {
+            const int c = i >> geo.logNP, p = i & (NP - 1);
+            return (int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1));
+        },
+        [&](int i) { return plane_lds_index(geo, i >> geo.logNP, i & (NP - 1)); });
     // G of each thread's first PF sites, loaded into registers here so that
     // the loads complete while the FFT runs in LDS
     const int64_t q0 = (int64_t)q * NP;
@@ -757,7 +780,7 @@ __global__ void __launch_bounds__(512) k_zt_fwd_bands(Geo geo, const C2<T>* __re
     const C2<T>* src = Din + (int64_t)(j * 4 + c) * geo.DS;
     C2<T>* dst = Dspec + (int64_t)(j * 4 + c) * geo.DS;
     const int8_t* bt = btab + (int64_t)j * n;
-    for (int i = tid; i < n; i += nth) buf[i] = src[i];
+    gather_to_lds<8>(buf, src, n, tid, nth, ident_index, ident_index);
     __syncthreads();
     const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
     const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
