@@ -131,19 +131,25 @@ __device__ __forceinline__ C2<T>* line_base(C2<T>* buf, const Lines& a, int line
     return buf + l_lo * a.s_lo + l_hi * a.s_hi;
 }
 
-// pass A (forward) or A^-1 (inverse); tw = W_L^k, k < L
+// pass A (forward) or A^-1 (inverse); tw = W_L^k, k < L.  Reads the lines
+// from `in` and writes them to `out` at the same offsets: in place when both
+// are the LDS buffer, or from / to a global array of the same layout, which
+// saves an LDS copy of the whole block.
 template <typename T, int R1, int R2, bool INV>
-__device__ void fft_pass_a(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
+__device__ __forceinline__ void fft_pass_a(const C2<T>* in, C2<T>* out, const Lines a, const C2<T>* __restrict__ tw,
+                                           int tid, int nth)
 {
     const int ntask = R2 << (a.lo_log + a.hi_log);
     const int es = a.es, st = R2 * es;
     for (int t = tid; t < ntask; t += nth) {
         int k2, line;
         task_split(t, R2, a, k2, line);
-        C2<T>* p = line_base(buf, a, line) + k2 * es;
+        const int64_t off = line_base(out, a, line) - out + k2 * es;
+        const C2<T>* pi = in + off;
+        C2<T>* p = out + off;
         C2<T> v[R1];
 #pragma unroll
-        for (int m = 0; m < R1; ++m) v[m] = p[m * st];
+        for (int m = 0; m < R1; ++m) v[m] = pi[m * st];
         if (!INV) {
             dft<T, R1, false>(v);
             if (R2 > 1 && k2 != 0) {
@@ -163,9 +169,15 @@ __device__ void fft_pass_a(C2<T>* buf, const Lines a, const C2<T>* __restrict__ 
     __syncthreads();
 }
 
+template <typename T, int R1, int R2, bool INV>
+__device__ __forceinline__ void fft_pass_a(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
+{
+    fft_pass_a<T, R1, R2, INV>(buf, buf, a, tw, tid, nth);
+}
+
 // pass B (forward) or B^-1 (inverse): R2-point DFTs of contiguous groups
 template <typename T, int R1, int R2, bool INV>
-__device__ void fft_pass_b(C2<T>* buf, const Lines a, int tid, int nth)
+__device__ __forceinline__ void fft_pass_b(C2<T>* buf, const Lines a, int tid, int nth)
 {
     if constexpr (R2 > 1) {
         const int ntask = R1 << (a.lo_log + a.hi_log);
@@ -186,47 +198,66 @@ __device__ void fft_pass_b(C2<T>* buf, const Lines a, int tid, int nth)
 }
 
 template <typename T, int L>
-__device__ __forceinline__ void fft_fwd_L(C2<T>* buf, const Lines& a, const C2<T>* tw, int tid, int nth)
+__device__ __forceinline__ void fft_fwd_L(const C2<T>* in, C2<T>* buf, const Lines& a, const C2<T>* tw, int tid,
+                                          int nth)
 {
-    fft_pass_a<T, fft_r1(L), fft_r2(L), false>(buf, a, tw, tid, nth);
+    fft_pass_a<T, fft_r1(L), fft_r2(L), false>(in, buf, a, tw, tid, nth);
     fft_pass_b<T, fft_r1(L), fft_r2(L), false>(buf, a, tid, nth);
 }
 
 template <typename T, int L>
-__device__ __forceinline__ void fft_inv_L(C2<T>* buf, const Lines& a, const C2<T>* tw, int tid, int nth)
+__device__ __forceinline__ void fft_inv_L(C2<T>* buf, C2<T>* out, const Lines& a, const C2<T>* tw, int tid, int nth)
 {
     fft_pass_b<T, fft_r1(L), fft_r2(L), true>(buf, a, tid, nth);
-    fft_pass_a<T, fft_r1(L), fft_r2(L), true>(buf, a, tw, tid, nth);
+    fft_pass_a<T, fft_r1(L), fft_r2(L), true>(buf, out, a, tw, tid, nth);
 }
 
 // Forward transform of every line (output in mode_of_position order).  L is
 // a power of two in [4, LMAX]; kernels built for LMAX = 64 carry no code (and
 // no register demand) for longer lines.
 template <typename T, int LMAX>
-__device__ void fft_fwd(C2<T>* buf, int L, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
+__device__ __forceinline__ void fft_fwd(const C2<T>* in, C2<T>* buf, int L, const Lines a,
+                                        const C2<T>* __restrict__ tw, int tid, int nth)
 {
     switch (L) {
-    case 4: fft_fwd_L<T, 4>(buf, a, tw, tid, nth); break;
-    case 8: fft_fwd_L<T, 8>(buf, a, tw, tid, nth); break;
-    case 16: fft_fwd_L<T, 16>(buf, a, tw, tid, nth); break;
-    case 32: fft_fwd_L<T, 32>(buf, a, tw, tid, nth); break;
-    case 64: fft_fwd_L<T, 64>(buf, a, tw, tid, nth); break;
-    default: if constexpr (LMAX >= 128) fft_fwd_L<T, 128>(buf, a, tw, tid, nth); break;
+    case 4: fft_fwd_L<T, 4>(in, buf, a, tw, tid, nth); break;
+    case 8: fft_fwd_L<T, 8>(in, buf, a, tw, tid, nth); break;
+    case 16: fft_fwd_L<T, 16>(in, buf, a, tw, tid, nth); break;
+    case 32: fft_fwd_L<T, 32>(in, buf, a, tw, tid, nth); break;
+    case 64: fft_fwd_L<T, 64>(in, buf, a, tw, tid, nth); break;
+    default: if constexpr (LMAX >= 128) fft_fwd_L<T, 128>(in, buf, a, tw, tid, nth); break;
     }
+}
+
+// The same transform, in place in buf.
+template <typename T, int LMAX>
+__device__ __forceinline__ void fft_fwd(C2<T>* buf, int L, const Lines a, const C2<T>* __restrict__ tw, int tid,
+                                        int nth)
+{
+    fft_fwd<T, LMAX>(buf, buf, L, a, tw, tid, nth);
 }
 
 // Inverse (unnormalised) transform of every line; undoes fft_fwd up to L.
 template <typename T, int LMAX>
-__device__ void fft_inv(C2<T>* buf, int L, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth)
+__device__ __forceinline__ void fft_inv(C2<T>* buf, C2<T>* out, int L, const Lines a, const C2<T>* __restrict__ tw,
+                                        int tid, int nth)
 {
     switch (L) {
-    case 4: fft_inv_L<T, 4>(buf, a, tw, tid, nth); break;
-    case 8: fft_inv_L<T, 8>(buf, a, tw, tid, nth); break;
-    case 16: fft_inv_L<T, 16>(buf, a, tw, tid, nth); break;
-    case 32: fft_inv_L<T, 32>(buf, a, tw, tid, nth); break;
-    case 64: fft_inv_L<T, 64>(buf, a, tw, tid, nth); break;
-    default: if constexpr (LMAX >= 128) fft_inv_L<T, 128>(buf, a, tw, tid, nth); break;
+    case 4: fft_inv_L<T, 4>(buf, out, a, tw, tid, nth); break;
+    case 8: fft_inv_L<T, 8>(buf, out, a, tw, tid, nth); break;
+    case 16: fft_inv_L<T, 16>(buf, out, a, tw, tid, nth); break;
+    case 32: fft_inv_L<T, 32>(buf, out, a, tw, tid, nth); break;
+    case 64: fft_inv_L<T, 64>(buf, out, a, tw, tid, nth); break;
+    default: if constexpr (LMAX >= 128) fft_inv_L<T, 128>(buf, out, a, tw, tid, nth); break;
     }
+}
+
+// The same transform, in place in buf.
+template <typename T, int LMAX>
+__device__ __forceinline__ void fft_inv(C2<T>* buf, int L, const Lines a, const C2<T>* __restrict__ tw, int tid,
+                                        int nth)
+{
+    fft_inv<T, LMAX>(buf, buf, L, a, tw, tid, nth);
 }
 
 }  // namespace lgf

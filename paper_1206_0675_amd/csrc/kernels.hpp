@@ -412,14 +412,15 @@ __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, co
                          const C2<T>* __restrict__ twt, const SpectralScale& sc, C2<T>* buf)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int W = geo.W, NQ = geo.NQ, n = NQ * W;
+    const int W = geo.W;
     C2<T>* src = D + (int64_t)(j * 4 + c) * geo.DS;
-    gather_to_lds<8>(buf, src, n, tid, nth, ident_index, ident_index);
-    __syncthreads();
     const int Lz = geo.L[2];
     const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
     const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
-    fft_fwd<T, LMAX>(buf, Lz, zl, twz, tid, nth);
+    // The tile in global memory has the layout of buf (index q W + w), so the
+    // first z pass reads its lines from global memory and the last one writes
+    // them back there.
+    fft_fwd<T, LMAX>(src, buf, Lz, zl, twz, tid, nth);
     switch (geo.L[3]) {
     case 4: zt_t_axis<T, 4>(buf, tl, twt, tid, nth, sc, geo, j); break;
     case 8: zt_t_axis<T, 8>(buf, tl, twt, tid, nth, sc, geo, j); break;
@@ -428,8 +429,7 @@ __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, co
     case 64: zt_t_axis<T, 64>(buf, tl, twt, tid, nth, sc, geo, j); break;
     default: if constexpr (LMAX >= 128) zt_t_axis<T, 128>(buf, tl, twt, tid, nth, sc, geo, j); break;
     }
-    fft_inv<T, LMAX>(buf, Lz, zl, twz, tid, nth);
-    for (int i = tid; i < n; i += nth) src[i] = buf[i];
+    fft_inv<T, LMAX>(buf, src, Lz, zl, twz, tid, nth);
 }
 
 // ---------------------------------------------------------------------------
