@@ -281,9 +281,10 @@ __global__ void __launch_bounds__(256) k_field_identity(int64_t V, int64_t VS, C
 //   red: 2 * blockDim doubles of LDS; buf: plane_lds_elems(geo) complex of LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int NE, int LMAX>
-__device__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ Uref, const C2<T>* __restrict__ G,
-                              C2<T>* __restrict__ D, double* __restrict__ partial, const C2<T>* __restrict__ twx,
-                              const C2<T>* __restrict__ twy, double* red, C2<T>* buf)
+__device__ __forceinline__ void measure_plane(const Geo& geo, int q, const C2<T>* __restrict__ Uref,
+                                              const C2<T>* __restrict__ G, C2<T>* __restrict__ D,
+                                              double* __restrict__ partial, const C2<T>* __restrict__ twx,
+                                              const C2<T>* __restrict__ twy, double* red, C2<T>* buf)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int Lx = geo.L[0], Ly = geo.L[1], Lz = geo.L[2], Lt = geo.L[3];
