@@ -112,3 +112,23 @@ def test_linesearch_linear_regime_closed_form(oracle_lib):
     assert np.all(ls[~held] == 0.0)
     th0 = oracle.measure(dims, U)[1]
     assert best < 1e-3 * th0 and oracle.measure(dims, oracle.step(dims, U, 1)[0])[1] > 0.07 * th0
+
+
+def test_forward_matches_torch_float64():
+    """The oracle's network forward against torch's float64 linear layers and
+    ReLU on the same bf16-rounded weights and float32 biases, plus the factor
+    map s = exp(clip(y, -2.3, 2.3)) written out here."""
+    p = random_params(21, scale=0.4)
+    rng = np.random.default_rng(22)
+    x = rng.normal(size=(64, 16)) * 2.0
+    y, _ = mlp.forward(p, x)
+    t = {k: torch.from_numpy(np.asarray(v, dtype=np.float64)) for k, v in p.items()}
+    h = torch.relu(torch.nn.functional.linear(torch.from_numpy(x), t["W1"].T, t["b1"]))
+    h = torch.relu(torch.nn.functional.linear(h, t["W2"].T, t["b2"]))
+    yt = torch.nn.functional.linear(h, t["W3"].T, t["b3"]).numpy()
+    assert np.max(np.abs(y - yt)) <= 1e-13 * max(1.0, np.max(np.abs(yt)))
+    # some outputs must land on each side of the clip, so the map is exercised
+    assert np.any(np.abs(yt) > 2.3) and np.any(np.abs(yt) < 2.3)
+    for i in range(8):
+        s = mlp.factors(p, x[i])
+        assert np.max(np.abs(s - np.exp(np.minimum(np.maximum(yt[i], -2.3), 2.3)))) <= 1e-13 * np.max(s)

@@ -452,3 +452,50 @@ def test_golden_trajectory_8x4_seed1(oracle_lib):
     _, tf, tt, _ = oracle.step(dims, synth.random_links(dims, 1), len(rows) - 1)
     assert np.max(np.abs(tf - rows[:, 1])) <= 1e-13
     assert np.max(np.abs(tt - rows[:, 2]) / rows[:, 2]) <= 1e-10
+
+
+def _np_unitarity(m):
+    """max |M M^dag - 1| (entry-wise complex modulus) and max |det M - 1|, in numpy."""
+    m = np.asarray(m, dtype=np.complex128).reshape(-1, 3, 3)
+    dev = np.abs(m @ dag(m) - np.eye(3))
+    return float(np.max(dev)), float(np.max(np.abs(np.linalg.det(m) - 1.0)))
+
+
+def test_unitarity_reports_a_perturbed_entry(oracle_lib):
+    """The checker must report, not only pass: one entry of one matrix in a
+    batch of SU(3) matrices moved by 1e-9 gives that size of error, equal to
+    numpy's to rounding."""
+    m = synth.haar_su3(5, 50)
+    assert max(oracle.unitarity(m)) <= 1e-14
+    for k, (i, j) in ((0, (0, 0)), (23, (1, 2)), (49, (2, 1))):
+        p = m.copy()
+        p[k, i, j] += 1e-9 * (1 + 1j)
+        mu, md = oracle.unitarity(p)
+        nu, nd = _np_unitarity(p)
+        assert 5e-10 <= mu <= 5e-9 and 1e-10 <= md <= 5e-9
+        assert abs(mu - nu) <= 1e-15 and abs(md - nd) <= 1e-15
+
+
+def test_unitarity_reports_a_u3_phase(oracle_lib):
+    """A U(3) matrix with det = exp(i phi) is unitary but not special: the
+    unitarity error stays at rounding and the det error is |exp(i phi) - 1|."""
+    m = synth.haar_su3(6, 8)
+    for phi in (1e-6, 0.3, np.pi / 2, 3.0):
+        p = m.copy()
+        p[3] = p[3] * np.exp(1j * phi / 3.0)
+        mu, md = oracle.unitarity(p)
+        assert mu <= 1e-14
+        assert abs(md - 2.0 * np.sin(phi / 2.0)) <= 1e-15 * max(1.0, 1e3 * phi)
+        nu, nd = _np_unitarity(p)
+        assert abs(mu - nu) <= 1e-15 and abs(md - nd) <= 1e-15
+
+
+def test_unitarity_reports_nonfinite(oracle_lib):
+    """A NaN anywhere in the batch makes both reported errors NaN (a checker
+    that skipped it would pass a broken field)."""
+    m = synth.haar_su3(7, 10)
+    for k in (0, 4, 9):
+        p = m.copy()
+        p[k, 1, 1] = complex(np.nan, 0.0)
+        mu, md = oracle.unitarity(p)
+        assert np.isnan(mu) and np.isnan(md)
