@@ -123,33 +123,43 @@ __device__ __forceinline__ void task_split(int t, int R, const Lines& a, int& kk
     }
 }
 
-template <typename T>
-__device__ __forceinline__ C2<T>* line_base(C2<T>* buf, const Lines& a, int line)
+__device__ __forceinline__ int line_offset(const Lines& a, int line)
 {
     const int l_lo = line & ((1 << a.lo_log) - 1);
     const int l_hi = line >> a.lo_log;
-    return buf + l_lo * a.s_lo + l_hi * a.s_hi;
+    return l_lo * a.s_lo + l_hi * a.s_hi;
+}
+
+template <typename T>
+__device__ __forceinline__ C2<T>* line_base(C2<T>* buf, const Lines& a, int line)
+{
+    return buf + line_offset(a, line);
+}
+
+template <typename T>
+__device__ __forceinline__ const C2<T>* line_base(const C2<T>* buf, const Lines& a, int line)
+{
+    return buf + line_offset(a, line);
 }
 
 // pass A (forward) or A^-1 (inverse); tw = W_L^k, k < L.  Reads the lines
-// from `in` and writes them to `out` at the same offsets: in place when both
-// are the LDS buffer, or from / to a global array of the same layout, which
-// saves an LDS copy of the whole block.
+// from `in` (laid out as ai) and writes them to `out` (laid out as ao; both
+// layouts hold the same set of lines): in place when both are the LDS buffer,
+// or from / to a global array, which saves an LDS copy of the whole block.
 template <typename T, int R1, int R2, bool INV>
-__device__ __forceinline__ void fft_pass_a(const C2<T>* in, C2<T>* out, const Lines a, const C2<T>* __restrict__ tw,
-                                           int tid, int nth)
+__device__ __forceinline__ void fft_pass_a(const C2<T>* in, const Lines ai, C2<T>* out, const Lines ao,
+                                           const C2<T>* __restrict__ tw, int tid, int nth)
 {
-    const int ntask = R2 << (a.lo_log + a.hi_log);
-    const int es = a.es, st = R2 * es;
+    const int ntask = R2 << (ao.lo_log + ao.hi_log);
+    const int sti = R2 * ai.es, sto = R2 * ao.es;
     for (int t = tid; t < ntask; t += nth) {
         int k2, line;
-        task_split(t, R2, a, k2, line);
-        const int64_t off = line_base(out, a, line) - out + k2 * es;
-        const C2<T>* pi = in + off;
-        C2<T>* p = out + off;
+        task_split(t, R2, ao, k2, line);
+        const C2<T>* pi = line_base(in, ai, line) + k2 * ai.es;
+        C2<T>* p = line_base(out, ao, line) + k2 * ao.es;
         C2<T> v[R1];
 #pragma unroll
-        for (int m = 0; m < R1; ++m) v[m] = pi[m * st];
+        for (int m = 0; m < R1; ++m) v[m] = pi[m * sti];
         if (!INV) {
             dft<T, R1, false>(v);
             if (R2 > 1 && k2 != 0) {
@@ -164,9 +174,16 @@ __device__ __forceinline__ void fft_pass_a(const C2<T>* in, C2<T>* out, const Li
             dft<T, R1, true>(v);
         }
 #pragma unroll
-        for (int m = 0; m < R1; ++m) p[m * st] = v[m];
+        for (int m = 0; m < R1; ++m) p[m * sto] = v[m];
     }
     __syncthreads();
+}
+
+template <typename T, int R1, int R2, bool INV>
+__device__ __forceinline__ void fft_pass_a(const C2<T>* in, C2<T>* out, const Lines a, const C2<T>* __restrict__ tw,
+                                           int tid, int nth)
+{
+    fft_pass_a<T, R1, R2, INV>(in, a, out, a, tw, tid, nth);
 }
 
 template <typename T, int R1, int R2, bool INV>
@@ -198,35 +215,44 @@ __device__ __forceinline__ void fft_pass_b(C2<T>* buf, const Lines a, int tid, i
 }
 
 template <typename T, int L>
-__device__ __forceinline__ void fft_fwd_L(const C2<T>* in, C2<T>* buf, const Lines& a, const C2<T>* tw, int tid,
-                                          int nth)
+__device__ __forceinline__ void fft_fwd_L(const C2<T>* in, const Lines& ai, C2<T>* buf, const Lines& a,
+                                          const C2<T>* tw, int tid, int nth)
 {
-    fft_pass_a<T, fft_r1(L), fft_r2(L), false>(in, buf, a, tw, tid, nth);
+    fft_pass_a<T, fft_r1(L), fft_r2(L), false>(in, ai, buf, a, tw, tid, nth);
     fft_pass_b<T, fft_r1(L), fft_r2(L), false>(buf, a, tid, nth);
 }
 
 template <typename T, int L>
-__device__ __forceinline__ void fft_inv_L(C2<T>* buf, C2<T>* out, const Lines& a, const C2<T>* tw, int tid, int nth)
+__device__ __forceinline__ void fft_inv_L(C2<T>* buf, const Lines& a, C2<T>* out, const Lines& ao, const C2<T>* tw,
+                                          int tid, int nth)
 {
     fft_pass_b<T, fft_r1(L), fft_r2(L), true>(buf, a, tid, nth);
-    fft_pass_a<T, fft_r1(L), fft_r2(L), true>(buf, out, a, tw, tid, nth);
+    fft_pass_a<T, fft_r1(L), fft_r2(L), true>(buf, a, out, ao, tw, tid, nth);
 }
 
-// Forward transform of every line (output in mode_of_position order).  L is
-// a power of two in [4, LMAX]; kernels built for LMAX = 64 carry no code (and
-// no register demand) for longer lines.
+// Forward transform of every line (output in mode_of_position order), read
+// from `in` laid out as ai into buf laid out as a.  L is a power of two in
+// [4, LMAX]; kernels built for LMAX = 64 carry no code (and no register
+// demand) for longer lines.
+template <typename T, int LMAX>
+__device__ __forceinline__ void fft_fwd(const C2<T>* in, const Lines ai, C2<T>* buf, int L, const Lines a,
+                                        const C2<T>* __restrict__ tw, int tid, int nth)
+{
+    switch (L) {
+    case 4: fft_fwd_L<T, 4>(in, ai, buf, a, tw, tid, nth); break;
+    case 8: fft_fwd_L<T, 8>(in, ai, buf, a, tw, tid, nth); break;
+    case 16: fft_fwd_L<T, 16>(in, ai, buf, a, tw, tid, nth); break;
+    case 32: fft_fwd_L<T, 32>(in, ai, buf, a, tw, tid, nth); break;
+    case 64: fft_fwd_L<T, 64>(in, ai, buf, a, tw, tid, nth); break;
+    default: if constexpr (LMAX >= 128) fft_fwd_L<T, 128>(in, ai, buf, a, tw, tid, nth); break;
+    }
+}
+
 template <typename T, int LMAX>
 __device__ __forceinline__ void fft_fwd(const C2<T>* in, C2<T>* buf, int L, const Lines a,
                                         const C2<T>* __restrict__ tw, int tid, int nth)
 {
-    switch (L) {
-    case 4: fft_fwd_L<T, 4>(in, buf, a, tw, tid, nth); break;
-    case 8: fft_fwd_L<T, 8>(in, buf, a, tw, tid, nth); break;
-    case 16: fft_fwd_L<T, 16>(in, buf, a, tw, tid, nth); break;
-    case 32: fft_fwd_L<T, 32>(in, buf, a, tw, tid, nth); break;
-    case 64: fft_fwd_L<T, 64>(in, buf, a, tw, tid, nth); break;
-    default: if constexpr (LMAX >= 128) fft_fwd_L<T, 128>(in, buf, a, tw, tid, nth); break;
-    }
+    fft_fwd<T, LMAX>(in, a, buf, L, a, tw, tid, nth);
 }
 
 // The same transform, in place in buf.
@@ -234,22 +260,30 @@ template <typename T, int LMAX>
 __device__ __forceinline__ void fft_fwd(C2<T>* buf, int L, const Lines a, const C2<T>* __restrict__ tw, int tid,
                                         int nth)
 {
-    fft_fwd<T, LMAX>(buf, buf, L, a, tw, tid, nth);
+    fft_fwd<T, LMAX>(buf, a, buf, L, a, tw, tid, nth);
 }
 
 // Inverse (unnormalised) transform of every line; undoes fft_fwd up to L.
+// The result goes to `out` laid out as ao.
+template <typename T, int LMAX>
+__device__ __forceinline__ void fft_inv(C2<T>* buf, const Lines a, C2<T>* out, const Lines ao, int L,
+                                        const C2<T>* __restrict__ tw, int tid, int nth)
+{
+    switch (L) {
+    case 4: fft_inv_L<T, 4>(buf, a, out, ao, tw, tid, nth); break;
+    case 8: fft_inv_L<T, 8>(buf, a, out, ao, tw, tid, nth); break;
+    case 16: fft_inv_L<T, 16>(buf, a, out, ao, tw, tid, nth); break;
+    case 32: fft_inv_L<T, 32>(buf, a, out, ao, tw, tid, nth); break;
+    case 64: fft_inv_L<T, 64>(buf, a, out, ao, tw, tid, nth); break;
+    default: if constexpr (LMAX >= 128) fft_inv_L<T, 128>(buf, a, out, ao, tw, tid, nth); break;
+    }
+}
+
 template <typename T, int LMAX>
 __device__ __forceinline__ void fft_inv(C2<T>* buf, C2<T>* out, int L, const Lines a, const C2<T>* __restrict__ tw,
                                         int tid, int nth)
 {
-    switch (L) {
-    case 4: fft_inv_L<T, 4>(buf, out, a, tw, tid, nth); break;
-    case 8: fft_inv_L<T, 8>(buf, out, a, tw, tid, nth); break;
-    case 16: fft_inv_L<T, 16>(buf, out, a, tw, tid, nth); break;
-    case 32: fft_inv_L<T, 32>(buf, out, a, tw, tid, nth); break;
-    case 64: fft_inv_L<T, 64>(buf, out, a, tw, tid, nth); break;
-    default: if constexpr (LMAX >= 128) fft_inv_L<T, 128>(buf, out, a, tw, tid, nth); break;
-    }
+    fft_inv<T, LMAX>(buf, a, out, a, L, tw, tid, nth);
 }
 
 // The same transform, in place in buf.
@@ -257,7 +291,7 @@ template <typename T, int LMAX>
 __device__ __forceinline__ void fft_inv(C2<T>* buf, int L, const Lines a, const C2<T>* __restrict__ tw, int tid,
                                         int nth)
 {
-    fft_inv<T, LMAX>(buf, buf, L, a, tw, tid, nth);
+    fft_inv<T, LMAX>(buf, a, buf, a, L, tw, tid, nth);
 }
 
 }  // namespace lgf

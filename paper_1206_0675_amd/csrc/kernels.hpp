@@ -350,6 +350,185 @@ __device__ __forceinline__ void measure_plane(const Geo& geo, int q, const C2<T>
 }
 
 // ---------------------------------------------------------------------------
+// Delta of one (z, t) plane with every in-plane link formed once.
+//
+// A link U'_mu(x) enters Delta at two sites: with a minus sign at x and with
+// a plus sign at x + mu.  Threads are laid out so that the x neighbours of a
+// site sit in neighbouring lanes of one wavefront (thread = column x of a
+// strip of J consecutive rows), so:
+//   - the x link a thread forms is handed to the lane of x + 1 by a
+//     cross-lane permute (no second formation, no LDS);
+//   - the y link of row j is carried in registers to row j + 1 of the same
+//     thread; only the first row of each strip forms its backward y link;
+//   - the z and t links of the neighbouring planes belong to other blocks and
+//     are formed again here.
+// That is 4 + 2 + 1/J formations per site instead of 8.  Requires Lx <= 64
+// (a row within one wavefront) and blockDim a multiple of Lx.
+// For each site of the plane, emit(p, Delta(x)) is called by the thread that
+// owns it; fsum and tsum receive the thread's F and theta terms.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void alg_of(const M3<T>& u, Alg8<T>& a)
+{
+#pragma clang fp contract(off)
+    const T third = T(2) / T(3);
+    a.c[0] = u.e[1] - conjg(u.e[3]);
+    a.c[1] = u.e[2] - conjg(u.e[6]);
+    a.c[2] = u.e[5] - conjg(u.e[7]);
+    const T tr = third * (u.e[0].y + u.e[4].y + u.e[8].y);
+    a.c[3] = mk<T>(T(2) * u.e[0].y - tr, T(2) * u.e[4].y - tr);
+}
+
+template <typename T>
+__device__ __forceinline__ void alg_add(Alg8<T>& acc, const Alg8<T>& a)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc.c[k] = acc.c[k] + a.c[k];
+}
+
+template <typename T>
+__device__ __forceinline__ void alg_sub(Alg8<T>& acc, const Alg8<T>& a)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc.c[k] = acc.c[k] - a.c[k];
+}
+
+// a of the lane `src` of this wavefront (every lane of the wavefront calls it)
+template <typename T>
+__device__ __forceinline__ Alg8<T> alg_from_lane(const Alg8<T>& a, int src)
+{
+    Alg8<T> b;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b.c[k] = mk<T>(__shfl(a.c[k].x, src), __shfl(a.c[k].y, src));
+    return b;
+}
+
+// r = a U b^dag for the link U of direction base `Umu` at site su
+template <typename T, int NE>
+__device__ __forceinline__ void link_abdag(const M3<T>& a, const C2<T>* __restrict__ Umu, int64_t VS, int64_t su,
+                                           const M3<T>& b, M3<T>& r)
+{
+    M3<T> u;
+    load_mat<T, NE>(u, Umu, VS, su);
+    a_u_bdag<T, (NE == 6 ? 2 : 3)>(a, u, b, r);
+}
+
+template <typename T, int NE, typename Emit>
+__device__ __forceinline__ void plane_delta_once(const Geo& geo, int q, const C2<T>* __restrict__ Uref,
+                                                 const C2<T>* __restrict__ G, double& fsum, double& tsum, Emit emit)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int Lx = geo.L[0], Ly = geo.L[1], Lz = geo.L[2], Lt = geo.L[3], lx = geo.logL[0];
+    const int64_t VS = geo.VS;
+    int nc = nth >> lx;                     // strips of rows
+    if (nc > Ly) nc = Ly;
+    const int J = Ly / nc;                  // rows per strip
+    const int x = tid & (Lx - 1), cr = tid >> lx;
+    const bool own = cr < nc;               // spare threads (plane smaller than the block) shadow a strip
+    const int cs = own ? cr : (cr & (nc - 1));
+    const int src = ((tid & ~(Lx - 1)) | ((x - 1) & (Lx - 1))) & 63;   // lane holding x - 1
+    const int z = q & (Lz - 1), t = q >> geo.logL[2];
+    const int NP = geo.NP;
+    const int64_t q0 = (int64_t)q * NP;
+    const int64_t dzp = (int64_t)(t * Lz + ((z + 1) & (Lz - 1))) * NP - q0;
+    const int64_t dzm = (int64_t)(t * Lz + ((z - 1) & (Lz - 1))) * NP - q0;
+    const int64_t dtp = (int64_t)(((t + 1) & (Lt - 1)) * Lz + z) * NP - q0;
+    const int64_t dtm = (int64_t)(((t - 1) & (Lt - 1)) * Lz + z) * NP - q0;
+    Alg8<T> ycarry;                         // U'_y of the row below, from the previous row
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ycarry.c[k] = mk<T>(T(0), T(0));
+#pragma unroll 1
+    for (int j = 0; j < J; ++j) {
+        const int y = cs * J + j;
+        const int p = (y << lx) + x;
+        const int64_t s = q0 + p;
+        const int64_t dxp = (int64_t)((x + 1) & (Lx - 1)) - x;
+        const int64_t dyp = (int64_t)((((y + 1) & (Ly - 1)) - y) << lx);
+        const int64_t dym = (int64_t)((((y - 1) & (Ly - 1)) - y) << lx);
+        Alg8<T> acc;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc.c[k] = mk<T>(T(0), T(0));
+        M3<T> gx;
+        load_mat<T, kGE>(gx, G, VS, s);
+        double f = 0.0;
+        // forward links U'_mu(x) = G(x) U0_mu(x) G^dag(x + mu)
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            M3<T> gn, r;
+            load_mat<T, kGE>(gn, G, VS, s + (mu == 0 ? dxp : mu == 1 ? dyp : mu == 2 ? dzp : dtp));
+            link_abdag<T, NE>(gx, Uref + (int64_t)mu * NE * VS, VS, s, gn, r);
+            f += re_trace(r);
+            Alg8<T> a;
+            alg_of(r, a);
+            alg_sub(acc, a);
+            if (mu == 0) {
+                alg_add(acc, alg_from_lane(a, src));    // U'_x(x - x) from the lane of x - 1
+            } else if (mu == 1) {
+                if (j > 0) alg_add(acc, ycarry);        // U'_y(x - y) from the row below
+                ycarry = a;
+            }
+        }
+        // backward links U'_nu(x - nu) = G(x - nu) U0_nu(x - nu) G^dag(x): z and t
+        // always, y only in the first row of the strip
+#pragma unroll 1
+        for (int nu = (j == 0 ? 1 : 2); nu < 4; ++nu) {
+            const int64_t sb = s + (nu == 1 ? dym : nu == 2 ? dzm : dtm);
+            M3<T> gb, r;
+            load_mat<T, kGE>(gb, G, VS, sb);
+            link_abdag<T, NE>(gb, Uref + (int64_t)nu * NE * VS, VS, sb, gx, r);
+            Alg8<T> b;
+            alg_of(r, b);
+            alg_add(acc, b);
+        }
+        if (own) {
+            fsum += f;
+            tsum += alg_norm2(acc);
+            emit(p, acc);
+        }
+    }
+}
+
+// F and theta partials of plane q, then the forward (x, y) FFT of the four
+// fields in buf (LDS, plane_lds_index layout) and the write of D.
+template <typename T, int LMAX>
+__device__ __forceinline__ void plane_finish(const Geo& geo, int q, double fsum, double tsum, C2<T>* __restrict__ D,
+                                             double* __restrict__ partial, const C2<T>* __restrict__ twx,
+                                             const C2<T>* __restrict__ twy, double* red, C2<T>* buf)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    double fb, tb;
+    block_sum2(fsum, tsum, red, tid, nth, &fb, &tb);
+    if (tid == 0) {
+        partial[2 * q] = fb;
+        partial[2 * q + 1] = tb;
+    }
+    fft_fwd<T, LMAX>(buf, geo.L[0], Lines{geo.logL[1], 2, geo.RP, geo.NPP, 1}, twx, tid, nth);
+    fft_fwd<T, LMAX>(buf, geo.L[1], Lines{geo.logL[0], 2, 1, geo.NPP, geo.RP}, twy, tid, nth);
+    const int W = geo.W, NP = geo.NP;
+    for (int i = tid; i < 4 * NP; i += nth) {
+        const int c = i >> geo.logNP, p = i & (NP - 1);
+        D[(int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1))] =
+            buf[plane_lds_index(geo, c, p)];
+    }
+}
+
+// The whole of a1 + a2 + a3(x, y) for plane q with links formed once where
+// the shape allows it.
+template <typename T, int NE, int LMAX>
+__device__ __forceinline__ void measure_plane_once(const Geo& geo, int q, const C2<T>* __restrict__ Uref,
+                                                   const C2<T>* __restrict__ G, C2<T>* __restrict__ D,
+                                                   double* __restrict__ partial, const C2<T>* __restrict__ twx,
+                                                   const C2<T>* __restrict__ twy, double* red, C2<T>* buf)
+{
+    double fsum = 0.0, tsum = 0.0;
+    plane_delta_once<T, NE>(geo, q, Uref, G, fsum, tsum, [&](int p, const Alg8<T>& acc) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) buf[plane_lds_index(geo, c, p)] = acc.c[c];
+    });
+    plane_finish<T, LMAX>(geo, q, fsum, tsum, D, partial, twx, twy, red, buf);
+}
+
+// ---------------------------------------------------------------------------
 // a3(z, t) + a4 + a5(z, t) for one (tile j of W plane positions, field c)
 // ---------------------------------------------------------------------------
 // ptab: four tables 4 sin^2(pi n / L_mu), indexed by position along the axis
@@ -380,7 +559,7 @@ __device__ __forceinline__ SpectralScale make_scale(const Geo& geo, const double
 // DFT of each contiguous group in registers, between the two A passes.
 template <typename T, int LT>
 __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth,
-                          const SpectralScale& sc, const Geo& geo, int j)
+                          const SpectralScale& sc, const Geo& geo, int logWb, int pxy0)
 {
     constexpr int R1 = fft_r1(LT), R2 = fft_r2(LT);
     constexpr int G = R2 > 1 ? R2 : R1;            // values per register group
@@ -390,8 +569,8 @@ __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ t
     for (int t = tid; t < ntask; t += nth) {
         const int lo = t & ((1 << a.lo_log) - 1);          // (z, w) line
         const int j1 = R2 > 1 ? (t >> a.lo_log) : 0;
-        const int w = lo & (geo.W - 1), zp = lo >> geo.logW;
-        const int pxy = j * geo.W + w;
+        const int w = lo & ((1 << logWb) - 1), zp = lo >> logWb;
+        const int pxy = pxy0 + w;
         const double base = sc.tx[pxy & (geo.L[0] - 1)] + sc.ty[pxy >> geo.logL[0]] + sc.tz[zp];
         C2<T>* p = buf + lo + j1 * R2 * es;
         C2<T> u[G];
@@ -408,29 +587,42 @@ __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ t
     if (R2 > 1) fft_pass_a<T, R1, R2, true>(buf, a, tw, tid, nth);
 }
 
+// One block's share of a (z, t) tile: the W plane positions of tile j are
+// split into parts of Wb = 2^logWb positions, and part h of field c is
+// transformed here (Wb = W: the whole tile).  The tile in global memory has
+// rows of W positions per (z, t) point; the LDS block has rows of Wb.  The
+// first z pass reads its lines straight from global memory and the last one
+// writes them back there.
+template <typename T, int LMAX>
+__device__ void zt_block(const Geo& geo, int j, int c, int h, int logWb, C2<T>* __restrict__ D,
+                         const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt, const SpectralScale& sc,
+                         C2<T>* buf)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int W = geo.W, Wb = 1 << logWb;
+    C2<T>* src = D + (int64_t)(j * 4 + c) * geo.DS + h * Wb;
+    const int Lz = geo.L[2];
+    const Lines zg{logWb, geo.logL[3], 1, Lz * W, W};
+    const Lines zl{logWb, geo.logL[3], 1, Lz * Wb, Wb};
+    const Lines tl{geo.logL[2] + logWb, 0, 1, 0, Lz * Wb};
+    const int pxy0 = j * W + h * Wb;
+    fft_fwd<T, LMAX>(src, zg, buf, Lz, zl, twz, tid, nth);
+    switch (geo.L[3]) {
+    case 4: zt_t_axis<T, 4>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
+    case 8: zt_t_axis<T, 8>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
+    case 16: zt_t_axis<T, 16>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
+    case 32: zt_t_axis<T, 32>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
+    case 64: zt_t_axis<T, 64>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
+    default: if constexpr (LMAX >= 128) zt_t_axis<T, 128>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
+    }
+    fft_inv<T, LMAX>(buf, zl, src, zg, Lz, twz, tid, nth);
+}
+
 template <typename T, int LMAX>
 __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
                          const C2<T>* __restrict__ twt, const SpectralScale& sc, C2<T>* buf)
 {
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int W = geo.W;
-    C2<T>* src = D + (int64_t)(j * 4 + c) * geo.DS;
-    const int Lz = geo.L[2];
-    const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
-    const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
-    // The tile in global memory has the layout of buf (index q W + w), so the
-    // first z pass reads its lines from global memory and the last one writes
-    // them back there.
-    fft_fwd<T, LMAX>(src, buf, Lz, zl, twz, tid, nth);
-    switch (geo.L[3]) {
-    case 4: zt_t_axis<T, 4>(buf, tl, twt, tid, nth, sc, geo, j); break;
-    case 8: zt_t_axis<T, 8>(buf, tl, twt, tid, nth, sc, geo, j); break;
-    case 16: zt_t_axis<T, 16>(buf, tl, twt, tid, nth, sc, geo, j); break;
-    case 32: zt_t_axis<T, 32>(buf, tl, twt, tid, nth, sc, geo, j); break;
-    case 64: zt_t_axis<T, 64>(buf, tl, twt, tid, nth, sc, geo, j); break;
-    default: if constexpr (LMAX >= 128) zt_t_axis<T, 128>(buf, tl, twt, tid, nth, sc, geo, j); break;
-    }
-    fft_inv<T, LMAX>(buf, src, Lz, zl, twz, tid, nth);
+    zt_block<T, LMAX>(geo, j, c, 0, geo.logW, D, twz, twt, sc, buf);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,6 +694,97 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
         M3<T> Gt;
         load_mat<T, kGE>(Gt, Gin, VS, q0 + p);
         update(p, Gt);
+    }
+}
+
+// The same update with the inverse (x, y) FFT done two fields at a time in a
+// plane buffer of 2 fields (half the LDS of gauge_plane, so more blocks fit
+// on a CU).  Each thread keeps the transformed fields 0 and 1 of its sites
+// (at most MAXS sites: NP <= MAXS * blockDim) in registers while fields 2
+// and 3 go through the buffer; G of its first PF sites is loaded into
+// registers before the second transform.
+template <typename T, int NE, int LMAX, int MAXS, int PF>
+__device__ void gauge_plane_2f(const Geo& geo, int q, const C2<T>* __restrict__ D, const C2<T>* __restrict__ Gin,
+                               C2<T>* __restrict__ Gout, const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
+                               C2<T>* buf)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int NP = geo.NP, W = geo.W;
+    const int64_t VS = geo.VS;
+    const int64_t q0 = (int64_t)q * NP;
+    const Lines ly{geo.logL[0], 1, 1, geo.NPP, geo.RP};
+    const Lines lx{geo.logL[1], 1, geo.RP, geo.NPP, 1};
+    C2<T> keep[MAXS][2];
+    C2<T> gpre[PF > 0 ? PF : 1][kGE];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        gather_to_lds<8>(
+            buf, D, 2 * NP, tid, nth,
+            [&](int i) {
+                const int c = 2 * half + (i >> geo.logNP), p = i & (NP - 1);
+                return (int64_t)((p >> geo.logW) * 4 + c) * geo.DS + (int64_t)q * W + (p & (W - 1));
+            },
+            [&](int i) { return plane_lds_index(geo, i >> geo.logNP, i & (NP - 1)); });
+        if (half == 1) {
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                const int p = tid + k * nth;
+                if (p < NP) {
+#pragma unroll
+                    for (int e = 0; e < kGE; ++e) gpre[k][e] = Gin[e * VS + q0 + p];
+                }
+            }
+        }
+        __syncthreads();
+        fft_inv<T, LMAX>(buf, geo.L[1], ly, twy, tid, nth);
+        fft_inv<T, LMAX>(buf, geo.L[0], lx, twx, tid, nth);
+        if (half == 0) {
+#pragma unroll
+            for (int k = 0; k < MAXS; ++k) {
+                const int p = tid + k * nth;
+                if (p < NP) {
+                    keep[k][0] = buf[plane_lds_index(geo, 0, p)];
+                    keep[k][1] = buf[plane_lds_index(geo, 1, p)];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    auto update = [&](int p, const C2<T>* v01, const M3<T>& Gt) {
+        C2<double> c[4];
+        c[0] = mk<double>((double)v01[0].x, (double)v01[0].y);
+        c[1] = mk<double>((double)v01[1].x, (double)v01[1].y);
+#pragma unroll
+        for (int k = 2; k < 4; ++k) {
+            const C2<T> v = buf[plane_lds_index(geo, k - 2, p)];
+            c[k] = mk<double>((double)v.x, (double)v.y);
+        }
+        M3<double> m;
+        one_plus_alg_reunit(c, m);
+        M3<double> Gd = cast_mat<double>(Gt), r;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                r.e[3 * i + k] =
+                    cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
+        reunit(r);
+        store_mat<T, kGE>(cast_mat<T>(r), Gout, VS, q0 + p);
+    };
+#pragma unroll
+    for (int k = 0; k < MAXS; ++k) {
+        const int p = tid + k * nth;
+        if (p < NP) {
+            M3<T> Gt;
+            if (k < PF) {
+#pragma unroll
+                for (int e = 0; e < kGE; ++e) Gt.e[e] = gpre[k < PF ? k : 0][e];
+                rebuild_row3(Gt);
+            } else {
+                load_mat<T, kGE>(Gt, Gin, VS, q0 + p);
+            }
+            update(p, keep[k], Gt);
+        }
     }
 }
 

@@ -47,6 +47,23 @@ inline std::vector<unsigned char> dyn_lds;
 
 inline void __syncthreads() { emu::bar->arrive_and_wait(); }
 
+// Cross-lane read within a wavefront of 64 threads (ds_bpermute on the GPU).
+// Every thread of the block must call it together, as every lane of a
+// wavefront does on the GPU where the library uses it.
+namespace emu {
+inline std::vector<double> shfl_slots;
+}
+inline double __shfl(double v, int src_lane, int width = 64)
+{
+    const unsigned t = emu::tidx.x + emu::bdim.x * (emu::tidx.y + emu::bdim.y * emu::tidx.z);
+    emu::shfl_slots[t] = v;
+    emu::bar->arrive_and_wait();
+    const double r = emu::shfl_slots[(t & ~63u) | (unsigned)(src_lane & (width - 1))];
+    emu::bar->arrive_and_wait();
+    return r;
+}
+inline float __shfl(float v, int src_lane, int width = 64) { return (float)__shfl((double)v, src_lane, width); }
+
 inline long long __double_as_longlong(double d)
 {
     long long r;
@@ -166,6 +183,7 @@ void launch(K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
     gdim = grid;
     bdim = block;
     dyn_lds.assign(lds ? lds : 1, 0xff);
+    shfl_slots.assign(nth + 64, 0.0);
     std::barrier<> b((std::ptrdiff_t)nth);
     bar = &b;
     std::vector<std::thread> th;
