@@ -205,6 +205,34 @@ int32_t lgf_fix_batch(const lgf_params *common, int32_t n, const int32_t (*dims)
                       double *const *links_out, lgf_stats *out);
 
 /* ---------------------------------------------------------------------------
+ * Allocation-free one call, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It is lgf_create + lgf_load_links + lgf_fix + lgf_store_links
+ * + lgf_destroy for one lattice whose links are in device memory, with the
+ * same kernels and launch shape as a default context (so the same result
+ * bits), but it calls no hipMalloc, hipFree or other allocating routine:
+ * every buffer beyond links_in and links_out lives in one static device
+ * array of lgf_noalloc_capacity() bytes (64 MiB: up to a 16^4 lattice with
+ * 18-real links), which each device the library runs on holds until the
+ * process ends.  Lattices that need more return LGF_E_UNSUPPORTED_SHAPE
+ * before any device work.
+ *   p          params as for lgf_create; precision must be LGF_FP64 and step
+ *              LGF_STEP_PLAIN (else LGF_E_INVALID_ARG); p->stream is the
+ *              stream used (NULL: the null stream); autotune, no_graph and
+ *              profile are ignored (kernel-by-kernel launches, default
+ *              launch shape).
+ *   links_in   canonical FP64 links on the current device (read only).
+ *   links_out  canonical FP64 links on the current device, written with the
+ *              gauge-fixed links; may equal links_in.
+ *   out        stats (or NULL), filled also for LGF_E_NOT_CONVERGED.
+ * The call returns when the result is in links_out.  Every call on a device
+ * shares that device's array: calls that overlap on one device race and are
+ * not supported.  Errors: as lgf_create, lgf_load_links and lgf_fix; the
+ * message is read with lgf_last_error(NULL). */
+int32_t lgf_fix_noalloc(const lgf_params *p, const double *links_in, double *links_out, lgf_stats *out);
+size_t lgf_noalloc_capacity(void);
+
+/* ---------------------------------------------------------------------------
  * Learned spectral step.  The modes p != 0 fall in 16 bands log-spaced in p^2
  * between the smallest nonzero p^2 of the lattice and p2max.  Features:
  * x_b = log10(P_b / V) / 8 with P_b the mean over band b of sum_c |Dhat_c|^2

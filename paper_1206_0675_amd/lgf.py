@@ -101,6 +101,8 @@ def load_library(path: str | None = None):
         "lgf_batch_config": ([V, C.POINTER(I32), C.POINTER(I32)], I32),
         "lgf_batch_last_error": ([V], C.c_char_p),
         "lgf_fix_batch": ([P, I32, C.POINTER(C.c_int32 * 4), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), S], I32),
+        "lgf_fix_noalloc": ([P, V, V, S], I32),
+        "lgf_noalloc_capacity": ([], C.c_size_t),
         "lgf_model_bytes": ([], C.c_size_t),
         "lgf_set_model": ([V, C.c_char_p, C.c_size_t], I32),
         "lgf_learned_factors": ([V, C.POINTER(C.c_double), C.POINTER(C.c_double)], I32),
@@ -365,6 +367,22 @@ def fix_batch(links_list, lib=None, **kw):
     st = (Stats * n)()
     rc = L.lgf_fix_batch(C.byref(p), n, arr, pin, pout, st)
     return outs, list(st), rc
+
+
+def fix_noalloc(links_in, links_out, lib=None, **kw):
+    """lgf_fix_noalloc: gauge-fix device-resident canonical links (torch
+    tensors on the GPU) with no device allocation by the library.  dims come
+    from the tensor shape (Lt, Lz, Ly, Lx, 4, 3, 3); returns (stats, status)."""
+    L = lib or load_library()
+    for t in (links_in, links_out):
+        if not (hasattr(t, "is_cuda") and t.is_cuda and t.is_contiguous()):
+            raise ValueError("lgf_fix_noalloc takes contiguous device tensors")
+    sh = tuple(links_in.shape)
+    p = default_params((sh[3], sh[2], sh[1], sh[0]), L, **kw)
+    st = Stats()
+    rc = L.lgf_fix_noalloc(C.byref(p), C.c_void_p(links_in.data_ptr()), C.c_void_p(links_out.data_ptr()),
+                           C.byref(st))
+    return st, rc
 
 
 def _f32(a, n=None):
