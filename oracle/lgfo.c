@@ -310,6 +310,7 @@ void lgfo_default_opts(lgfo_opts *o)
     o->accel = 1;
     o->store12 = 0;
     o->band_scale = NULL;
+    o->expo = 0;
 }
 
 int lgfo_filter(const lgfo_opts *o, const int *dims, const double *delta, double *out)
@@ -398,6 +399,67 @@ int lgfo_gauge(const int *dims, const double *dtilde, double alpha, double *g)
     return 0;
 }
 
+/* exp(X) of a 3x3 complex matrix: halve X until its Frobenius norm is at
+ * most 1/2, sum the Taylor series until a term is below 1e-18 of the sum (at
+ * most 40 terms), then square the result once per halving. */
+static mat expm3(const mat *x)
+{
+    double nrm = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) nrm += creal(x->e[i][j] * conj(x->e[i][j]));
+    nrm = sqrt(nrm);
+    int halvings = 0;
+    double scale = 1.0;
+    while (nrm * scale > 0.5) {
+        scale *= 0.5;
+        ++halvings;
+    }
+    mat a = *x, sum, term;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            a.e[i][j] *= scale;
+            sum.e[i][j] = term.e[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int n = 1; n <= 40; ++n) {
+        term = mul(&term, &a);
+        double tn = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                term.e[i][j] /= (double)n;
+                tn += creal(term.e[i][j] * conj(term.e[i][j]));
+            }
+        add_to(&sum, &term, 1.0);
+        if (sqrt(tn) < 1e-18) break;
+    }
+    for (int k = 0; k < halvings; ++k) sum = mul(&sum, &sum);
+    return sum;
+}
+
+int lgfo_expm(const double *m, long n, double *out)
+{
+    if (!m || !out || n < 0) return -1;
+    for (long k = 0; k < n; ++k) {
+        mat a = load(m + k * 18), e = expm3(&a);
+        store(out + k * 18, &e);
+    }
+    return 0;
+}
+
+int lgfo_gauge_exp(const int *dims, const double *dtilde, double alpha, double *g)
+{
+    if (!dims_ok(dims) || !dtilde || !g) return -1;
+    long V = vol(dims);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s) {
+        mat d = load(dtilde + s * 18);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) d.e[i][j] *= 0.5 * alpha;
+        mat e = expm3(&d);
+        store(g + s * 18, &e);
+    }
+    return 0;
+}
+
 int lgfo_transform(const int *dims, const double *U, const double *g, double *out)
 {
     if (!dims_ok(dims) || !U || !g || !out || U == out) return -1;
@@ -476,7 +538,8 @@ static void update(const lgfo_opts *o, const int *dims, double *U, double *G, wo
 {
     long V = vol(dims);
     lgfo_filter(o, dims, w->delta, w->dtilde);
-    lgfo_gauge(dims, w->dtilde, o->alpha, w->g);
+    if (o->expo) lgfo_gauge_exp(dims, w->dtilde, o->alpha, w->g);
+    else lgfo_gauge(dims, w->dtilde, o->alpha, w->g);
     lgfo_transform(dims, U, w->g, w->Unew);
     memcpy(U, w->Unew, sizeof(double) * 72 * V);
     if (o->store12) lgfo_rebuild_row3(U, 4 * V);

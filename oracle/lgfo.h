@@ -39,6 +39,10 @@ typedef struct {
                             rebuilt as (a x b)^* whenever read (Section 3.2)    */
     const double *band_scale; /* NULL, or 16 per-band factors s_b multiplying
                                  the acceleration kernel (learned step)         */
+    int    expo;         /* 0: g = reunit(1 + alpha/2 dtilde), first order in
+                            alpha then projected to SU(3) (Section 2);
+                            1: g = exp(alpha/2 dtilde) exactly (eq. gx as
+                            written, without the first-order expansion)        */
 } lgfo_opts;
 
 /* Fill opts with the paper's settings: alpha 0.08, theta_stop 1e-15, accel 1. */
@@ -61,6 +65,15 @@ int lgfo_filter(const lgfo_opts *o, const int *dims, const double *delta, double
 /* g(x) = reunit(1 + alpha/2 * dtilde(x)): eq. gx to first order in alpha,
  * then projected to SU(3) by row Gram-Schmidt with row 3 = (row1 x row2)^*. */
 int lgfo_gauge(const int *dims, const double *dtilde, double alpha, double *g);
+
+/* g(x) = exp(alpha/2 * dtilde(x)): eq. gx with the exponential evaluated
+ * exactly (Taylor series of the 3x3 matrix after scaling by a power of two,
+ * then repeated squaring). */
+int lgfo_gauge_exp(const int *dims, const double *dtilde, double alpha, double *g);
+
+/* exp(M) of n 3x3 complex matrices (18 doubles each), by the method of
+ * lgfo_gauge_exp. */
+int lgfo_expm(const double *m, long n, double *out);
 
 /* U_mu(x) -> g(x) U_mu(x) g^dagger(x + mu) for all x, mu (Section 2). */
 int lgfo_transform(const int *dims, const double *U, const double *g, double *out);

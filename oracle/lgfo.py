@@ -17,7 +17,8 @@ _LIB = None
 
 class Opts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("theta_stop", C.c_double), ("max_iter", C.c_long),
-                ("accel", C.c_int), ("store12", C.c_int), ("band_scale", C.POINTER(C.c_double))]
+                ("accel", C.c_int), ("store12", C.c_int), ("band_scale", C.POINTER(C.c_double)),
+                ("expo", C.c_int)]
 
 
 def lib():
@@ -34,6 +35,8 @@ def lib():
         L.lgfo_fft4d.argtypes = [I4, D, C.c_int]
         L.lgfo_filter.argtypes = [P, I4, D, D]
         L.lgfo_gauge.argtypes = [I4, D, C.c_double, D]
+        L.lgfo_gauge_exp.argtypes = [I4, D, C.c_double, D]
+        L.lgfo_expm.argtypes = [D, C.c_long, D]
         L.lgfo_transform.argtypes = [I4, D, D, D]
         L.lgfo_step.argtypes = [P, I4, D, C.c_long, D, D, D]
         L.lgfo_fix.argtypes = [P, I4, D, C.POINTER(C.c_long), D, D, D]
@@ -65,11 +68,11 @@ def _field_shape(dims):
 
 
 def opts(alpha=0.08, theta_stop=1e-15, max_iter=100000, accel=True, store12=False,
-         band_scale=None):
+         band_scale=None, expo=False):
     o = Opts()
     lib().lgfo_default_opts(C.byref(o))
     o.alpha, o.theta_stop, o.max_iter = alpha, theta_stop, max_iter
-    o.accel, o.store12 = int(bool(accel)), int(bool(store12))
+    o.accel, o.store12, o.expo = int(bool(accel)), int(bool(store12)), int(bool(expo))
     if band_scale is not None:
         arr = np.ascontiguousarray(band_scale, dtype=np.float64)
         assert arr.shape == (16,)
@@ -107,11 +110,20 @@ def filter_delta(dims, delta, o=None):
     return out
 
 
-def gauge(dims, dtilde, alpha=0.08):
+def gauge(dims, dtilde, alpha=0.08, expo=False):
     dtilde = np.ascontiguousarray(dtilde, dtype=np.complex128)
     g = np.empty_like(dtilde)
-    _check(lib().lgfo_gauge(_dims(dims), _dp(dtilde), float(alpha), _dp(g)), "gauge")
+    fn = lib().lgfo_gauge_exp if expo else lib().lgfo_gauge
+    _check(fn(_dims(dims), _dp(dtilde), float(alpha), _dp(g)), "gauge")
     return g
+
+
+def expm(m):
+    """exp of each 3x3 complex matrix in m (..., 3, 3), by the oracle's series."""
+    m = np.ascontiguousarray(m, dtype=np.complex128)
+    out = np.empty_like(m)
+    _check(lib().lgfo_expm(_dp(m), m.size // 9, _dp(out)), "expm")
+    return out
 
 
 def transform(dims, U, g):

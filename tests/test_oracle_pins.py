@@ -499,3 +499,59 @@ def test_unitarity_reports_nonfinite(oracle_lib):
         p[k, 1, 1] = complex(np.nan, 0.0)
         mu, md = oracle.unitarity(p)
         assert np.isnan(mu) and np.isnan(md)
+
+
+def _rand_su3_algebra(rng, n, scale):
+    """n random anti-Hermitian traceless 3x3 matrices with Frobenius norm ~ scale."""
+    a = rng.normal(size=(n, 3, 3)) + 1j * rng.normal(size=(n, 3, 3))
+    x = a - dag(a)
+    x -= np.trace(x, axis1=1, axis2=2)[:, None, None] * np.eye(3) / 3.0
+    return x * (scale / np.linalg.norm(x, axis=(1, 2)))[:, None, None]
+
+
+def test_expm_matches_scipy_and_eigendecomposition(oracle_lib):
+    """The oracle's matrix exponential (eq. gx evaluated exactly) against
+    scipy.linalg.expm on general complex matrices and against the spectral
+    formula V diag(exp(i l)) V^dag for anti-Hermitian X = i V diag(l) V^dag."""
+    rng = np.random.default_rng(31)
+    general = (rng.normal(size=(40, 3, 3)) + 1j * rng.normal(size=(40, 3, 3))) * \
+        np.logspace(-9, 0.7, 40)[:, None, None]
+    ours = oracle.expm(general)
+    for m, e in zip(general, ours):
+        ref = scipy.linalg.expm(m)
+        assert np.max(np.abs(e - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+    for scale in (1e-9, 1e-3, 0.3, 2.0, 6.0):
+        x = _rand_su3_algebra(rng, 20, scale)
+        e = oracle.expm(x)
+        lam, v = np.linalg.eigh(-1j * x)
+        ref = (v * np.exp(1j * lam)[:, None, :]) @ dag(v)
+        assert np.max(np.abs(e - ref)) <= 2e-14 * max(1.0, scale)
+        mu, md = oracle.unitarity(e)
+        assert mu <= 1e-13 and md <= 1e-13
+    d = np.diag([0.3j, -1.1j, 0.8j])
+    assert np.max(np.abs(oracle.expm(d[None])[0] - np.diag(np.exp(np.diag(d))))) <= 1e-15
+
+
+def test_exact_exponential_update(oracle_lib):
+    """The update with g = exp(alpha/2 dtilde): g equals expm of the filtered
+    field, the plaquette is unchanged, F rises, the linear-regime contraction
+    (1 - alpha p2max)^2 is the same as the first-order update's, and a
+    generator field converges."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 17)
+    o = oracle.opts(expo=True)
+    _, _, delta = oracle.measure(dims, U)
+    dt = oracle.filter_delta(dims, delta, o)
+    g = oracle.gauge(dims, dt, ALPHA, expo=True)
+    ref = np.array([scipy.linalg.expm(0.5 * ALPHA * m) for m in dt.reshape(-1, 3, 3)]).reshape(g.shape)
+    assert np.max(np.abs(g - ref)) <= 1e-13
+    mu, md = oracle.unitarity(g)
+    assert mu <= 1e-13 and md <= 1e-13
+    U1, tf, _, _ = oracle.step(dims, U, 6, o)
+    assert abs(oracle.plaquette(dims, U1) - oracle.plaquette(dims, U)) <= 1e-12
+    assert np.all(np.diff(tf) >= -1e-14)
+    Us = synth.small_field(dims, 5, eps=1e-5)
+    _, _, th, _ = oracle.step(dims, Us, 1, o)
+    assert abs(th[1] / th[0] / (1 - ALPHA * 16) ** 2 - 1) <= 1e-4
+    _, it, _, th_end, conv, _ = oracle.fix(dims, U, o)
+    assert conv and th_end < 1e-15 and it < 200
