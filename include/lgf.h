@@ -78,6 +78,12 @@ extern "C" {
                                network set by lgf_set_model; an update that does not
                                increase F is replaced by the plain one (FP64 only)          */
 
+/* how g(x) is formed from the filtered Delta (eq. gx) */
+#define LGF_UPDATE_FIRST_ORDER 0  /* g = reunit(1 + (alpha/2) dtilde): first order in alpha, then
+                                     projected to SU(3) (Section 2; the paper's choice)          */
+#define LGF_UPDATE_EXP 1          /* g = exp((alpha/2) dtilde), the exponential of eq. gx taken
+                                     exactly (Cayley-Hamilton form, FP64)                        */
+
 /* acceleration kernel */
 #define LGF_ACCEL_FOURIER 1  /* K(p) = p2max/p2, K(0) = 0 (eq. gx)                       */
 #define LGF_ACCEL_NONE 0     /* K(p) = 1: plain steepest descent (the same update without
@@ -89,8 +95,7 @@ typedef struct lgf_params {
     int32_t storage;        /* LGF_STORE18 | LGF_STORE12                                 */
     int32_t step;           /* LGF_STEP_PLAIN                                            */
     int32_t accel;          /* LGF_ACCEL_FOURIER | LGF_ACCEL_NONE                        */
-    int32_t track_gauge;    /* ignored: the accumulated G = ... g2 g1 (U = G U0 G^dag(x+mu))
-                               is always kept; the iteration is carried in it          */
+    int32_t update;         /* LGF_UPDATE_FIRST_ORDER | LGF_UPDATE_EXP                   */
     int32_t profile;        /* 1: time every kernel launch with HIP events               */
     double alpha;           /* step size, paper: 0.08                                    */
     double theta_stop;      /* stop when theta < theta_stop, paper: 1e-15                */

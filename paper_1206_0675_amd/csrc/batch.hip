@@ -134,12 +134,13 @@ template <typename T, int NE, int LMAX>
 int32_t set_batch_lds(lgf_batch* b)
 {
     const int P = prec_index<T>();
-    HIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_measure<T, NE, false, LMAX>),
+    HIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_measure<T, NE, false, LMAX, LMAX == 64>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_m[P]));
-    HIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_measure<T, NE, true, LMAX>),
+    HIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_measure<T, NE, true, LMAX, LMAX == 64>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_m[P]));
-    HIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_gauge<T, NE, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_g[P]));
+    for (const void* f : {reinterpret_cast<const void*>(&kb_gauge<T, NE, LMAX, false>),
+                          reinterpret_cast<const void*>(&kb_gauge<T, NE, LMAX, true>)})
+        HIPCHK(b, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_g[P]));
     HIPCHK(b, hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_zt<T, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_z[P]));
     return LGF_OK;
@@ -174,6 +175,8 @@ int32_t configure(lgf_batch* b, int nth, int tile_bytes)
 
 int grid_for(lgf_batch* b, int items, int per_cu) { return std::max(1, std::min(items, b->ncu * per_cu)); }
 
+// Every extent of the batch is at most 64 when LMAX = 64, so every member's
+// x rows fit a wavefront and the plane kernels form each in-plane link once.
 template <typename T, int NE, int LMAX>
 int32_t phase_sequence(lgf_batch* b)
 {
@@ -182,13 +185,17 @@ int32_t phase_sequence(lgf_batch* b)
     const uint32_t* zt = P ? b->items_zt64 : b->items_zt32;
     const int nzt = P ? b->n_zt64 : b->n_zt32;
     const dim3 gp(grid_for(b, b->n_plane, 4)), bp(b->nth_plane), gz(grid_for(b, nzt, 2)), gr(b->n);
-    TRY(launch(b, K_MEASURE, kb_measure<T, NE, false, LMAX>, gp, bp, b->lds_m[P], cf, (const uint32_t*)b->items_plane,
+    TRY(launch(b, K_MEASURE, kb_measure<T, NE, false, LMAX, LMAX == 64>, gp, bp, b->lds_m[P], cf, (const uint32_t*)b->items_plane,
                b->n_plane, P));
     TRY(launch(b, K_REDUCE, kb_reduce<T>, gr, dim3(256), 0, cf, P, 0));
     TRY(launch(b, K_ZT, kb_zt<T, LMAX>, gz, dim3(kZtThreads), b->lds_z[P], cf, zt, nzt, P));
-    TRY(launch(b, K_GAUGE, kb_gauge<T, NE, LMAX>, gp, bp, b->lds_g[P], cf, (const uint32_t*)b->items_plane,
-               b->n_plane, P));
-    TRY(launch(b, K_TRANSFORM_MEASURE, kb_measure<T, NE, true, LMAX>, gp, bp, b->lds_m[P], cf,
+    if (b->p.update == LGF_UPDATE_EXP)
+        TRY(launch(b, K_GAUGE, kb_gauge<T, NE, LMAX, true>, gp, bp, b->lds_g[P], cf, (const uint32_t*)b->items_plane,
+                   b->n_plane, P));
+    else
+        TRY(launch(b, K_GAUGE, kb_gauge<T, NE, LMAX, false>, gp, bp, b->lds_g[P], cf, (const uint32_t*)b->items_plane,
+                   b->n_plane, P));
+    TRY(launch(b, K_TRANSFORM_MEASURE, kb_measure<T, NE, true, LMAX, LMAX == 64>, gp, bp, b->lds_m[P], cf,
                (const uint32_t*)b->items_plane, b->n_plane, P));
     TRY(launch(b, K_REDUCE, kb_reduce<T>, gr, dim3(256), 0, cf, P, 1));
     return LGF_OK;
@@ -435,6 +442,8 @@ int32_t lgf_batch_create(const lgf_params* p, int32_t n, const int32_t (*dims)[4
     if (p->step != LGF_STEP_PLAIN) return fail(nullptr, LGF_E_INVALID_ARG, "unknown step kind");
     if (p->accel != LGF_ACCEL_FOURIER && p->accel != LGF_ACCEL_NONE)
         return fail(nullptr, LGF_E_INVALID_ARG, "accel must be LGF_ACCEL_FOURIER or LGF_ACCEL_NONE");
+    if (p->update != LGF_UPDATE_FIRST_ORDER && p->update != LGF_UPDATE_EXP)
+        return fail(nullptr, LGF_E_INVALID_ARG, "update must be LGF_UPDATE_FIRST_ORDER or LGF_UPDATE_EXP");
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(nullptr, LGF_E_INVALID_ARG, "alpha must be > 0");
     if (!(p->theta_stop >= 0.0) || !(p->theta_switch >= 0.0) || p->max_iter < 0 || p->poll_every < 1)
         return fail(nullptr, LGF_E_INVALID_ARG, "bad theta_stop/theta_switch/max_iter/poll_every");

@@ -445,11 +445,21 @@ __device__ __forceinline__ void plane_delta_once(const Geo& geo, int q, const C2
         const int64_t dxp = (int64_t)((x + 1) & (Lx - 1)) - x;
         const int64_t dyp = (int64_t)((((y + 1) & (Ly - 1)) - y) << lx);
         const int64_t dym = (int64_t)((((y - 1) & (Ly - 1)) - y) << lx);
-        Alg8<T> acc;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc.c[k] = mk<T>(T(0), T(0));
         M3<T> gx;
         load_mat<T, kGE>(gx, G, VS, s);
+        // U'_y(x - y): carried from the row below, or formed in the strip's
+        // first row.  It enters the sum first either way, so the result does
+        // not depend on where the strips start (on the block size).
+        Alg8<T> acc;
+        if (j == 0) {
+            const int64_t sb = s + dym;
+            M3<T> gb, r;
+            load_mat<T, kGE>(gb, G, VS, sb);
+            link_abdag<T, NE>(gb, Uref + (int64_t)NE * VS, VS, sb, gx, r);
+            alg_of(r, acc);
+        } else {
+            acc = ycarry;
+        }
         double f = 0.0;
         // forward links U'_mu(x) = G(x) U0_mu(x) G^dag(x + mu)
 #pragma unroll 1
@@ -461,18 +471,13 @@ __device__ __forceinline__ void plane_delta_once(const Geo& geo, int q, const C2
             Alg8<T> a;
             alg_of(r, a);
             alg_sub(acc, a);
-            if (mu == 0) {
-                alg_add(acc, alg_from_lane(a, src));    // U'_x(x - x) from the lane of x - 1
-            } else if (mu == 1) {
-                if (j > 0) alg_add(acc, ycarry);        // U'_y(x - y) from the row below
-                ycarry = a;
-            }
+            if (mu == 0) alg_add(acc, alg_from_lane(a, src));    // U'_x(x - x) from the lane of x - 1
+            else if (mu == 1) ycarry = a;                         // U'_y(x) for the row above
         }
-        // backward links U'_nu(x - nu) = G(x - nu) U0_nu(x - nu) G^dag(x): z and t
-        // always, y only in the first row of the strip
+        // backward links U'_nu(x - nu) = G(x - nu) U0_nu(x - nu) G^dag(x) of the z and t neighbours
 #pragma unroll 1
-        for (int nu = (j == 0 ? 1 : 2); nu < 4; ++nu) {
-            const int64_t sb = s + (nu == 1 ? dym : nu == 2 ? dzm : dtm);
+        for (int nu = 2; nu < 4; ++nu) {
+            const int64_t sb = s + (nu == 2 ? dzm : dtm);
             M3<T> gb, r;
             load_mat<T, kGE>(gb, G, VS, sb);
             link_abdag<T, NE>(gb, Uref + (int64_t)nu * NE * VS, VS, sb, gx, r);
@@ -629,7 +634,26 @@ __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, co
 // a5(x, y) + a6 + a8 for one plane q: inverse (x, y) FFT,
 // g = reunit(1 + dtilde) and Gout = reunit(g Gin), both in FP64.
 // ---------------------------------------------------------------------------
-template <typename T, int NE, int LMAX>
+// g from the packed filtered Delta (alpha/2 folded in): reunit(1 + dtilde),
+// or exp(dtilde) when expo; then Gout(site) = reunit(g Gt), all in FP64.
+template <typename T, bool EXPO>
+__device__ __forceinline__ void gauge_site(const C2<double> c[4], const M3<T>& Gt, C2<T>* __restrict__ Gout,
+                                           int64_t VS, int64_t site)
+{
+    M3<double> m;
+    if constexpr (EXPO) alg_exp(c, m);
+    else one_plus_alg_reunit(c, m);
+    M3<double> Gd = cast_mat<double>(Gt), r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            r.e[3 * i + k] = cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
+    reunit(r);
+    store_mat<T, kGE>(cast_mat<T>(r), Gout, VS, site);
+}
+
+template <typename T, int NE, int LMAX, bool EXPO = false>
 __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, const C2<T>* __restrict__ Gin,
                             C2<T>* __restrict__ Gout, const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
                             C2<T>* buf)
@@ -667,17 +691,7 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
             const C2<T> v = buf[plane_lds_index(geo, k, p)];
             c[k] = mk<double>((double)v.x, (double)v.y);
         }
-        M3<double> m;
-        one_plus_alg_reunit(c, m);
-        M3<double> Gd = cast_mat<double>(Gt), r;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                r.e[3 * i + k] =
-                    cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
-        reunit(r);
-        store_mat<T, kGE>(cast_mat<T>(r), Gout, VS, q0 + p);
+        gauge_site<T, EXPO>(c, Gt, Gout, VS, q0 + p);
     };
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
@@ -703,7 +717,7 @@ __device__ void gauge_plane(const Geo& geo, int q, const C2<T>* __restrict__ D, 
 // (at most MAXS sites: NP <= MAXS * blockDim) in registers while fields 2
 // and 3 go through the buffer; G of its first PF sites is loaded into
 // registers before the second transform.
-template <typename T, int NE, int LMAX, int MAXS, int PF>
+template <typename T, int NE, int LMAX, int MAXS, int PF, bool EXPO = false>
 __device__ void gauge_plane_2f(const Geo& geo, int q, const C2<T>* __restrict__ D, const C2<T>* __restrict__ Gin,
                                C2<T>* __restrict__ Gout, const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
                                C2<T>* buf)
@@ -759,17 +773,7 @@ __device__ void gauge_plane_2f(const Geo& geo, int q, const C2<T>* __restrict__ 
             const C2<T> v = buf[plane_lds_index(geo, k - 2, p)];
             c[k] = mk<double>((double)v.x, (double)v.y);
         }
-        M3<double> m;
-        one_plus_alg_reunit(c, m);
-        M3<double> Gd = cast_mat<double>(Gt), r;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                r.e[3 * i + k] =
-                    cfma(m.e[3 * i + 2], Gd.e[6 + k], cfma(m.e[3 * i + 1], Gd.e[3 + k], cmul(m.e[3 * i], Gd.e[k])));
-        reunit(r);
-        store_mat<T, kGE>(cast_mat<T>(r), Gout, VS, q0 + p);
+        gauge_site<T, EXPO>(c, Gt, Gout, VS, q0 + p);
     };
 #pragma unroll
     for (int k = 0; k < MAXS; ++k) {
@@ -842,7 +846,9 @@ __device__ __forceinline__ void reduce_state(const double* __restrict__ partial,
 // reference links Uref (those loaded) and the accumulated gauge G, kept in a
 // pair of buffers.  next = 0 measures the current G (G[cur]); next = 1 the
 // one k_gauge has just formed (G[1 - cur]).
-template <typename T, int NE, int LMAX>
+// ONCE: the link-once plane function (x extent <= 64), else the one that
+// forms every link at both of its sites.
+template <typename T, int NE, int LMAX, bool ONCE>
 __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restrict__ Uref, const C2<T>* G0,
                                                  const C2<T>* G1, int next, C2<T>* __restrict__ D,
                                                  double* __restrict__ partial, const C2<T>* __restrict__ twx,
@@ -851,23 +857,49 @@ __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restric
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     const C2<T>* G = (st->cur ^ next) ? G1 : G0;
-    measure_plane<T, NE, LMAX>(geo, plane_of_block(blockIdx.x, geo), Uref, G, D, partial, twx, twy, lds_raw,
-                               reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
+    const int q = plane_of_block(blockIdx.x, geo);
+    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x);
+    if constexpr (ONCE) measure_plane_once<T, NE, LMAX>(geo, q, Uref, G, D, partial, twx, twy, lds_raw, buf);
+    else measure_plane<T, NE, LMAX>(geo, q, Uref, G, D, partial, twx, twy, lds_raw, buf);
 }
 
+// Part h and (tile, field) chunk of block b of a (z, t) launch with
+// 2^lnh parts per chunk (blocks = chunks << lnh).  When the chunks are a
+// multiple of 8, the parts of one chunk go to blocks of one XCD (blocks are
+// dealt to the 8 XCDs round robin), so each cache line of the chunk is read
+// into one L2; otherwise the parts of a chunk are consecutive blocks.
+__host__ __device__ __forceinline__ void zt_part_of_block(int b, int nchunk, int lnh, int& h, int& chunk)
+{
+    if (lnh == 0) {
+        h = 0;
+        chunk = b;
+    } else if ((nchunk & 7) == 0) {
+        const int xcd = b & 7, l = b >> 3;
+        h = l & ((1 << lnh) - 1);
+        chunk = ((l >> lnh) << 3) | xcd;
+    } else {
+        h = b & ((1 << lnh) - 1);
+        chunk = b >> lnh;
+    }
+}
+
+// One block per (tile, field, part of 2^logWb plane positions).
 template <typename T, int LMAX>
 __global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
                                             const C2<T>* __restrict__ twt, const double* __restrict__ ptab,
-                                            double c0, int accel, const DevState* __restrict__ st)
+                                            double c0, int accel, int logWb, const DevState* __restrict__ st)
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
-    zt_block<T, LMAX>(geo, blockIdx.x >> 2, blockIdx.x & 3, D, twz, twt, make_scale(geo, ptab, c0, accel),
+    int h, chunk;
+    zt_part_of_block(blockIdx.x, (geo.NP >> geo.logW) * 4, geo.logW - logWb, h, chunk);
+    zt_block<T, LMAX>(geo, chunk >> 2, chunk & 3, h, logWb, D, twz, twt, make_scale(geo, ptab, c0, accel),
                       reinterpret_cast<C2<T>*>(lds_raw));
 }
 
 // G[1 - cur] <- reunit(g G[cur]) with g = reunit(1 + dtilde) from D.
-template <typename T, int NE, int LMAX>
+// EXPO: g = exp(dtilde) (LGF_UPDATE_EXP) instead of reunit(1 + dtilde).
+template <typename T, int NE, int LMAX, bool EXPO>
 __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict__ D, C2<T>* G0, C2<T>* G1,
                                                const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
                                                const DevState* __restrict__ st)
@@ -875,8 +907,24 @@ __global__ void __launch_bounds__(256) k_gauge(Geo geo, const C2<T>* __restrict_
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     const int cur = st->cur;
-    gauge_plane<T, NE, LMAX>(geo, plane_of_block(blockIdx.x, geo), D, cur ? G1 : G0, cur ? G0 : G1, twx, twy,
-                             reinterpret_cast<C2<T>*>(lds_raw));
+    gauge_plane<T, NE, LMAX, EXPO>(geo, plane_of_block(blockIdx.x, geo), D, cur ? G1 : G0, cur ? G0 : G1, twx, twy,
+                                   reinterpret_cast<C2<T>*>(lds_raw));
+}
+
+// The same with the inverse (x, y) FFT two fields at a time in half the LDS;
+// for planes of exactly 4 sites per thread (kGauge2fSites).
+constexpr int kGauge2fSites = 4;
+
+template <typename T, int NE, int LMAX, bool EXPO>
+__global__ void __launch_bounds__(256) k_gauge2f(Geo geo, const C2<T>* __restrict__ D, C2<T>* G0, C2<T>* G1,
+                                                 const C2<T>* __restrict__ twx, const C2<T>* __restrict__ twy,
+                                                 const DevState* __restrict__ st)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    const int cur = st->cur;
+    gauge_plane_2f<T, NE, LMAX, kGauge2fSites, 0, EXPO>(geo, plane_of_block(blockIdx.x, geo), D, cur ? G1 : G0,
+                                                       cur ? G0 : G1, twx, twy, reinterpret_cast<C2<T>*>(lds_raw));
 }
 
 template <int UNUSED = 0>
@@ -948,7 +996,7 @@ __device__ __forceinline__ bool batch_active(const DevState* st, int phase, int 
 
 // NEXT = false: measure the links of the current gauge G[cur] (members that
 // need a measure); NEXT = true: those of the gauge k_gauge just formed.
-template <typename T, int NE, bool NEXT, int LMAX>
+template <typename T, int NE, bool NEXT, int LMAX, bool ONCE>
 __global__ void __launch_bounds__(256) kb_measure(const BatchCfg<T>* __restrict__ cfgs, const uint32_t* __restrict__ items,
                                                   int nitems, int phase)
 {
@@ -959,8 +1007,13 @@ __global__ void __launch_bounds__(256) kb_measure(const BatchCfg<T>* __restrict_
         if (!batch_active(bc.st, phase, NEXT ? 1 : 0)) continue;
         const int sel = bc.st->cur ^ (NEXT ? 1 : 0);
         __syncthreads();
-        measure_plane<T, NE, LMAX>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), bc.U, bc.G[sel], bc.D, bc.partial,
-                                   bc.tw[0], bc.tw[1], lds_raw, reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x));
+        const int q = (int)(w & ((1u << kItemShift) - 1));
+        C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x);
+        if constexpr (ONCE)
+            measure_plane_once<T, NE, LMAX>(bc.geo, q, bc.U, bc.G[sel], bc.D, bc.partial, bc.tw[0], bc.tw[1], lds_raw,
+                                            buf);
+        else
+            measure_plane<T, NE, LMAX>(bc.geo, q, bc.U, bc.G[sel], bc.D, bc.partial, bc.tw[0], bc.tw[1], lds_raw, buf);
     }
 }
 
@@ -980,7 +1033,7 @@ __global__ void __launch_bounds__(512) kb_zt(const BatchCfg<T>* __restrict__ cfg
     }
 }
 
-template <typename T, int NE, int LMAX>
+template <typename T, int NE, int LMAX, bool EXPO>
 __global__ void __launch_bounds__(256) kb_gauge(const BatchCfg<T>* __restrict__ cfgs, const uint32_t* __restrict__ items,
                                                 int nitems, int phase)
 {
@@ -991,8 +1044,8 @@ __global__ void __launch_bounds__(256) kb_gauge(const BatchCfg<T>* __restrict__ 
         if (!batch_active(bc.st, phase, 1)) continue;
         __syncthreads();
         const int cur = bc.st->cur;
-        gauge_plane<T, NE, LMAX>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), bc.D, bc.G[cur], bc.G[cur ^ 1],
-                                 bc.tw[0], bc.tw[1], reinterpret_cast<C2<T>*>(lds_raw));
+        gauge_plane<T, NE, LMAX, EXPO>(bc.geo, (int)(w & ((1u << kItemShift) - 1)), bc.D, bc.G[cur],
+                                       bc.G[cur ^ 1], bc.tw[0], bc.tw[1], reinterpret_cast<C2<T>*>(lds_raw));
     }
 }
 

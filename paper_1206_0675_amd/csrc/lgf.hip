@@ -136,17 +136,7 @@ int32_t set_stop(lgf_context* c, double theta_stop)
 template <typename T, int NE, int LMAX>
 int32_t set_lds_attrs(lgf_context* c)
 {
-    const Geo& g = bufs<T>(c).geo;
-    const int mlds = (int)(plane_lds_elems(g) * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double));
-    const int glds = (int)(plane_lds_elems(g) * sizeof(C2<T>));
-    const int zlds = (int)((size_t)g.NQ * g.W * sizeof(C2<T>));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T, NE, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, mlds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<T, NE, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, glds));
-    HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt<T, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, zlds));
-    return LGF_OK;
+    return set_plane_lds<T, NE, LMAX>(c, bufs<T>(c).geo, c->nth_plane);
 }
 
 // ----------------------------------------------------------------------------
@@ -155,48 +145,44 @@ int32_t set_lds_attrs(lgf_context* c)
 // Delta, F, theta of the current links G[cur] U0 G[cur]^dag(x+mu) with no
 // update (the first line of Algorithm 1).
 template <typename T, int NE, int LMAX>
-int32_t enqueue_measure(lgf_context* c, double* trace_slot)
+IterArgs<T> iter_args(lgf_context* c)
 {
     Bufs<T>& b = bufs<T>(c);
-    const Geo& g = b.geo;
-    const size_t lds = plane_lds_elems(g) * sizeof(C2<T>) + 2 * c->nth_plane * sizeof(double);
-    TRY(launch(c, K_MEASURE, k_measure<T, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane), lds, g,
-               (const C2<T>*)b.U, (const C2<T>*)b.G, (const C2<T>*)b.Gb, 0, b.D, c->partial,
-               (const C2<T>*)(b.tw + b.tw_off[0]), (const C2<T>*)(b.tw + b.tw_off[1]), (const DevState*)c->st));
-    TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
-               trace_slot, 0));
+    IterArgs<T> a;
+    a.U = b.U;
+    a.G0 = b.G;
+    a.G1 = b.Gb;
+    a.D = b.D;
+    for (int m = 0; m < 4; ++m) a.tw[m] = b.tw + b.tw_off[m];
+    a.ptab = c->ptab;
+    a.partial = c->partial;
+    a.st = c->st;
+    a.c0 = c->c0;
+    a.accel = c->p.accel == LGF_ACCEL_FOURIER ? 1 : 0;
+    a.expo = c->p.update == LGF_UPDATE_EXP ? 1 : 0;
+    a.nth = c->nth_plane;
+    return a;
+}
+
+// Delta, F, theta of the current links G[cur] U0 G[cur]^dag(x+mu) with no
+// update (the first line of Algorithm 1).
+template <typename T, int NE, int LMAX>
+int32_t enqueue_measure(lgf_context* c, double* trace_slot)
+{
+    TRY((enqueue_plain_measure<T, NE, LMAX>(c, bufs<T>(c).geo, iter_args<T, NE, LMAX>(c), trace_slot)));
     c->delta_valid = true;
     return LGF_OK;
 }
 
 // filter, g, transform, Delta/F/theta of the new links (the loop body of
-// Algorithm 1).  The links are G U0 G^dag(x+mu) for the loaded links U0 and
-// the accumulated gauge G: k_gauge forms G[1 - cur] = reunit(g G[cur]) and
-// k_measure measures the links it gives; the reduction flips cur.  No link is
-// written.  When the stop flag is set every kernel returns at once.  The launch arguments do not change
-// from one iteration to the next, so a chunk of iterations can be captured
-// once in a graph and replayed.
+// Algorithm 1); see enqueue_plain_update.  When the stop flag is set every
+// kernel returns at once.  The launch arguments do not change from one
+// iteration to the next, so a chunk of iterations can be captured once in a
+// graph and replayed.
 template <typename T, int NE, int LMAX>
 int32_t enqueue_update(lgf_context* c, double* trace_slot)
 {
-    Bufs<T>& b = bufs<T>(c);
-    const Geo& g = b.geo;
-    const size_t zlds = (size_t)g.NQ * g.W * sizeof(C2<T>);
-    const size_t glds = plane_lds_elems(g) * sizeof(C2<T>);
-    const size_t mlds = glds + 2 * c->nth_plane * sizeof(double);
-    const C2<T>* twx = b.tw + b.tw_off[0];
-    const C2<T>* twy = b.tw + b.tw_off[1];
-    TRY(launch(c, K_ZT, k_zt<T, LMAX>, dim3((g.NP / g.W) * 4), dim3(512), zlds, g, b.D,
-               (const C2<T>*)(b.tw + b.tw_off[2]), (const C2<T>*)(b.tw + b.tw_off[3]), (const double*)c->ptab,
-               c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), (const DevState*)c->st));
-    TRY(launch(c, K_GAUGE, k_gauge<T, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g, (const C2<T>*)b.D, b.G,
-               b.Gb, twx, twy, (const DevState*)c->st));
-    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<T, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane), mlds, g,
-               (const C2<T>*)b.U, (const C2<T>*)b.G, (const C2<T>*)b.Gb, 1, b.D, c->partial, twx, twy,
-               (const DevState*)c->st));
-    TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
-               trace_slot, 1));
-    return LGF_OK;
+    return enqueue_plain_update<T, NE, LMAX>(c, bufs<T>(c).geo, iter_args<T, NE, LMAX>(c), trace_slot);
 }
 
 // Kernel variant for the current phase, storage and longest lattice axis.
@@ -574,22 +560,16 @@ int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double*
 {
     Bufs<double>& b = c->d;
     const Geo& g = b.geo;
-    const C2<double>* twx = b.tw + b.tw_off[0];
-    const C2<double>* twy = b.tw + b.tw_off[1];
-    const size_t glds = plane_lds_elems(g) * sizeof(C2<double>);
     TRY(launch(c, K_ZT_INV, k_zt_inv_scaled<double, LMAX>, dim3((g.NP / g.W) * 4), dim3(512),
                (size_t)g.NQ * g.W * sizeof(C2<double>), g, (const C2<double>*)c->D2, c->D3,
                (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
                (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), (const int8_t*)c->btab, s,
                (const DevState*)c->st));
-    TRY(launch(c, K_GAUGE, k_gauge<double, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane), glds, g,
-               (const C2<double>*)c->D3, b.G, b.Gb, twx, twy, (const DevState*)c->st));
-    TRY(launch(c, K_TRANSFORM_MEASURE, k_measure<double, NE, LMAX>, dim3(g.NQ), dim3(c->nth_plane),
-               glds + 2 * c->nth_plane * sizeof(double), g, (const C2<double>*)b.U, (const C2<double>*)b.G,
-               (const C2<double>*)b.Gb, 1, b.D, c->partial, twx, twy, (const DevState*)c->st));
-    TRY(launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
-               trace_slot, mode));
-    return LGF_OK;
+    IterArgs<double> a = iter_args<double, NE, LMAX>(c);
+    a.D = c->D3;
+    TRY((enqueue_gauge_k<double, NE, LMAX>(c, g, a)));
+    a.D = b.D;
+    return enqueue_measure_k<double, NE, LMAX>(c, g, a, 1, trace_slot, mode);
 }
 
 int32_t bands_any(lgf_context* c, bool use_model)
@@ -746,6 +726,8 @@ int32_t lgf_create(const lgf_params* p, lgf_ctx* out)
         return fail(nullptr, LGF_E_INVALID_ARG, "the learned step runs in FP64");
     if (p->accel != LGF_ACCEL_FOURIER && p->accel != LGF_ACCEL_NONE)
         return fail(nullptr, LGF_E_INVALID_ARG, "accel must be LGF_ACCEL_FOURIER or LGF_ACCEL_NONE");
+    if (p->update != LGF_UPDATE_FIRST_ORDER && p->update != LGF_UPDATE_EXP)
+        return fail(nullptr, LGF_E_INVALID_ARG, "update must be LGF_UPDATE_FIRST_ORDER or LGF_UPDATE_EXP");
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(nullptr, LGF_E_INVALID_ARG, "alpha must be > 0");
     if (!(p->theta_stop >= 0.0) || !(p->theta_switch >= 0.0))
         return fail(nullptr, LGF_E_INVALID_ARG, "theta_stop and theta_switch must be >= 0");

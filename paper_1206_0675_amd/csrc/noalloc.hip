@@ -162,20 +162,20 @@ int32_t run(Runner* r, const lgf_params* p, const Geo& g, unsigned char* base, c
         HIPCHK(r, hipMemcpyAsync(tw, tw_h, sizeof(C2<double>) * n, hipMemcpyHostToDevice, r->stream));
         HIPCHK(r, hipMemcpyAsync(ptab, pt_h, sizeof(double) * n, hipMemcpyHostToDevice, r->stream));
     }
-    const double c0 = 0.5 * p->alpha * (p->accel == LGF_ACCEL_FOURIER ? p2max : 1.0) / (double)g.V;
-    const C2<double>* twx = tw + tw_off[0];
-    const C2<double>* twy = tw + tw_off[1];
-    const C2<double>* twz = tw + tw_off[2];
-    const C2<double>* twt = tw + tw_off[3];
-    const size_t glds = plane_lds_elems(g) * sizeof(C2<double>);
-    const size_t mlds = glds + 2 * nth * sizeof(double);
-    const size_t zlds = (size_t)g.NQ * g.W * sizeof(C2<double>);
-    HIPCHK(r, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<double, NE, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds));
-    HIPCHK(r, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gauge<double, NE, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds));
-    HIPCHK(r, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt<double, LMAX>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)zlds));
+    IterArgs<double> a;
+    a.U = U;
+    a.G0 = G;
+    a.G1 = Gb;
+    a.D = D;
+    for (int m = 0; m < 4; ++m) a.tw[m] = tw + tw_off[m];
+    a.ptab = ptab;
+    a.partial = partial;
+    a.st = st;
+    a.c0 = 0.5 * p->alpha * (p->accel == LGF_ACCEL_FOURIER ? p2max : 1.0) / (double)g.V;
+    a.accel = p->accel == LGF_ACCEL_FOURIER ? 1 : 0;
+    a.expo = p->update == LGF_UPDATE_EXP ? 1 : 0;
+    a.nth = nth;
+    TRY((set_plane_lds<double, NE, LMAX>(r, g, nth)));
 
     // load: state and counters cleared, links laid out and checked, G = 1
     TRY(launch(r, K_STATE, k_na_init, dim3(1), dim3(1), 0, st, check));
@@ -196,27 +196,13 @@ int32_t run(Runner* r, const lgf_params* p, const Geo& g, unsigned char* base, c
 
     // Algorithm 1: measure, then updates in chunks of poll_every until
     // theta < theta_stop or max_iter
-    const int accel = p->accel == LGF_ACCEL_FOURIER ? 1 : 0;
     TRY(launch(r, K_STATE, k_na_stop, dim3(1), dim3(1), 0, st, p->theta_stop));
-    TRY(launch(r, K_MEASURE, k_measure<double, NE, LMAX>, dim3(g.NQ), dim3(nth), mlds, g, (const C2<double>*)U,
-               (const C2<double>*)G, (const C2<double>*)Gb, 0, D, partial, twx, twy, (const DevState*)st));
-    TRY(launch(r, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)partial, g.NQ, g.V, st,
-               (double*)nullptr, 0));
+    TRY((enqueue_plain_measure<double, NE, LMAX>(r, g, a, nullptr)));
     HIPCHK(r, hipMemcpyAsync(&sh, st, sizeof(DevState), hipMemcpyDeviceToHost, r->stream));
     HIPCHK(r, hipStreamSynchronize(r->stream));
     while (!sh.done && sh.iter < p->max_iter) {
         const int64_t chunk = std::min<int64_t>(p->poll_every, p->max_iter - sh.iter);
-        for (int64_t k = 0; k < chunk; ++k) {
-            TRY(launch(r, K_ZT, k_zt<double, LMAX>, dim3((g.NP / g.W) * 4), dim3(512), zlds, g, D, twz, twt,
-                       (const double*)ptab, c0, accel, (const DevState*)st));
-            TRY(launch(r, K_GAUGE, k_gauge<double, NE, LMAX>, dim3(g.NQ), dim3(nth), glds, g, (const C2<double>*)D,
-                       G, Gb, twx, twy, (const DevState*)st));
-            TRY(launch(r, K_TRANSFORM_MEASURE, k_measure<double, NE, LMAX>, dim3(g.NQ), dim3(nth), mlds, g,
-                       (const C2<double>*)U, (const C2<double>*)G, (const C2<double>*)Gb, 1, D, partial, twx, twy,
-                       (const DevState*)st));
-            TRY(launch(r, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)partial, g.NQ, g.V, st,
-                       (double*)nullptr, 1));
-        }
+        for (int64_t k = 0; k < chunk; ++k) TRY((enqueue_plain_update<double, NE, LMAX>(r, g, a, nullptr)));
         HIPCHK(r, hipMemcpyAsync(&sh, st, sizeof(DevState), hipMemcpyDeviceToHost, r->stream));
         HIPCHK(r, hipStreamSynchronize(r->stream));
     }
@@ -257,6 +243,8 @@ int32_t lgf_fix_noalloc(const lgf_params* p, const double* links_in, double* lin
         return fail(nullptr, LGF_E_INVALID_ARG, "storage must be LGF_STORE18 or LGF_STORE12");
     if (p->accel != LGF_ACCEL_FOURIER && p->accel != LGF_ACCEL_NONE)
         return fail(nullptr, LGF_E_INVALID_ARG, "accel must be LGF_ACCEL_FOURIER or LGF_ACCEL_NONE");
+    if (p->update != LGF_UPDATE_FIRST_ORDER && p->update != LGF_UPDATE_EXP)
+        return fail(nullptr, LGF_E_INVALID_ARG, "update must be LGF_UPDATE_FIRST_ORDER or LGF_UPDATE_EXP");
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(nullptr, LGF_E_INVALID_ARG, "alpha must be > 0");
     if (!(p->theta_stop >= 0.0)) return fail(nullptr, LGF_E_INVALID_ARG, "theta_stop must be >= 0");
     if (p->max_iter < 0 || p->poll_every < 1) return fail(nullptr, LGF_E_INVALID_ARG, "max_iter >= 0, poll_every >= 1");

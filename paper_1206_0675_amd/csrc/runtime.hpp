@@ -208,6 +208,28 @@ Geo make_geo(const int32_t* dims, int tile_bytes = 64)
     return g;
 }
 
+// log2 of the plane positions one (z, t) block transforms: the tile width W,
+// halved while the block's LDS exceeds 64 KB (so two blocks share a CU) and,
+// on small lattices, while there are fewer than 512 blocks (down to 2
+// positions per block).
+template <typename T>
+int zt_part_log(const Geo& g)
+{
+    int l = g.logW;
+    while (l > 0 && ((size_t)g.NQ << l) * sizeof(C2<T>) > 64 * 1024) --l;
+    while (l > 1 && (g.NP >> l) * 4 < 512) --l;
+    return l;
+}
+
+// Blocks and LDS bytes of the (z, t) launch with parts of 2^l positions.
+inline int zt_blocks(const Geo& g, int l) { return (g.NP >> l) * 4; }
+template <typename T>
+size_t zt_lds(const Geo& g, int l) { return ((size_t)g.NQ << l) * sizeof(C2<T>); }
+
+// The gauge kernel runs its inverse (x, y) FFT two fields at a time when every
+// thread holds exactly kGauge2fSites sites of the plane.
+inline bool gauge_two_field(const Geo& g, int nth) { return g.NP == kGauge2fSites * nth; }
+
 // Complex elements of the Delta buffer.
 inline int64_t delta_elems(const Geo& g) { return (int64_t)(g.NP / g.W) * 4 * g.DS; }
 
@@ -236,6 +258,112 @@ bool shape_fits(const int32_t* dims, int nth)
     if (4 * npp * sizeof(C2<T>) + 2 * nth * sizeof(double) > kMaxLds) return false;
     if (nq * sizeof(C2<T>) > kMaxLdsZt) return false;
     return true;
+}
+
+// ---------------------------------------------------------------------------
+// One plain iteration of Algorithm 1 on one lattice, enqueued.  Shared by the
+// context (lgf.hip) and the allocation-free entry point (noalloc.hip), so
+// both launch the same kernels with the same shapes.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct IterArgs {
+    const C2<T>* U = nullptr;    // loaded links U0
+    C2<T>* G0 = nullptr;         // gauge pair; G[cur] current
+    C2<T>* G1 = nullptr;
+    C2<T>* D = nullptr;          // packed Delta (tiled)
+    const C2<T>* tw[4] = {};     // twiddles per axis
+    const double* ptab = nullptr;
+    double* partial = nullptr;   // per-plane F, theta partials
+    DevState* st = nullptr;
+    double c0 = 0.0;             // (alpha/2) p2max / V (or (alpha/2) / V without acceleration)
+    int accel = 1;
+    int expo = 0;
+    int nth = 256;               // threads per plane block
+};
+
+template <typename T>
+size_t measure_lds(const Geo& g, int nth) { return plane_lds_elems(g) * sizeof(C2<T>) + 2 * nth * sizeof(double); }
+template <typename T>
+size_t gauge_lds(const Geo& g, int nth)
+{
+    return plane_lds_elems(g) * sizeof(C2<T>) / (gauge_two_field(g, nth) ? 2 : 1);
+}
+
+template <typename T, int NE, int LMAX>
+int32_t set_plane_lds(Runner* r, const Geo& g, int nth)
+{
+    for (const void* f : {reinterpret_cast<const void*>(&k_measure<T, NE, LMAX, false>),
+                          reinterpret_cast<const void*>(&k_measure<T, NE, LMAX, true>)})
+        HIPCHK(r, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)measure_lds<T>(g, nth)));
+    for (const void* f : {reinterpret_cast<const void*>(&k_gauge<T, NE, LMAX, false>),
+                          reinterpret_cast<const void*>(&k_gauge<T, NE, LMAX, true>)})
+        HIPCHK(r, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)(plane_lds_elems(g) * sizeof(C2<T>))));
+    for (const void* f : {reinterpret_cast<const void*>(&k_gauge2f<T, NE, LMAX, false>),
+                          reinterpret_cast<const void*>(&k_gauge2f<T, NE, LMAX, true>)})
+        HIPCHK(r, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)(plane_lds_elems(g) * sizeof(C2<T>) / 2)));
+    HIPCHK(r, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt<T, LMAX>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)zt_lds<T>(g, g.logW)));
+    return LGF_OK;
+}
+
+// The plane kernels form each in-plane link once when an x row fits in one
+// wavefront.
+inline bool measure_once(const Geo& g) { return g.L[0] <= 64; }
+
+// Transform + Delta + F/theta partials + forward (x, y) FFT, then the
+// one-block reduction of F and theta (a7).  next = 0: the links of the
+// current gauge G[cur]; next = 1: those of G[1 - cur] just formed.
+// counts_update as for reduce_state.
+template <typename T, int NE, int LMAX>
+int32_t enqueue_measure_k(Runner* r, const Geo& g, const IterArgs<T>& a, int next, double* trace, int counts_update)
+{
+    const int kid = next ? K_TRANSFORM_MEASURE : K_MEASURE;
+    const size_t lds = measure_lds<T>(g, a.nth);
+    if (measure_once(g))
+        TRY(launch(r, kid, k_measure<T, NE, LMAX, true>, dim3(g.NQ), dim3(a.nth), lds, g, a.U, (const C2<T>*)a.G0,
+                   (const C2<T>*)a.G1, next, a.D, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st));
+    else
+        TRY(launch(r, kid, k_measure<T, NE, LMAX, false>, dim3(g.NQ), dim3(a.nth), lds, g, a.U, (const C2<T>*)a.G0,
+                   (const C2<T>*)a.G1, next, a.D, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st));
+    return launch(r, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)a.partial, g.NQ, g.V, a.st, trace,
+                  counts_update);
+}
+
+// G[1 - cur] = reunit(g G[cur]) with g from the filtered Delta in a.D.
+template <typename T, int NE, int LMAX, bool EXPO>
+int32_t enqueue_gauge_kx(Runner* r, const Geo& g, const IterArgs<T>& a)
+{
+    if (gauge_two_field(g, a.nth))
+        return launch(r, K_GAUGE, k_gauge2f<T, NE, LMAX, EXPO>, dim3(g.NQ), dim3(a.nth), gauge_lds<T>(g, a.nth), g,
+                      (const C2<T>*)a.D, a.G0, a.G1, a.tw[0], a.tw[1], (const DevState*)a.st);
+    return launch(r, K_GAUGE, k_gauge<T, NE, LMAX, EXPO>, dim3(g.NQ), dim3(a.nth), gauge_lds<T>(g, a.nth), g,
+                  (const C2<T>*)a.D, a.G0, a.G1, a.tw[0], a.tw[1], (const DevState*)a.st);
+}
+
+template <typename T, int NE, int LMAX>
+int32_t enqueue_gauge_k(Runner* r, const Geo& g, const IterArgs<T>& a)
+{
+    return a.expo ? enqueue_gauge_kx<T, NE, LMAX, true>(r, g, a) : enqueue_gauge_kx<T, NE, LMAX, false>(r, g, a);
+}
+
+template <typename T, int NE, int LMAX>
+int32_t enqueue_plain_measure(Runner* r, const Geo& g, const IterArgs<T>& a, double* trace)
+{
+    return enqueue_measure_k<T, NE, LMAX>(r, g, a, 0, trace, 0);
+}
+
+// Filter ((z, t) FFT, spectral scale, inverse), g and G, then the Delta of
+// the new links; the reduction flips cur.
+template <typename T, int NE, int LMAX>
+int32_t enqueue_plain_update(Runner* r, const Geo& g, const IterArgs<T>& a, double* trace)
+{
+    const int l = zt_part_log<T>(g);
+    TRY(launch(r, K_ZT, k_zt<T, LMAX>, dim3(zt_blocks(g, l)), dim3(512), zt_lds<T>(g, l), g, a.D, a.tw[2], a.tw[3],
+               a.ptab, a.c0, a.accel, l, (const DevState*)a.st));
+    TRY((enqueue_gauge_k<T, NE, LMAX>(r, g, a)));
+    return enqueue_measure_k<T, NE, LMAX>(r, g, a, 1, trace, 1);
 }
 
 template <typename T>

@@ -164,6 +164,7 @@ __device__ __forceinline__ double re_trace(const M3<T>& u)
 template <typename T>
 __device__ __forceinline__ double alg_norm2(const Alg8<T>& d)
 {
+#pragma clang fp contract(off)
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) s += 2.0 * ((double)d.c[c].x * d.c[c].x + (double)d.c[c].y * d.c[c].y);
@@ -173,8 +174,11 @@ __device__ __forceinline__ double alg_norm2(const Alg8<T>& d)
 
 // 1 + D for a packed anti-Hermitian traceless D, projected to SU(3) by row
 // Gram-Schmidt (row 3 = (row 1 x row 2)^*), in double precision.
+// No contraction anywhere in it, so every kernel that inlines it rounds the
+// same way (the launch shape picks among kernels, and must not change bits).
 __device__ __forceinline__ void one_plus_alg_reunit(const C2<double> c[4], M3<double>& m)
 {
+#pragma clang fp contract(off)
     const double a = c[3].x, b = c[3].y;
     C2<double> r0[3] = {mk<double>(1.0, a), c[0], c[1]};
     C2<double> r1[3] = {mk<double>(-c[0].x, c[0].y), mk<double>(1.0, b), c[2]};
@@ -201,9 +205,92 @@ __device__ __forceinline__ void one_plus_alg_reunit(const C2<double> c[4], M3<do
     rebuild_row3(m);
 }
 
-// Row Gram-Schmidt projection of a general 3x3 matrix to SU(3), in double.
+// exp(X) for a packed anti-Hermitian traceless X (c[0] = X01, c[1] = X02,
+// c[2] = X12, c[3] = Im X00 + i Im X11), in double: the update of eq. gx
+// with the exponential taken exactly instead of to first order.
+// Q = -i X is Hermitian and traceless, so by the Cayley-Hamilton theorem
+// Q^3 = k1 Q + k0 1 with k1 = Tr(Q^2)/2 and k0 = det Q, and every power
+// Q^n = b0 1 + b1 Q + b2 Q^2 with Q^(n+1) = k0 b2 1 + (b0 + k1 b2) Q + b1 Q^2.
+// exp(iQ) = f0 1 + f1 Q + f2 Q^2 with f_k = sum_n (i^n / n!) b_k(n), summed
+// over 24 terms after Q is scaled by 2^-m so that its eigenvalues (at most
+// sqrt(2 k1) in size) are at most 1 (remainder below 1e-24); the result is
+// then squared m times.
+__device__ __forceinline__ void alg_exp(const C2<double> c[4], M3<double>& m)
+{
+#pragma clang fp contract(off)
+    const double a = c[3].x, b = c[3].y;
+    // Q = -i X
+    M3<double> q;
+    q.e[0] = mk<double>(a, 0.0);
+    q.e[4] = mk<double>(b, 0.0);
+    q.e[8] = mk<double>(-(a + b), 0.0);
+    q.e[1] = mk<double>(c[0].y, -c[0].x);        // -i X01
+    q.e[2] = mk<double>(c[1].y, -c[1].x);
+    q.e[5] = mk<double>(c[2].y, -c[2].x);
+    q.e[3] = conjg(q.e[1]);
+    q.e[6] = conjg(q.e[2]);
+    q.e[7] = conjg(q.e[5]);
+    double k1 = 0.5 * (a * a + b * b + (a + b) * (a + b)) +
+                (c[0].x * c[0].x + c[0].y * c[0].y + c[1].x * c[1].x + c[1].y * c[1].y + c[2].x * c[2].x +
+                 c[2].y * c[2].y);
+    int halvings = 0;
+    double sc = 1.0;
+    while (2.0 * k1 * sc * sc > 1.0) {
+        sc *= 0.5;
+        ++halvings;
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) q.e[e] = scale(q.e[e], sc);
+    k1 *= sc * sc;
+    // det Q (real for Hermitian Q)
+    const C2<double> d = cmul(q.e[0], cmul(q.e[4], q.e[8]) - cmul(q.e[5], q.e[7])) -
+                         cmul(q.e[1], cmul(q.e[3], q.e[8]) - cmul(q.e[5], q.e[6])) +
+                         cmul(q.e[2], cmul(q.e[3], q.e[7]) - cmul(q.e[4], q.e[6]));
+    const double k0 = d.x;
+    double b0 = 1.0, b1 = 0.0, b2 = 0.0, t = 1.0;           // Q^0, and |i^n / n!|
+    double f0r = 0.0, f0i = 0.0, f1r = 0.0, f1i = 0.0, f2r = 0.0, f2i = 0.0;
+#pragma unroll
+    for (int n = 0; n < 24; ++n) {
+        // i^n: n mod 4 = 0, 1, 2, 3 -> 1, i, -1, -i
+        const int r = n & 3;
+        const double tr = r == 0 ? t : (r == 2 ? -t : 0.0);
+        const double ti = r == 1 ? t : (r == 3 ? -t : 0.0);
+        f0r += tr * b0; f0i += ti * b0;
+        f1r += tr * b1; f1i += ti * b1;
+        f2r += tr * b2; f2i += ti * b2;
+        const double nb0 = k0 * b2, nb1 = b0 + k1 * b2, nb2 = b1;
+        b0 = nb0; b1 = nb1; b2 = nb2;
+        t /= (double)(n + 1);
+    }
+    M3<double> q2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            q2.e[3 * i + k] = cfma(q.e[3 * i + 2], q.e[6 + k], cfma(q.e[3 * i + 1], q.e[3 + k], cmul(q.e[3 * i], q.e[k])));
+    const C2<double> f0 = mk<double>(f0r, f0i), f1 = mk<double>(f1r, f1i), f2 = mk<double>(f2r, f2i);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m.e[e] = cfma(f2, q2.e[e], cmul(f1, q.e[e]));
+    m.e[0] = m.e[0] + f0;
+    m.e[4] = m.e[4] + f0;
+    m.e[8] = m.e[8] + f0;
+    for (int h = 0; h < halvings; ++h) {
+        M3<double> s2;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                s2.e[3 * i + k] =
+                    cfma(m.e[3 * i + 2], m.e[6 + k], cfma(m.e[3 * i + 1], m.e[3 + k], cmul(m.e[3 * i], m.e[k])));
+        m = s2;
+    }
+}
+
+// Row Gram-Schmidt projection of a general 3x3 matrix to SU(3), in double
+// (no contraction, as one_plus_alg_reunit).
 __device__ __forceinline__ void reunit(M3<double>& m)
 {
+#pragma clang fp contract(off)
     double n0 = 0.0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) n0 += m.e[j].x * m.e[j].x + m.e[j].y * m.e[j].y;

@@ -28,11 +28,12 @@ FP64, FP32, MIXED = 0, 1, 2
 STORE18, STORE12 = 18, 12
 STEP_PLAIN, STEP_LEARNED = 0, 1
 ACCEL_NONE, ACCEL_FOURIER = 0, 1
+UPDATE_FIRST_ORDER, UPDATE_EXP = 0, 1
 
 
 class Params(C.Structure):
     _fields_ = [("dims", C.c_int32 * 4), ("precision", C.c_int32), ("storage", C.c_int32),
-                ("step", C.c_int32), ("accel", C.c_int32), ("track_gauge", C.c_int32),
+                ("step", C.c_int32), ("accel", C.c_int32), ("update", C.c_int32),
                 ("profile", C.c_int32), ("alpha", C.c_double), ("theta_stop", C.c_double),
                 ("theta_switch", C.c_double), ("unit_tol", C.c_double), ("max_iter", C.c_int64),
                 ("poll_every", C.c_int32), ("no_graph", C.c_int32), ("stream", C.c_void_p),

@@ -1,20 +1,22 @@
 // CPU stand-in for the small part of the HIP API the gauge-fixing library
 // uses.  TEST INFRASTRUCTURE: it lets the unmodified HIP sources be compiled
-// by g++ and run on the host (one std::thread per GPU thread, a std::barrier
-// per __syncthreads, blocks one after another) so that index arithmetic,
-// bounds and barrier placement can be checked on a machine without a GPU,
-// with AddressSanitizer.  It is never part of the library that runs on the GPU.
+// by g++ and run on the host, so that index arithmetic, bounds and barrier
+// placement can be checked on a machine without a GPU, with
+// AddressSanitizer.  It is never part of the library that runs on the GPU.
+//
+// Blocks run one after another.  The threads of a block are fibers on one
+// host thread (user-space stacks and a small context switch): each runs until
+// its next __syncthreads, and once all of them are there the next round
+// starts, so a barrier costs two context switches per thread.
 #pragma once
 #include <algorithm>
 #include <atomic>
-#include <barrier>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
-#include <thread>
 #include <vector>
 
 #define __global__
@@ -23,6 +25,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __restrict__ __restrict
+#define __align__(n) __attribute__((aligned(n)))
 // one block runs at a time, so a function-static array is exactly the
 // block's shared memory
 #define __shared__ static
@@ -33,10 +36,10 @@ struct dim3 {
 };
 
 namespace emu {
-inline thread_local dim3 tidx;
+inline dim3 tidx;
 inline dim3 bidx, bdim, gdim;
-inline std::barrier<>* bar = nullptr;
 inline std::vector<unsigned char> dyn_lds;
+inline void yield_barrier();
 }  // namespace emu
 
 #define threadIdx (emu::tidx)
@@ -45,7 +48,8 @@ inline std::vector<unsigned char> dyn_lds;
 #define gridDim (emu::gdim)
 #define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(emu::dyn_lds.data());
 
-inline void __syncthreads() { emu::bar->arrive_and_wait(); }
+inline void __syncthreads() { emu::yield_barrier(); }
+inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 
 // Cross-lane read within a wavefront of 64 threads (ds_bpermute on the GPU).
 // Every thread of the block must call it together, as every lane of a
@@ -57,9 +61,9 @@ inline double __shfl(double v, int src_lane, int width = 64)
 {
     const unsigned t = emu::tidx.x + emu::bdim.x * (emu::tidx.y + emu::bdim.y * emu::tidx.z);
     emu::shfl_slots[t] = v;
-    emu::bar->arrive_and_wait();
+    emu::yield_barrier();
     const double r = emu::shfl_slots[(t & ~63u) | (unsigned)(src_lane & (width - 1))];
-    emu::bar->arrive_and_wait();
+    emu::yield_barrier();
     return r;
 }
 inline float __shfl(float v, int src_lane, int width = 64) { return (float)__shfl((double)v, src_lane, width); }
@@ -170,11 +174,101 @@ inline hipError_t hipGraphLaunch(hipGraphExec_t g, hipStream_t)
 }
 enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 1 };
 inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+// A file-scope device array is an ordinary host array here.
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void** p, const void* symbol)
+{
+    *p = const_cast<void*>(symbol);
+    return hipSuccess;
+}
 inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 4; return hipSuccess; }
 
+#if defined(__SANITIZE_ADDRESS__)
+#include <sanitizer/common_interface_defs.h>
+#endif
+
+// Switch stacks: push the callee-saved registers, store the stack pointer in
+// *save, load `load` and pop the next context's registers.  A new fiber's
+// stack is laid out so that the final `ret` enters emu::fiber_entry.
+extern "C" void emu_ctx_switch(void** save, void* load);
+asm(R"(
+    .text
+    .weak emu_ctx_switch
+    .type emu_ctx_switch, @function
+emu_ctx_switch:
+    pushq %rbp
+    pushq %rbx
+    pushq %r12
+    pushq %r13
+    pushq %r14
+    pushq %r15
+    movq %rsp, (%rdi)
+    movq %rsi, %rsp
+    popq %r15
+    popq %r14
+    popq %r13
+    popq %r12
+    popq %rbx
+    popq %rbp
+    ret
+    .size emu_ctx_switch, .-emu_ctx_switch
+)");
+
 namespace emu {
-// One team of host threads per launch walks the blocks in order.  The LDS is
-// refilled with 0xff before each block, as a GPU gives no guarantee about it.
+constexpr size_t kFiberStack = size_t(512) << 10;
+struct Fiber {
+    void* sp = nullptr;
+    char* stack = nullptr;
+    int state = 0;              // 0 runnable, 1 at a barrier, 2 finished
+    void* asan_fake = nullptr;
+};
+inline std::vector<Fiber> fibers;
+inline void* sched_sp = nullptr;
+inline void* sched_fake = nullptr;
+inline const void* sched_bottom = nullptr;
+inline size_t sched_size = 0;
+inline unsigned cur = 0;
+inline std::function<void()> body;
+
+inline void asan_start(void** fake, const void* bottom, size_t size)
+{
+#if defined(__SANITIZE_ADDRESS__)
+    __sanitizer_start_switch_fiber(fake, bottom, size);
+#else
+    (void)fake; (void)bottom; (void)size;
+#endif
+}
+inline void asan_finish(void* fake, const void** bottom, size_t* size)
+{
+#if defined(__SANITIZE_ADDRESS__)
+    __sanitizer_finish_switch_fiber(fake, bottom, size);
+#else
+    (void)fake; (void)bottom; (void)size;
+#endif
+}
+
+[[noreturn]] inline void fiber_entry()
+{
+    asan_finish(nullptr, &sched_bottom, &sched_size);
+    body();
+    fibers[cur].state = 2;
+    asan_start(nullptr, sched_bottom, sched_size);      // this fiber's stack is done with
+    emu_ctx_switch(&fibers[cur].sp, sched_sp);
+    __builtin_unreachable();
+}
+
+inline void yield_barrier()
+{
+    Fiber& f = fibers[cur];
+    f.state = 1;
+    asan_start(&f.asan_fake, sched_bottom, sched_size);
+    emu_ctx_switch(&f.sp, sched_sp);
+    asan_finish(f.asan_fake, nullptr, nullptr);
+}
+
+// One launch: blocks in order; the block's threads run as fibers in rounds
+// from barrier to barrier.  The LDS is refilled with 0xff before each block,
+// as a GPU gives no guarantee about it.
 template <typename K, typename... Args>
 void launch(K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
 {
@@ -184,25 +278,40 @@ void launch(K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
     bdim = block;
     dyn_lds.assign(lds ? lds : 1, 0xff);
     shfl_slots.assign(nth + 64, 0.0);
-    std::barrier<> b((std::ptrdiff_t)nth);
-    bar = &b;
-    std::vector<std::thread> th;
-    th.reserve(nth);
+    if (fibers.size() < nth) fibers.resize(nth);
     for (unsigned t = 0; t < nth; ++t)
-        th.emplace_back([&, t] {
-            tidx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
-            for (unsigned k = 0; k < nblk; ++k) {
-                if (t == 0) {
-                    bidx = dim3(k % grid.x, (k / grid.x) % grid.y, k / (grid.x * grid.y));
-                    std::memset(dyn_lds.data(), 0xff, dyn_lds.size());
-                }
-                b.arrive_and_wait();
-                kernel(args...);
-                b.arrive_and_wait();
+        if (!fibers[t].stack) fibers[t].stack = static_cast<char*>(std::malloc(kFiberStack));
+    body = [&] { kernel(args...); };
+    for (unsigned k = 0; k < nblk; ++k) {
+        bidx = dim3(k % grid.x, (k / grid.x) % grid.y, k / (grid.x * grid.y));
+        std::memset(dyn_lds.data(), 0xff, dyn_lds.size());
+        for (unsigned t = 0; t < nth; ++t) {
+            Fiber& f = fibers[t];
+            uintptr_t top = (reinterpret_cast<uintptr_t>(f.stack) + kFiberStack) & ~uintptr_t(15);
+            void** sp = reinterpret_cast<void**>(top - 64);
+            for (int r = 0; r < 6; ++r) sp[r] = nullptr;             // r15 .. rbp
+            sp[6] = reinterpret_cast<void*>(&fiber_entry);           // ret target
+            sp[7] = nullptr;
+            f.sp = sp;
+            f.state = 0;
+        }
+        bool live = true;
+        while (live) {
+            live = false;
+            for (unsigned t = 0; t < nth; ++t) {
+                Fiber& f = fibers[t];
+                if (f.state == 2) continue;
+                cur = t;
+                tidx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+                f.state = 0;
+                asan_start(&sched_fake, f.stack, kFiberStack);
+                emu_ctx_switch(&sched_sp, f.sp);
+                asan_finish(sched_fake, nullptr, nullptr);
+                if (f.state != 2) live = true;
             }
-        });
-    for (auto& x : th) x.join();
-    bar = nullptr;
+        }
+    }
+    body = nullptr;
 }
 
 template <typename K, typename... Args>

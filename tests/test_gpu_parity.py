@@ -320,3 +320,38 @@ def test_autotuned_shape_gives_the_same_links(L, oracle_lib, dims, kw, tmp_path,
     assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[2])
     if not kw.get("precision"):
         assert rel(outs[2], oracle.step(dims, U, 4)[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("dims, kw", [((16, 16, 16, 16), {}), ((8, 16, 4, 32), {"storage": 12}),
+                                      ((8, 8, 8, 8), {"accel": 0})])
+def test_exact_exponential_steps(L, oracle_lib, dims, kw):
+    """g = exp((alpha/2) dtilde) (LGF_UPDATE_EXP, Cayley-Hamilton form on the
+    GPU) against the oracle's scaled Taylor series: one update to 1e-13, ten
+    to 1e-12 with F and theta at every iteration."""
+    U = links(dims)
+    o = oracle.opts(accel=kw.get("accel", 1) == 1, store12=kw.get("storage", 18) == 12, expo=True)
+    U1, _, _ = gpu_steps(L, dims, U, 1, update=lgf.UPDATE_EXP, **kw)
+    Uo1, _, _, _ = oracle.step(dims, U, 1, o)
+    assert rel(U1, Uo1) <= 1e-13
+    U10, tf, tt = gpu_steps(L, dims, U, 10, update=lgf.UPDATE_EXP, **kw)
+    Uo10, of, ot, _ = oracle.step(dims, U, 10, o)
+    assert rel(U10, Uo10) <= 1e-12
+    assert np.max(np.abs(tf - of) / np.abs(of)) <= 1e-12
+    assert np.max(np.abs(tt - ot) / ot) <= 1e-12
+
+
+@pytest.mark.parametrize("dims, seed", [((8, 8, 8, 8), 1), ((16, 16, 16, 16), 2)])
+def test_exact_exponential_fix(L, oracle_lib, dims, seed):
+    """Full runs with the exact exponential: final F within 1e-9 of the
+    oracle's, iteration counts within one, links unitary and on the orbit."""
+    U = links(dims, seed)
+    announce(f"exp fix {dims} seed {seed}")
+    with lgf.Context(dims, lib=L, poll_every=8, update=lgf.UPDATE_EXP) as ctx:
+        ctx.load(U)
+        s = ctx.fix()
+        Ug = ctx.store()
+    _, it, F, th, ok, _ = oracle.fix(dims, U, oracle.opts(expo=True))
+    assert ok and s.theta < 1e-15 and abs(s.F - F) <= 1e-9 and abs(s.iter - it) <= 1
+    mu, md = oracle.unitarity(Ug)
+    assert mu <= 1e-12 and md <= 1e-12
+    assert abs(oracle.plaquette(dims, Ug) - oracle.plaquette(dims, U)) <= 1e-12
