@@ -1,24 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark of Fourier-accelerated steepest-descent Landau gauge fixing.
 
-Workload: one 32^4 SU(3) lattice (V = 2^20 sites) from the seeded generator
-(U = g exp(i eps H) g^dag(x+mu), eps for mean plaquette 0.6), alpha 0.08,
-FP64, links stored as two rows (12 reals).  A "step" is one iteration of
-Algorithm 1 (filter, g, gauge transform, Delta/F/theta), on links resident in
-HBM.  Printed as one JSON line:
+Headline workload: one 32^4 SU(3) lattice (V = 2^20 sites) from the seeded
+generator (U = g exp(i eps H) g^dag(x+mu), eps for mean plaquette 0.6),
+alpha 0.08, FP64, links stored as two rows (12 reals).  A "step" is one
+iteration of Algorithm 1 (filter, g, gauge transform, Delta/F/theta) on links
+resident in HBM.  Printed as one JSON line:
 
-  value          iterations per second (K timed iterations, no profiling)
-  roofline       the dominant kernel (fused transform + Delta + (x,y) FFT):
-                 algorithmic bytes per launch / its mean duration from HIP
-                 events on the library's stream in a second, profiled pass
-  time_to_theta  wall time of lgf_fix to theta < 1e-15 for FP64 (12- and
-                 18-real) and mixed FP32/FP64, from freshly loaded links:
-                 best of three fixes on one context (the first, which also
-                 captures the context's graphs, is reported beside it)
-  mixed_16       16^4, seeds 1-4: plain FP64 against FP32 bulk + FP64 finish
-  batch          64 lattices of three shapes in one lgf_batch (mixed), against
-                 the same lattices fixed one by one in single contexts
-  cpu_baseline   the FP64 oracle on this host's cores, a bounded sample
+  value            iterations per second (K timed iterations, no profiling)
+  roofline         the dominant kernel (fused transform + Delta + (x,y) FFT):
+                   algorithmic bytes per launch / its mean duration from HIP
+                   events on the library's stream, in a second, profiled pass
+  per_precision    32^4 iteration rate, kernel times and roofline fractions in
+                   FP64 and FP32, 12- and 18-real links
+  time_to_theta    32^4, seeds 1-4: wall time of lgf_fix to theta < 1e-15 from
+                   freshly loaded links (Algorithm 1's first measurement
+                   included) for FP64 and mixed FP32/FP64, 12- and 18-real
+  small_8          8^4: iteration rate and time to theta, F against the oracle
+  mixed_16         16^4, seeds 1-4: plain FP64 against FP32 bulk + FP64 finish
+  batch            64 lattices of three shapes in one lgf_batch (mixed), with
+                   its aggregate algorithmic bandwidth, against the same
+                   lattices fixed one by one in single contexts
+  learned_vs_plain 32^3x64, seeds 3000-3003: the committed learned step
+                   against the plain step
+  update_variants  16^4: iterations and time to theta for first-order and
+                   exact-exponential updates over a sweep of alpha, and plain
+                   steepest descent (no Fourier acceleration)
+  cpu_baseline     the FP64 oracle on this host's cores, a bounded sample of
+                   the headline workload; oracle_time_to_theta: full oracle
+                   runs at 8^4 and 16^4 with all cores and with one
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -33,12 +43,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+HEADLINE_DIMS = (32, 32, 32, 32)
 LEARNED_DIMS = (32, 32, 32, 64)
+MIXED16_DIMS = (16, 16, 16, 16)
+SMALL_DIMS = (8, 8, 8, 8)
 PAPER_C2070_ITERS_PER_S = 16.35    # 32^4, DP, 12-real, texture, ECC off (Table 3)
 
 
 def alg_bytes(V, s, R):
-    """Algorithmic HBM bytes: per iteration and per launch of each kernel.
+    """Algorithmic HBM bytes per iteration and per launch of each kernel.
 
     The links are G U0 G^dag(x+mu), formed where needed from the loaded links
     U0 (R reals per link) and the accumulated gauge G (kept as two rows, 12
@@ -54,6 +67,13 @@ def alg_bytes(V, s, R):
         "zt_fft_scale": V * s * 16,
         "gauge": V * s * (8 + 24),
     }
+
+
+def survey_bytes(V, s, R, with_G=False):
+    """The reference byte count of one iteration of a design that reads and
+    rewrites the links: V s (8R + 2R_g + 32), R_g = R; the FP32 phase of a
+    mixed run adds the accumulated gauge (+2R_g)."""
+    return V * s * (8 * R + (4 if with_G else 2) * R + 32)
 
 
 def source_digest():
@@ -85,9 +105,6 @@ def measured_traffic(kernel, dims, storage):
     return e.get("bytes_per_launch")
 
 
-MIXED16_DIMS = (16, 16, 16, 16)
-
-
 def batch_workload():
     """64 lattices of three shapes (24 x 8^4, 24 x 16^3 x 32, 16 x 16^4); lattice i
     has eps = 0.2 + 0.3 i / 63 and seed 1000 + i."""
@@ -95,16 +112,111 @@ def batch_workload():
     return shapes, [0.2 + 0.3 * i / 63 for i in range(64)]
 
 
-def fix_best(ctx, U, tries, torch):
-    """Best of `tries` fixes from freshly loaded links (the first also
-    captures the context's graphs)."""
+def vol(d):
+    return d[0] * d[1] * d[2] * d[3]
+
+
+# ---------------------------------------------------------------------------
+# GPU measurements
+# ---------------------------------------------------------------------------
+def fix_runs(ctx, U, tries, torch):
+    """Fixes from freshly loaded links; each time includes Algorithm 1's first
+    measurement.  Returns (best, first): the first also captures the
+    context's graphs."""
     runs = []
     for _ in range(tries):
         ctx.load(U)
-        ctx.measure()
         torch.cuda.synchronize()
-        runs.append(ctx.fix())
+        runs.append(ctx.fix(raise_on_error=False))
     return min(runs, key=lambda r: r.seconds), runs[0]
+
+
+def rate_and_kernels(L, dims, U, steps, warmup, torch, **kw):
+    """Iteration rate over `steps` plain lgf_step iterations, then a profiled
+    pass with per-kernel mean durations (HIP events)."""
+    from paper_1206_0675_amd import lgf
+    with lgf.Context(dims, lib=L, **kw) as ctx:
+        shape = dict(zip(("plane_threads", "tile_bytes"), ctx.config()))
+        ctx.load(U)
+        ctx.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    with lgf.Context(dims, lib=L, profile=1, **kw) as ctx:
+        ctx.load(U)
+        ctx.step(warmup)
+        ctx.profile_reset()
+        ctx.step(steps)
+        prof = ctx.profile()
+    return steps / dt, dt / steps, prof, shape
+
+
+def kernel_table(prof, ab):
+    out = {}
+    for name in ("transform_measure", "zt_fft_scale", "gauge", "reduce"):
+        n, ms = prof.get(name, (0, 0.0))
+        if n:
+            avg_s = ms / n / 1e3
+            k = {"launches": n, "avg_us": round(avg_s * 1e6, 2)}
+            if name in ab:
+                k["alg_bytes"] = ab[name]
+                k["gbps"] = round(ab[name] / avg_s / 1e9, 1)
+                k["frac"] = round(ab[name] / avg_s / 1e9 / HBM_PEAK_GBPS, 4)
+            out[name] = k
+    return out
+
+
+def per_precision(L, U, args, torch):
+    from paper_1206_0675_amd import lgf
+    V = vol(HEADLINE_DIMS)
+    out = {}
+    for prec, pname, s in ((lgf.FP64, "fp64", 8), (lgf.FP32, "fp32", 4)):
+        for R in (12, 18):
+            rate, t_it, prof, _ = rate_and_kernels(L, HEADLINE_DIMS, U, args.steps, args.warmup, torch,
+                                                   precision=prec, storage=R)
+            ab = alg_bytes(V, s, R)
+            sb = survey_bytes(V, s, R, with_G=(s == 4))
+            out[f"{pname}_{R}real"] = {
+                "iters_per_s": round(rate, 2), "ms_per_iter": round(t_it * 1e3, 4),
+                "iteration_alg_bytes": ab["iteration"],
+                "iteration_frac": round(ab["iteration"] / t_it / 1e9 / HBM_PEAK_GBPS, 4),
+                "survey_bytes": sb, "survey_frac": round(sb / t_it / 1e9 / HBM_PEAK_GBPS, 4),
+                "kernels": kernel_table(prof, ab)}
+            print(f"# {pname} {R}-real: {rate:.1f} iters/s", file=sys.stderr, flush=True)
+    return out
+
+
+def time_to_theta_32(L, fields, torch):
+    from paper_1206_0675_amd import lgf
+    modes = (("fp64_12real", dict(storage=12)), ("fp64_18real", dict(storage=18)),
+             ("mixed_12real", dict(storage=12, precision=lgf.MIXED)),
+             ("mixed_18real", dict(storage=18, precision=lgf.MIXED)))
+    out = {label: [] for label, _ in modes}
+    for seed, U in fields:
+        for label, kw in modes:
+            with lgf.Context(HEADLINE_DIMS, lib=L, poll_every=8, **kw) as ctx:
+                s, first = fix_runs(ctx, U, 2, torch)
+            out[label].append({"seed": seed, "seconds": round(s.seconds, 5), "first_seconds": round(first.seconds, 5),
+                               "iters": s.iter, "iters_fp32": s.iter_fp32, "F": s.F, "theta": s.theta})
+        print(f"# 32^4 seed {seed}: " + ", ".join(f"{k} {v[-1]['seconds'] * 1e3:.2f} ms" for k, v in out.items()),
+              file=sys.stderr, flush=True)
+    for label in list(out):
+        runs = out[label]
+        out[label] = {"runs": runs, "mean_seconds": round(sum(r["seconds"] for r in runs) / len(runs), 5)}
+    return out
+
+
+def small_8(L, U, torch, oracle_F):
+    from paper_1206_0675_amd import lgf
+    rate, t_it, _, _ = rate_and_kernels(L, SMALL_DIMS, U, 500, 50, torch)
+    with lgf.Context(SMALL_DIMS, lib=L, poll_every=8) as ctx:
+        s, first = fix_runs(ctx, U, 5, torch)
+    return {"dims": list(SMALL_DIMS), "iters_per_s": round(rate, 1), "ms_per_iter": round(t_it * 1e3, 4),
+            "time_to_theta_s": round(s.seconds, 6), "first_seconds": round(first.seconds, 6), "iters": s.iter,
+            "F": s.F, "F_minus_oracle": (s.F - oracle_F) if oracle_F is not None else None,
+            "note": "cache resident (2 MB of links): launch and latency bound, not an HBM roofline point"}
 
 
 def mixed_16(L, fields, torch):
@@ -115,7 +227,7 @@ def mixed_16(L, fields, torch):
         rec = {"seed": seed}
         for label, kw in (("fp64", {}), ("mixed", {"precision": lgf.MIXED})):
             with lgf.Context(MIXED16_DIMS, lib=L, storage=12, poll_every=8, **kw) as ctx:
-                s, _ = fix_best(ctx, U, 3, torch)
+                s, _ = fix_runs(ctx, U, 3, torch)
             rec[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "iters_fp32": s.iter_fp32, "F": s.F,
                           "theta": s.theta}
         rec["F_mixed_minus_fp64"] = rec["mixed"]["F"] - rec["fp64"]["F"]
@@ -143,47 +255,125 @@ def batch_run(L, shapes, Us, torch):
     single = 0.0
     for d, U in zip(shapes, Us):
         with lgf.Context(d, lib=L, precision=lgf.MIXED, storage=12, poll_every=8) as ctx:
-            s, _ = fix_best(ctx, U, 2, torch)
+            s, _ = fix_runs(ctx, U, 2, torch)
             single += s.seconds
-    sites = sum(d[0] * d[1] * d[2] * d[3] for d in shapes)
+    sites = sum(vol(d) for d in shapes)
+    # algorithmic bytes of every iteration every member made, in its precision
+    moved = sum(x.iter_fp32 * alg_bytes(vol(d), 4, 12)["iteration"] + x.iter_fp64 * alg_bytes(vol(d), 8, 12)["iteration"]
+                for d, x in zip(shapes, st))
     return {"configs": len(shapes), "sites": sites, "all_converged": ok, "seconds": round(best, 5),
             "configs_per_s": round(len(shapes) / best, 2), "iters_total": int(sum(x.iter for x in st)),
+            "alg_bytes_total": int(moved), "aggregate_alg_gbps": round(moved / best / 1e9, 1),
+            "aggregate_frac": round(moved / best / 1e9 / HBM_PEAK_GBPS, 4),
             "single_contexts_seconds": round(single, 5), "speedup_vs_single": round(single / best, 3),
             "launch_shape": {"plane_threads": cfg[0], "tile_bytes": cfg[1]}}
 
 
-def shape_sweep(L, dims, R, U, args):
-    """Force each candidate launch shape through the autotuner's cache file
-    and time it like the main measurement."""
-    import tempfile
-    import torch
+def learned_vs_plain(L, fields, blob, torch):
     from paper_1206_0675_amd import lgf
-    cache = os.path.join(tempfile.mkdtemp(), "tune.txt")
-    os.environ["LGF_TUNE_CACHE"] = cache
-    with lgf.Context(dims, lib=L, storage=R, autotune=1) as ctx:
-        print(f"# autotuner pick (threads, tile bytes): {ctx.config()}", flush=True)
-    with open(cache) as fh:
-        key = fh.read().split()[0]
-    for nth in (64, 128, 256):
-        for tb in (32, 64, 128):
-            with open(cache, "w") as fh:
-                fh.write(f"{key} {nth} {tb}\n")
-            with lgf.Context(dims, lib=L, storage=R, autotune=1) as ctx:
-                ctx.load(U)
-                ctx.step(args.warmup)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                ctx.step(args.steps)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-            with lgf.Context(dims, lib=L, storage=R, autotune=1, profile=1) as ctx:
-                ctx.load(U)
-                ctx.step(args.warmup)
-                ctx.profile_reset()
-                ctx.step(args.steps)
-                prof = ctx.profile()
-            us = {k: round(ms / n * 1e3, 1) for k, (n, ms) in prof.items() if n}
-            print(f"threads {nth} tile_bytes {tb}: {args.steps / dt:.1f} iters/s, kernel us {us}", flush=True)
+    runs = []
+    for seed, Ul in fields:
+        rec = {"seed": seed}
+        for label, kw in (("plain", {}), ("learned", {"step": lgf.STEP_LEARNED})):
+            with lgf.Context(LEARNED_DIMS, lib=L, storage=12, poll_every=8, **kw) as ctx:
+                if kw:
+                    ctx.set_model(blob)
+                s, _ = fix_runs(ctx, Ul, 2, torch)
+            rec[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "fallbacks": s.fallbacks, "F": s.F,
+                          "theta": s.theta}
+        rec["F_diff"] = abs(rec["learned"]["F"] - rec["plain"]["F"])
+        runs.append(rec)
+        print(f"# learned vs plain seed {seed}: {rec['plain']['iters']} -> {rec['learned']['iters']} iterations, "
+              f"{rec['plain']['seconds']:.4f} -> {rec['learned']['seconds']:.4f} s", file=sys.stderr, flush=True)
+    tp = sum(r["plain"]["seconds"] for r in runs)
+    tl = sum(r["learned"]["seconds"] for r in runs)
+    return {"dims": list(LEARNED_DIMS), "storage": 12, "runs": runs, "plain_seconds": round(tp, 5),
+            "learned_seconds": round(tl, 5), "speedup": round(tp / tl, 4) if tl > 0 else None}
+
+
+def update_variants(L, U, torch):
+    """16^4 seed 1: iterations and time to theta < 1e-15 over alpha, for the
+    first-order update (the paper's) and the exact exponential; and plain
+    steepest descent (no Fourier acceleration) at alpha = 0.08."""
+    from paper_1206_0675_amd import lgf
+    out = []
+    for alpha in (0.04, 0.05, 0.0625, 0.07, 0.08, 0.10, 0.12):
+        for label, upd in (("first_order", lgf.UPDATE_FIRST_ORDER), ("exp", lgf.UPDATE_EXP)):
+            with lgf.Context(MIXED16_DIMS, lib=L, storage=12, poll_every=8, alpha=alpha, update=upd,
+                             max_iter=3000) as ctx:
+                s, _ = fix_runs(ctx, U, 2, torch)
+            out.append({"alpha": alpha, "update": label, "converged": s.status == lgf.OK and s.theta < 1e-15,
+                        "iters": s.iter, "seconds": round(s.seconds, 5), "F": s.F})
+    with lgf.Context(MIXED16_DIMS, lib=L, storage=12, poll_every=64, accel=lgf.ACCEL_NONE, max_iter=20000) as ctx:
+        ctx.load(U)
+        s = ctx.fix(raise_on_error=False)
+    out.append({"alpha": 0.08, "update": "first_order", "accel": "none", "converged": s.theta < 1e-15,
+                "iters": s.iter, "seconds": round(s.seconds, 5), "F": s.F})
+    return out
+
+
+# ---------------------------------------------------------------------------
+# CPU (oracle) measurements: run before the GPU is touched
+# ---------------------------------------------------------------------------
+def omp_threads(n):
+    """Set the OpenMP thread count of the oracle's runtime (libgomp) in this
+    process; returns the previous count."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(int(n))
+    return prev
+
+
+def cpu_baseline(U, R, dims):
+    import oracle
+    o = oracle.opts(store12=(R == 12))
+    n_a, n_b = 2, 32
+    t = time.perf_counter()
+    oracle.step(dims, U, n_a, o)
+    t_a = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.step(dims, U, n_b, o)
+    t_b = time.perf_counter() - t
+    return {"value": round((n_b - n_a) / (t_b - t_a), 4), "unit": "iters/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle (plain C, OpenMP) on the same {'x'.join(map(str, dims))} lattice, "
+                      f"{R}-real: rate = {n_b - n_a} / (t({n_b} updates) - t({n_a} updates)), "
+                      f"{t_a + t_b:.1f}s of CPU work"}
+
+
+def oracle_time_to_theta(small, med):
+    import oracle
+    nproc = oracle.threads()
+    out = {"nproc": nproc}
+    try:
+        import platform
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), platform.processor())
+        out["cpu_model"] = model
+    except OSError:
+        pass
+    for label, dims, U in (("8^4", SMALL_DIMS, small), ("16^4", MIXED16_DIMS, med)):
+        t = time.perf_counter()
+        _, it, F, th, ok, _ = oracle.fix(dims, U)
+        out[label] = {"threads": nproc, "seconds": round(time.perf_counter() - t, 3), "iters": it, "F": F,
+                      "converged": ok}
+    prev = omp_threads(1)
+    try:
+        t = time.perf_counter()
+        _, it, F, th, ok, _ = oracle.fix(SMALL_DIMS, small)
+        out["8^4_1thread"] = {"threads": 1, "seconds": round(time.perf_counter() - t, 3), "iters": it, "F": F,
+                              "converged": ok}
+        t = time.perf_counter()
+        oracle.step(MIXED16_DIMS, med, 1)
+        t1 = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.step(MIXED16_DIMS, med, 4)
+        t4 = time.perf_counter() - t
+        out["16^4_1thread_ms_per_iter"] = round((t4 - t1) / 3 * 1e3, 2)
+    finally:
+        omp_threads(prev)
+    return out
 
 
 def main():
@@ -191,11 +381,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--dims", type=int, nargs=4, default=[32, 32, 32, 32])
     ap.add_argument("--storage", type=int, default=12, choices=[12, 18])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the time-to-theta runs")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline line (rate and roofline)")
     ap.add_argument("--learned-seeds", type=int, default=4,
                     help="32^3x64 fields (seeds 3000...) for the learned-vs-plain comparison (0: skip)")
     ap.add_argument("--pmc-sample", action="store_true",
@@ -205,12 +394,9 @@ def main():
     ap.add_argument("--batch-sample", action="store_true",
                     help="run only the batch of 64 (one lgf_batch fix, then the lattices one by one) and print "
                          "its JSON; for profiling")
-    ap.add_argument("--shape-sweep", action="store_true",
-                    help="time every launch shape the autotuner chooses from (threads per plane block x tile "
-                         "row bytes), one line each; no JSON")
-    ap.add_argument("--gen-workers", type=int, default=1,
-                    help="worker processes for input generation (fork + exec); leave at 1 under a profiler, "
-                         "which sets up the GPU before this program starts")
+    ap.add_argument("--gen-workers", type=int, default=min(8, os.cpu_count() or 1),
+                    help="worker processes for input generation (started before this program touches the GPU; "
+                         "use 1 under a profiler, which sets up the GPU before this program starts)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -221,34 +407,43 @@ def main():
 
     import synth
 
-    # All inputs are generated before this program touches the GPU (with
-    # --gen-workers > 1 the generator starts worker processes by fork and exec).
-    dims = tuple(args.dims)
-    V = synth.volume(dims)
+    # ---- inputs, generated before this program touches the GPU -------------
+    extras = not (args.no_extras or args.pmc_sample or args.batch_sample)
+    gw = args.gen_workers
     t = time.time()
-    U = None
-    if not args.batch_sample:
-        U = synth.random_links(dims, args.seed, workers=args.gen_workers)
-        print(f"# generated {dims} seed {args.seed} in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
-    model_path = os.path.join(ROOT, "paper_1206_0675_amd", "models", "learned_step.bin")
-    learned_fields = []
-    if not (args.pmc_sample or args.shape_sweep or args.batch_sample or args.no_extras) and args.learned_seeds > 0 and os.path.exists(model_path):
-        t = time.time()
-        learned_fields = [(seed, synth.random_links(LEARNED_DIMS, seed, workers=args.gen_workers))
-                          for seed in range(3000, 3000 + args.learned_seeds)]
-        print(f"# generated {len(learned_fields)} fields {LEARNED_DIMS} in {time.time() - t:.1f}s", file=sys.stderr,
-              flush=True)
-
-    extra_inputs = not (args.pmc_sample or args.shape_sweep or args.no_extras) or args.batch_sample
+    U = None if args.batch_sample else synth.random_links(HEADLINE_DIMS, args.seed, workers=gw)
+    seeds32 = []
+    small = med = None
     mixed16 = []
+    learned_fields = []
     batch_in = None
-    if extra_inputs:
-        t = time.time()
-        mixed16 = [] if args.batch_sample else [(seed, synth.random_links(MIXED16_DIMS, seed)) for seed in (1, 2, 3, 4)]
+    model_path = os.path.join(ROOT, "paper_1206_0675_amd", "models", "learned_step.bin")
+    if extras:
+        seeds32 = [(args.seed, U)] + [(s, synth.random_links(HEADLINE_DIMS, s, workers=gw)) for s in (2, 3, 4)]
+        small = synth.random_links(SMALL_DIMS, 1)
+        mixed16 = [(seed, synth.random_links(MIXED16_DIMS, seed, workers=gw)) for seed in (1, 2, 3, 4)]
+        med = mixed16[0][1]
+        if args.learned_seeds > 0 and os.path.exists(model_path):
+            learned_fields = [(seed, synth.random_links(LEARNED_DIMS, seed, workers=gw))
+                              for seed in range(3000, 3000 + args.learned_seeds)]
+    if extras or args.batch_sample:
         shapes, eps = batch_workload()
         batch_in = (shapes, [synth.random_links(d, 1000 + i, eps=e) for i, (d, e) in enumerate(zip(shapes, eps))])
-        print(f"# generated the 16^4 seeds and the batch of {len(shapes)} in {time.time() - t:.1f}s", file=sys.stderr,
-              flush=True)
+    print(f"# inputs generated in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+
+    # ---- CPU: the oracle on this host, before the GPU is touched ----------
+    cpu = None
+    oracle_ttt = None
+    oracle_F8 = None
+    if not args.no_cpu_baseline and not (args.pmc_sample or args.batch_sample):
+        cpu = cpu_baseline(U, args.storage, HEADLINE_DIMS)
+        print(f"# cpu baseline: {cpu['value']} iters/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
+        if extras:
+            oracle_ttt = oracle_time_to_theta(small, med)
+            oracle_F8 = oracle_ttt["8^4"]["F"]
+    elif extras:
+        import oracle
+        oracle_F8 = oracle.fix(SMALL_DIMS, small)[2]
 
     import torch
 
@@ -258,10 +453,11 @@ def main():
     torch.cuda.set_device(0)
     L = lgf.load_library()
     R = args.storage
+    V = vol(HEADLINE_DIMS)
     ab = alg_bytes(V, 8, R)
 
     if args.pmc_sample:
-        with lgf.Context(dims, lib=L, storage=R) as ctx:
+        with lgf.Context(HEADLINE_DIMS, lib=L, storage=R) as ctx:
             ctx.load(U)
             ctx.step(5)
         n = args.copy_mib * (1 << 20) // 8
@@ -271,124 +467,37 @@ def main():
         torch.cuda.synchronize()
         print(f"# pmc sample: 5 iterations, then one copy of {args.copy_mib} MiB", file=sys.stderr, flush=True)
         return
-
-    if args.shape_sweep:
-        shape_sweep(L, dims, R, U, args)
-        return
     if args.batch_sample:
         print(json.dumps(batch_run(L, batch_in[0], batch_in[1], torch)), flush=True)
         return
 
-    # ---- timed iterations (no profiling) -----------------------------------
-    with lgf.Context(dims, lib=L, storage=R) as ctx:
-        launch_shape = dict(zip(("plane_threads", "tile_bytes"), ctx.config()))
-        ctx.load(U)
-        ctx.step(args.warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.step(args.steps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-    dt = t1 - t0
-    iters_per_s = args.steps / dt
-    print(f"# {args.steps} iterations in {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
-
-    # ---- profiled pass: per-kernel durations from HIP events ----------------
-    with lgf.Context(dims, lib=L, storage=R, profile=1) as ctx:
-        ctx.load(U)
-        ctx.step(args.warmup)
-        ctx.profile_reset()
-        ctx.step(args.steps)
-        prof = ctx.profile()
-    kernels = {}
-    for name in ("transform_measure", "zt_fft_scale", "gauge", "reduce"):
-        n, ms = prof.get(name, (0, 0.0))
-        if n:
-            avg_s = ms / n / 1e3
-            k = {"launches": n, "avg_us": round(avg_s * 1e6, 2)}
-            if name in ab:
-                k["alg_bytes"] = ab[name]
-                k["gbps"] = round(ab[name] / avg_s / 1e9, 1)
-                k["frac"] = round(ab[name] / avg_s / 1e9 / HBM_PEAK_GBPS, 4)
-            kernels[name] = k
+    # ---- headline: timed iterations, then the profiled pass ---------------
+    iters_per_s, t_it, prof, launch_shape = rate_and_kernels(L, HEADLINE_DIMS, U, args.steps, args.warmup, torch,
+                                                             storage=R)
+    print(f"# {args.steps} iterations at {t_it * 1e3:.4f} ms", file=sys.stderr, flush=True)
+    kernels = kernel_table(prof, ab)
     dom = kernels["transform_measure"]
-    achieved = dom["gbps"]
-    traffic = measured_traffic("transform_measure", dims, R)
+    traffic = measured_traffic("transform_measure", HEADLINE_DIMS, R)
 
-    # ---- time to theta < 1e-15 ---------------------------------------------
-    extras = {}
-    if not args.no_extras:
-        for label, kw in (("fp64_12real", dict(storage=12)), ("fp64_18real", dict(storage=18)),
-                          ("mixed_12real", dict(storage=12, precision=lgf.MIXED)),
-                          ("mixed_18real", dict(storage=18, precision=lgf.MIXED))):
-            with lgf.Context(dims, lib=L, poll_every=8, **kw) as ctx:
-                runs = []
-                for _ in range(3):         # the first fix also captures the context's graphs
-                    ctx.load(U)
-                    ctx.measure()
-                    torch.cuda.synchronize()
-                    runs.append(ctx.fix())
-            s = min(runs, key=lambda r: r.seconds)
-            extras[label] = {"seconds": round(s.seconds, 5), "first_seconds": round(runs[0].seconds, 5),
-                             "iters": s.iter, "iters_fp32": s.iter_fp32, "F": s.F, "theta": s.theta}
-
-    # ---- learned vs plain step: time to theta < 1e-15 on 32^3 x 64 ----------
-    learned = None
-    if learned_fields:
-        with open(model_path, "rb") as fh:
-            blob = fh.read()
-        ld = LEARNED_DIMS
-        runs = []
-        for seed, Ul in learned_fields:
-            rec = {"seed": seed}
-            for label, kw in (("plain", {}), ("learned", {"step": lgf.STEP_LEARNED})):
-                with lgf.Context(ld, lib=L, storage=12, poll_every=8, **kw) as ctx:
-                    if kw:
-                        ctx.set_model(blob)
-                    tries = []
-                    for _ in range(2):     # the first fix also captures the context's graphs
-                        ctx.load(Ul)
-                        ctx.measure()
-                        torch.cuda.synchronize()
-                        tries.append(ctx.fix())
-                    s = min(tries, key=lambda r: r.seconds)
-                rec[label] = {"seconds": round(s.seconds, 5), "iters": s.iter, "fallbacks": s.fallbacks, "F": s.F,
-                              "theta": s.theta}
-            rec["F_diff"] = abs(rec["learned"]["F"] - rec["plain"]["F"])
-            runs.append(rec)
-            print(f"# learned vs plain seed {seed}: {rec['plain']['iters']} -> {rec['learned']['iters']} iterations, "
-                  f"{rec['plain']['seconds']:.4f} -> {rec['learned']['seconds']:.4f} s", file=sys.stderr, flush=True)
-        tp = sum(r["plain"]["seconds"] for r in runs)
-        tl = sum(r["learned"]["seconds"] for r in runs)
-        learned = {"dims": list(ld), "storage": 12, "runs": runs, "plain_seconds": round(tp, 5),
-                   "learned_seconds": round(tl, 5), "speedup": round(tp / tl, 4) if tl > 0 else None}
-
-    # ---- 16^4 mixed precision, and the batch of 64 ----------------------------
-    m16 = mixed_16(L, mixed16, torch) if mixed16 else None
-    batch = batch_run(L, batch_in[0], batch_in[1], torch) if batch_in else None
-    if batch:
-        print(f"# batch of {batch['configs']}: {batch['seconds']:.4f} s, {batch['configs_per_s']} configs/s, "
-              f"{batch['speedup_vs_single']}x one by one", file=sys.stderr, flush=True)
-
-    # ---- CPU baseline: the FP64 oracle on this host -------------------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        o = oracle.opts(store12=(R == 12))
-        n_a, n_b = 2, 32
-        t = time.perf_counter()
-        oracle.step(dims, U, n_a, o)
-        t_a = time.perf_counter() - t
-        t = time.perf_counter()
-        oracle.step(dims, U, n_b, o)
-        t_b = time.perf_counter() - t
-        cpu = {"value": round((n_b - n_a) / (t_b - t_a), 4), "unit": "iters/s", "cores": oracle.threads(),
-               "kind": "oracle",
-               "sample": f"FP64 oracle (plain C, OpenMP) on the same {'x'.join(map(str, dims))} lattice, "
-                         f"{R}-real: rate = {n_b - n_a} / (t({n_b} updates) - t({n_a} updates)), "
-                         f"{t_a + t_b:.1f}s of CPU work"}
+    line_extra = {}
+    if extras:
+        line_extra["per_precision"] = per_precision(L, U, args, torch)
+        line_extra["time_to_theta"] = time_to_theta_32(L, seeds32, torch)
+        line_extra["small_8"] = small_8(L, small, torch, oracle_F8)
+        line_extra["mixed_16"] = mixed_16(L, mixed16, torch)
+        line_extra["update_variants"] = update_variants(L, med, torch)
+        if learned_fields:
+            with open(model_path, "rb") as fh:
+                blob = fh.read()
+            line_extra["learned_vs_plain"] = learned_vs_plain(L, learned_fields, blob, torch)
+        b = batch_run(L, batch_in[0], batch_in[1], torch)
+        line_extra["batch"] = b
+        print(f"# batch of {b['configs']}: {b['seconds']:.4f} s, {b['configs_per_s']} configs/s, "
+              f"{b['aggregate_alg_gbps']} GB/s aggregate, {b['speedup_vs_single']}x one by one", file=sys.stderr,
+              flush=True)
 
     it_bytes = ab["iteration"]
+    sb = survey_bytes(V, 8, R)
     line = {
         "metric": "FA-SD iters/s and time to theta<1e-15 on 32^4 SU(3); HBM GB/s; learned vs plain",
         "value": round(iters_per_s, 2),
@@ -396,25 +505,26 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "ms_per_step": round(t_it * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, dims))} SU(3) FA-SD iteration, FP64, {R}-real links, alpha 0.08",
-                   "dims": list(dims), "storage": R, "seed": args.seed, "generator": "g exp(i eps H) g^dag, plaquette 0.6"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+        "config": {"workload": f"{'x'.join(map(str, HEADLINE_DIMS))} SU(3) FA-SD iteration, FP64, {R}-real links, "
+                               "alpha 0.08",
+                   "dims": list(HEADLINE_DIMS), "storage": R, "seed": args.seed,
+                   "generator": "g exp(i eps H) g^dag, plaquette 0.6"},
+        "roofline": {"bound": "hbm", "achieved": dom["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": dom["frac"], "traffic": traffic,
                      "kernel": "transform_measure", "alg_bytes_per_launch": ab["transform_measure"]},
-        "iteration_alg_gbps": round(it_bytes * iters_per_s / 1e9, 1),
-        "iteration_frac": round(it_bytes * iters_per_s / 1e9 / HBM_PEAK_GBPS, 4),
+        "iteration_alg_gbps": round(it_bytes / t_it / 1e9, 1),
+        "iteration_frac": round(it_bytes / t_it / 1e9 / HBM_PEAK_GBPS, 4),
+        "iteration_survey_frac": round(sb / t_it / 1e9 / HBM_PEAK_GBPS, 4),
         "kernels": kernels,
-        "time_to_theta": extras,
-        "learned_vs_plain": learned,
-        "mixed_16": m16,
-        "batch": batch,
+        **line_extra,
         "cpu_baseline": cpu,
+        "oracle_time_to_theta": oracle_ttt,
         "context": {"paper_c2070_iters_per_s": PAPER_C2070_ITERS_PER_S,
                     "device": torch.cuda.get_device_name(0), "source_digest": source_digest(),
                     "launch_shape": launch_shape},

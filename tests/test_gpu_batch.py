@@ -85,3 +85,23 @@ def test_batch_fp64_bitwise_equals_single(L):
                 s = c.fix()
                 assert s.iter == st[i].iter and s.F == st[i].F
                 assert np.array_equal(c.store(), b.store(i))
+
+
+def test_fix_batch_one_call_matches_oracle(L, oracle_lib):
+    """lgf_fix_batch (create, load, fix, store and destroy in one C call) on
+    host arrays of three shapes, mixed precision: every member converges, its
+    links lie on the gauge orbit of its input and its F is the oracle's to
+    1e-9."""
+    dims = [(8, 8, 8, 8), (16, 8, 8, 16), (8, 16, 4, 8)]
+    Us = [synth.random_links(d, 60 + i) for i, d in enumerate(dims)]
+    print("\n[gpu] lgf_fix_batch, 3 shapes, mixed", flush=True)
+    outs, sts, rc = lgf.fix_batch(Us, lib=L, precision=lgf.MIXED, storage=12, poll_every=4)
+    assert rc == lgf.OK
+    for d, U, out, st in zip(dims, Us, outs, sts):
+        assert st.status == lgf.OK and st.theta < 1e-15 and st.iter_fp32 > 0 and st.iter_fp64 > 0
+        _, it, F, _, ok, _ = oracle.fix(d, U)
+        assert ok and abs(st.F - F) <= 1e-9 and abs(st.iter - it) <= 2
+        assert abs(oracle.plaquette(d, out) - oracle.plaquette(d, U)) <= 1e-12
+        mu, md = oracle.unitarity(out)
+        assert mu <= 1e-12 and md <= 1e-12
+        assert abs(oracle.measure(d, out)[0] - st.F) <= 1e-12
