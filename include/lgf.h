@@ -75,8 +75,10 @@ extern "C" {
 /* step kind */
 #define LGF_STEP_PLAIN 0    /* eq. gx: (alpha/2) p2max/p2                                  */
 #define LGF_STEP_LEARNED 1  /* s_b (alpha/2) p2max/p2 with per-band factors s_b from the
-                               network set by lgf_set_model; an update that does not
-                               increase F is replaced by the plain one (FP64 only)          */
+                               network set by lgf_set_model, applied to the band powers of
+                               the previous update's spectrum (s = 1 for the first update
+                               after a load); an update that does not increase F is
+                               replaced by the plain one (FP64 only)                       */
 
 /* how g(x) is formed from the filtered Delta (eq. gx) */
 #define LGF_UPDATE_FIRST_ORDER 0  /* g = reunit(1 + (alpha/2) dtilde): first order in alpha, then
@@ -254,8 +256,10 @@ size_t lgf_model_bytes(void);
  * a blob of the wrong size or header. */
 int32_t lgf_set_model(lgf_ctx ctx, const void *blob, size_t bytes);
 
-/* Features x and factors s (all 1 without a model) the learned step would
- * use at the current links of an FP64 context; the links are not changed. */
+/* Features x of the band powers of the current links' spectrum, and the
+ * network's factors s for them (all 1 without a model): the factors a learned
+ * update from these links leaves for the update after it.  The links and the
+ * factors the next update uses are not changed. */
 int32_t lgf_learned_factors(lgf_ctx ctx, double features[16], double s[16]);
 
 /* Training data at the current links of an FP64 context: the band features

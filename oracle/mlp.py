@@ -17,8 +17,12 @@ factors:
 
 Weights are stored in bfloat16 (round to nearest even from float32) and
 biases in float32; this reference evaluates the network in float64 on those
-exact values.  An update with factors s is accepted only if it increases F;
-otherwise the plain update (s = 1) is taken.
+exact values.  The factors an update applies come from the network on the band powers
+of the previous update's spectrum (s = 1 for the first update after a load):
+the spectrum of the current links is only known once the update's own
+(z, t) pass has run, so the factors lag it by one update.  An update with
+factors s is accepted only if it increases F; otherwise the plain update
+(s = 1) is taken.
 
 Training targets: the one factor s, common to all bands, that minimises theta
 after one update (theta is what the stop test reads, and it stays resolvable
@@ -150,17 +154,36 @@ def update_with(dims, U, s, alpha=0.08):
     return lgfo.transform(dims, U, g)
 
 
-def learned_step(dims, U, p: dict, alpha=0.08):
-    """(U', accepted, s, x): factors from the network; plain step if F drops."""
+def learned_step(dims, U, p: dict, s, alpha=0.08):
+    """One learned update with the factors s it was handed (s = None: the
+    plain factors).  Returns (U', accepted, s_next, x): the candidate from s
+    is kept iff it raises F, else the plain update is taken; x are the
+    features of the band powers of U's spectrum and s_next the network's
+    factors for them, which the next update uses (the factors lag the
+    spectrum by one update)."""
     V = int(np.prod(dims))
     F0, _, delta = lgfo.measure(dims, U)
     P, cnt = lgfo.band_powers(dims, delta)
     x = features(P, cnt, V)
-    s = factors(p, x)
+    s_next = factors(p, x)
     U1 = update_with(dims, U, s, alpha)
     if lgfo.measure(dims, U1)[0] > F0:
-        return U1, True, s, x
-    return update_with(dims, U, None, alpha), False, s, x
+        return U1, True, s_next, x
+    return update_with(dims, U, None, alpha), False, s_next, x
+
+
+def learned_run(dims, U, p: dict, n=None, theta_stop=1e-15, max_iter=100000, alpha=0.08):
+    """n learned updates from freshly loaded links (s = 1 for the first), or,
+    with n = None, updates until theta < theta_stop.  Returns (U, iterations,
+    fallbacks, F, theta)."""
+    s, it, fb = None, 0, 0
+    while True:
+        F, th, _ = lgfo.measure(dims, U)
+        if (n is not None and it >= n) or (n is None and (th < theta_stop or it >= max_iter)):
+            return U, it, fb, F, th
+        U, ok, s, _ = learned_step(dims, U, p, s, alpha)
+        fb += 0 if ok else 1
+        it += 1
 
 
 def linesearch(dims, U, alpha=0.08, iters=20):

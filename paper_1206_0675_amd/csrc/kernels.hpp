@@ -101,6 +101,8 @@ struct DevState {
                            // the host has run the plain update
     double trial_F, trial_theta;   // learned step: F, theta of the candidate links
     int64_t fallbacks;     // learned step: updates that fell back to the plain factors
+    int32_t dsel;          // learned step: Delta of the current links is in the Delta buffer dsel
+    int32_t pad0;
 };
 
 // Plane handled by block b.  Blocks are dealt to the 8 XCDs round robin
@@ -541,6 +543,10 @@ __device__ __forceinline__ void measure_plane_once(const Geo& geo, int q, const 
 // n = mode_of_position(L_mu, pos).
 // accel = 1: factor c0 / p^2 with c0 = (alpha/2) p2max / V, zero at p = 0;
 // accel = 0 (plain steepest descent): the constant c0 = (alpha/2) / V.
+// Learned step (a10): band of every spectrum position of the tile being
+// transformed (btab: one int8 per position of a tile, in the layout of one
+// field of a Delta chunk, -1 for p = 0), and the per-band factors s_b that
+// multiply the factor.
 struct SpectralScale {
     const double* tx;
     const double* ty;
@@ -548,6 +554,8 @@ struct SpectralScale {
     const double* tt;
     double c0;
     int accel;
+    const int8_t* btab = nullptr;   // this tile's band table, or NULL (plain step)
+    const double* sb = nullptr;     // 16 factors
     __device__ __forceinline__ double factor(double p2) const
     {
         return accel ? (p2 > 0.0 ? c0 / p2 : 0.0) : c0;
@@ -557,14 +565,17 @@ struct SpectralScale {
 __device__ __forceinline__ SpectralScale make_scale(const Geo& geo, const double* ptab, double c0, int accel)
 {
     return SpectralScale{ptab, ptab + geo.L[0], ptab + geo.L[0] + geo.L[1], ptab + geo.L[0] + geo.L[1] + geo.L[2],
-                         c0, accel};
+                         c0, accel, nullptr, nullptr};
 }
 
 // The t axis of the (z, t) block: forward DFT, spectral factor and inverse
 // DFT of each contiguous group in registers, between the two A passes.
-template <typename T, int LT>
+// LEARNED: the factor is multiplied by s_b of the mode's band, and the
+// thread adds |Dhat(p)|^2 (before scaling) to bands[b] (a7's band powers for
+// the next update's factors).
+template <typename T, int LT, bool LEARNED = false>
 __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth,
-                          const SpectralScale& sc, const Geo& geo, int logWb, int pxy0)
+                          const SpectralScale& sc, const Geo& geo, int logWb, int pxy0, double* bands = nullptr)
 {
     constexpr int R1 = fft_r1(LT), R2 = fft_r2(LT);
     constexpr int G = R2 > 1 ? R2 : R1;            // values per register group
@@ -583,7 +594,20 @@ __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ t
         for (int k = 0; k < G; ++k) u[k] = p[k * es];
         dft<T, G, false>(u);
 #pragma unroll
-        for (int k = 0; k < G; ++k) u[k] = scale(u[k], (T)sc.factor(base + sc.tt[j1 * R2 + k]));
+        for (int k = 0; k < G; ++k) {
+            double f = sc.factor(base + sc.tt[j1 * R2 + k]);
+            if constexpr (LEARNED) {
+                // chunk position of this mode: (t position * Lz + z) * W + plane offset in the tile
+                const int b = sc.btab[(((j1 * R2 + k) << geo.logL[2]) + zp) * geo.W + (pxy & (geo.W - 1))];
+                if (b >= 0) {
+                    const double pw = (double)u[k].x * u[k].x + (double)u[k].y * u[k].y;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) bands[q] += (q == b) ? pw : 0.0;
+                    f *= sc.sb[b];
+                }
+            }
+            u[k] = scale(u[k], (T)f);
+        }
         dft<T, G, true>(u);
 #pragma unroll
         for (int k = 0; k < G; ++k) p[k * es] = u[k];
@@ -596,38 +620,40 @@ __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ t
 // split into parts of Wb = 2^logWb positions, and part h of field c is
 // transformed here (Wb = W: the whole tile).  The tile in global memory has
 // rows of W positions per (z, t) point; the LDS block has rows of Wb.  The
-// first z pass reads its lines straight from global memory and the last one
-// writes them back there.
-template <typename T, int LMAX>
-__device__ void zt_block(const Geo& geo, int j, int c, int h, int logWb, C2<T>* __restrict__ D,
-                         const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt, const SpectralScale& sc,
-                         C2<T>* buf)
+// first z pass reads its lines straight from Din and the last one writes
+// them to Dout (the same buffer for the plain step).
+template <typename T, int LMAX, bool LEARNED = false>
+__device__ void zt_block(const Geo& geo, int j, int c, int h, int logWb, const C2<T>* __restrict__ Din,
+                         C2<T>* __restrict__ Dout, const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt,
+                         const SpectralScale& sc, C2<T>* buf, double* bands = nullptr)
 {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int W = geo.W, Wb = 1 << logWb;
-    C2<T>* src = D + (int64_t)(j * 4 + c) * geo.DS + h * Wb;
+    const int64_t off = (int64_t)(j * 4 + c) * geo.DS + h * Wb;
     const int Lz = geo.L[2];
     const Lines zg{logWb, geo.logL[3], 1, Lz * W, W};
     const Lines zl{logWb, geo.logL[3], 1, Lz * Wb, Wb};
     const Lines tl{geo.logL[2] + logWb, 0, 1, 0, Lz * Wb};
     const int pxy0 = j * W + h * Wb;
-    fft_fwd<T, LMAX>(src, zg, buf, Lz, zl, twz, tid, nth);
+    fft_fwd<T, LMAX>(Din + off, zg, buf, Lz, zl, twz, tid, nth);
     switch (geo.L[3]) {
-    case 4: zt_t_axis<T, 4>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
-    case 8: zt_t_axis<T, 8>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
-    case 16: zt_t_axis<T, 16>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
-    case 32: zt_t_axis<T, 32>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
-    case 64: zt_t_axis<T, 64>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
-    default: if constexpr (LMAX >= 128) zt_t_axis<T, 128>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0); break;
+    case 4: zt_t_axis<T, 4, LEARNED>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0, bands); break;
+    case 8: zt_t_axis<T, 8, LEARNED>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0, bands); break;
+    case 16: zt_t_axis<T, 16, LEARNED>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0, bands); break;
+    case 32: zt_t_axis<T, 32, LEARNED>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0, bands); break;
+    case 64: zt_t_axis<T, 64, LEARNED>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0, bands); break;
+    default:
+        if constexpr (LMAX >= 128) zt_t_axis<T, 128, LEARNED>(buf, tl, twt, tid, nth, sc, geo, logWb, pxy0, bands);
+        break;
     }
-    fft_inv<T, LMAX>(buf, zl, src, zg, Lz, twz, tid, nth);
+    fft_inv<T, LMAX>(buf, zl, Dout + off, zg, Lz, twz, tid, nth);
 }
 
 template <typename T, int LMAX>
 __device__ void zt_block(const Geo& geo, int j, int c, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
                          const C2<T>* __restrict__ twt, const SpectralScale& sc, C2<T>* buf)
 {
-    zt_block<T, LMAX>(geo, j, c, 0, geo.logW, D, twz, twt, sc, buf);
+    zt_block<T, LMAX>(geo, j, c, 0, geo.logW, D, D, twz, twt, sc, buf);
 }
 
 // ---------------------------------------------------------------------------
@@ -848,15 +874,20 @@ __device__ __forceinline__ void reduce_state(const double* __restrict__ partial,
 // one k_gauge has just formed (G[1 - cur]).
 // ONCE: the link-once plane function (x extent <= 64), else the one that
 // forms every link at both of its sites.
+// D1 (learned step only, else NULL): a second Delta buffer; Delta of the
+// current links is in D if st->dsel = 0, else in D1, and the links of the
+// gauge just formed (next = 1) write the other one, so a rejected candidate
+// leaves the current Delta in place.
 template <typename T, int NE, int LMAX, bool ONCE>
 __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restrict__ Uref, const C2<T>* G0,
-                                                 const C2<T>* G1, int next, C2<T>* __restrict__ D,
+                                                 const C2<T>* G1, int next, C2<T>* D0, C2<T>* D1,
                                                  double* __restrict__ partial, const C2<T>* __restrict__ twx,
                                                  const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     const C2<T>* G = (st->cur ^ next) ? G1 : G0;
+    C2<T>* D = (D1 && ((st->dsel ^ next) & 1)) ? D1 : D0;
     const int q = plane_of_block(blockIdx.x, geo);
     C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x);
     if constexpr (ONCE) measure_plane_once<T, NE, LMAX>(geo, q, Uref, G, D, partial, twx, twy, lds_raw, buf);
@@ -893,7 +924,7 @@ __global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, cons
     HIP_DYNAMIC_SHARED(double, lds_raw)
     int h, chunk;
     zt_part_of_block(blockIdx.x, (geo.NP >> geo.logW) * 4, geo.logW - logWb, h, chunk);
-    zt_block<T, LMAX>(geo, chunk >> 2, chunk & 3, h, logWb, D, twz, twt, make_scale(geo, ptab, c0, accel),
+    zt_block<T, LMAX>(geo, chunk >> 2, chunk & 3, h, logWb, D, D, twz, twt, make_scale(geo, ptab, c0, accel),
                       reinterpret_cast<C2<T>*>(lds_raw));
 }
 
@@ -1094,94 +1125,61 @@ __global__ void kb_switch_done(const BatchCfg<double>* __restrict__ c64, int ncf
 // ===========================================================================
 // a10: learned spectral step
 // ===========================================================================
-// Band of a mode from its p^2: 16 bands log-spaced between the smallest
-// nonzero p^2 of the lattice (pmin) and p2max; -1 for the zero mode.
+// The factor (alpha/2) p2max / (p^2 V) of mode p is multiplied by s_b of the
+// mode's band b: 16 bands log-spaced between the smallest nonzero p^2 of the
+// lattice and p2max (the zero mode has none).  The factors used by an update
+// come from the network applied to the band powers of the previous update's
+// spectrum (s = 1 for the first update after a load), so each update makes a
+// single (z, t) pass that applies the factors and adds up the band powers of
+// the spectrum it transforms, and the network runs in the one-block
+// reduction that follows the update.
 
-// Forward (z, t) transform of one tile from Din into Dspec (Din keeps Delta)
-// and this block's band sums of sum_c |Dhat_c(p)|^2: per-thread accumulation,
-// then a fixed-order tree in LDS (the launch gives at least 16 * blockDim
-// doubles of LDS).  btab: the band of every spectrum position, laid out like
-// one field of a Delta chunk (-1 for the zero mode).
-template <typename T, int LMAX>
-__global__ void __launch_bounds__(512) k_zt_fwd_bands(Geo geo, const C2<T>* __restrict__ Din, C2<T>* __restrict__ Dspec,
-                                                      const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt,
-                                                      const int8_t* __restrict__ btab, double* __restrict__ band_partial,
-                                                      const DevState* __restrict__ st)
+// Wavefront-then-block sum of 16 per-thread values in a fixed order; thread 0
+// writes them to out.  wred: 16 * (blockDim / 64) doubles of LDS.
+__device__ __forceinline__ void block_sum16(double* v, double* wred, double* __restrict__ out)
 {
-    if (st->done) return;
-    HIP_DYNAMIC_SHARED(double, lds_raw)
-    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
-    const int W = geo.W, NQ = geo.NQ, n = NQ * W, Lz = geo.L[2];
-    const C2<T>* src = Din + (int64_t)(j * 4 + c) * geo.DS;
-    C2<T>* dst = Dspec + (int64_t)(j * 4 + c) * geo.DS;
-    const int8_t* bt = btab + (int64_t)j * n;
-    gather_to_lds<8>(buf, src, n, tid, nth, ident_index, ident_index);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] += __shfl(v[q], lane ^ m);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) wred[q * nw + wave] = v[q];
     __syncthreads();
-    const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
-    const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
-    fft_fwd<T, LMAX>(buf, Lz, zl, twz, tid, nth);
-    fft_fwd<T, LMAX>(buf, geo.L[3], tl, twt, tid, nth);
-    double acc[16];
-#pragma unroll
-    for (int b = 0; b < 16; ++b) acc[b] = 0.0;
-    for (int i = tid; i < n; i += nth) {
-        const C2<T> v = buf[i];
-        dst[i] = v;
-        const int b = bt[i];
-        const double pw = (double)v.x * v.x + (double)v.y * v.y;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) acc[k] += (k == b) ? pw : 0.0;
+    if (tid < 16) {
+        double a = 0.0;
+        for (int w = 0; w < nw; ++w) a += wred[tid * nw + w];
+        out[tid] = a;
     }
-    __syncthreads();
-    double* red = lds_raw;   // reuse: 16 * nth doubles fit in the tile buffer
-#pragma unroll
-    for (int k = 0; k < 16; ++k) red[k * nth + tid] = acc[k];
-    __syncthreads();
-    for (int h = nth >> 1; h > 0; h >>= 1) {
-        if (tid < h)
-#pragma unroll
-            for (int k = 0; k < 16; ++k) red[k * nth + tid] += red[k * nth + tid + h];
-        __syncthreads();
-    }
-    if (tid < 16) band_partial[(int64_t)blockIdx.x * 16 + tid] = red[tid * nth];
 }
 
-// Scale by s_b * (alpha/2) p2max / (p^2 V) and inverse (z, t) transform of
-// one tile, from Dspec (the full 4D spectrum, kept) into Dout.
+// One block per (tile, field, part) as k_zt: forward (z, t) FFT of the
+// current Delta (buffer st->dsel of D0, D1), band powers of the spectrum into
+// band_partial[block][16], factors s_b (alpha/2) p2max/(p^2 V), inverse
+// (z, t) FFT into Dout.  The current Delta is left as it is.
 template <typename T, int LMAX>
-__global__ void __launch_bounds__(512) k_zt_inv_scaled(Geo geo, const C2<T>* __restrict__ Dspec, C2<T>* __restrict__ Dout,
-                                                       const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt,
-                                                       const double* __restrict__ ptab, double c0, int accel,
-                                                       const int8_t* __restrict__ btab, const double* __restrict__ s,
-                                                       const DevState* __restrict__ st)
+__global__ void __launch_bounds__(512) k_zt_learned(Geo geo, const C2<T>* D0, const C2<T>* D1, C2<T>* __restrict__ Dout,
+                                                    const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt,
+                                                    const double* __restrict__ ptab, double c0, int accel, int logWb,
+                                                    const int8_t* __restrict__ btab, const double* __restrict__ sb,
+                                                    double* __restrict__ band_partial, const DevState* __restrict__ st)
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
-    C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw);
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int j = blockIdx.x >> 2, c = blockIdx.x & 3;
-    const int W = geo.W, NQ = geo.NQ, n = NQ * W, Lz = geo.L[2];
-    const C2<T>* src = Dspec + (int64_t)(j * 4 + c) * geo.DS;
-    const int8_t* bt = btab + (int64_t)j * n;
-    const SpectralScale sc = make_scale(geo, ptab, c0, accel);
-    for (int i = tid; i < n; i += nth) {
-        const int w = i & (W - 1), qq = i >> geo.logW;
-        const int pxy = j * W + w;
-        const double base = sc.tx[pxy & (geo.L[0] - 1)] + sc.ty[pxy >> geo.logL[0]] + sc.tz[qq & (Lz - 1)];
-        const double p2 = base + sc.tt[qq >> geo.logL[2]];
-        const int b = bt[i];
-        const double sb = b < 0 ? 1.0 : s[b];
-        buf[i] = scale(src[i], (T)(sb * sc.factor(p2)));
-    }
-    __syncthreads();
-    const Lines zl{geo.logW, geo.logL[3], 1, Lz * W, W};
-    const Lines tl{geo.logL[2] + geo.logW, 0, 1, 0, Lz * W};
-    fft_inv<T, LMAX>(buf, geo.L[3], tl, twt, tid, nth);
-    fft_inv<T, LMAX>(buf, Lz, zl, twz, tid, nth);
-    C2<T>* dst = Dout + (int64_t)(j * 4 + c) * geo.DS;
-    for (int i = tid; i < n; i += nth) dst[i] = buf[i];
+    __shared__ double wred[16 * 8];
+    int h, chunk;
+    zt_part_of_block(blockIdx.x, (geo.NP >> geo.logW) * 4, geo.logW - logWb, h, chunk);
+    const int j = chunk >> 2;
+    SpectralScale sc = make_scale(geo, ptab, c0, accel);
+    sc.btab = btab + (int64_t)j * geo.NQ * geo.W;
+    sc.sb = sb;
+    double bands[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) bands[q] = 0.0;
+    zt_block<T, LMAX, true>(geo, j, chunk & 3, h, logWb, (st->dsel & 1) ? D1 : D0, Dout, twz, twt, sc,
+                            reinterpret_cast<C2<T>*>(lds_raw), bands);
+    block_sum16(bands, wred, band_partial + (int64_t)blockIdx.x * 16);
 }
 
 __device__ __forceinline__ float bf16_to_float(uint16_t b)
@@ -1203,33 +1201,46 @@ struct MlpDev {
     const float* b3;
 };
 
-// Band powers -> features -> factors s_b = exp(clip(y_b, -2.3, 2.3)).  One
-// block of 256 threads: the per-block band sums are added in 16 interleaved
-// slices and a fixed-order tree (deterministic), then the network runs on the
-// first 64 threads.  Empty bands (count 0) get feature 0.
-template <int UNUSED = 0>
-__global__ void __launch_bounds__(256) k_bands_mlp(const double* __restrict__ band_partial, int nblk,
-                                                   const double* __restrict__ count16, int64_t V, MlpDev net,
-                                                   double* __restrict__ s_out, double* __restrict__ x_out,
-                                                   const DevState* __restrict__ st)
+// Band powers -> features -> factors s_b = exp(clip(y_b, -2.3, 2.3)), by one
+// block of 256 threads.  The per-block band sums are added in a fixed order:
+// thread t adds rows t, t + 256, ... (16 bands each), then a tree over the
+// threads.  Empty bands (count 0) get feature 0.  The network runs with its
+// weights staged in LDS as floats, each layer's dot products split over all
+// threads and their parts added in a fixed order.  Without a network (net.W1
+// NULL) s = 1.  Ends with a barrier.
+__device__ __forceinline__ void band_factors(const double* __restrict__ band_partial, int nblk,
+                                             const double* __restrict__ count16, int64_t V, const MlpDev& net,
+                                             double* __restrict__ s_out, double* __restrict__ x_out)
 {
-    if (st->done) return;
-    __shared__ double psum[16 * 16];
+    __shared__ double red[16 * 256];
+    __shared__ float w1[16 * 64], w2[64 * 64], w3[64 * 16], part[256];
     __shared__ float x[16], h1[64], h2[64];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x;        // blockDim.x == 256
     {
-        const int band = tid & 15, slice = tid >> 4;
-        double p = 0.0;
-        for (int i = slice; i < nblk; i += 16) p += band_partial[(int64_t)i * 16 + band];
-        psum[slice * 16 + band] = p;
+        double acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+        for (int r = tid; r < nblk; r += 256) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] += band_partial[(int64_t)r * 16 + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) red[q * 256 + tid] = acc[q];
+    }
+    if (net.W1) {
+        for (int i = tid; i < 16 * 64; i += 256) w1[i] = bf16_to_float(net.W1[i]);
+        for (int i = tid; i < 64 * 64; i += 256) w2[i] = bf16_to_float(net.W2[i]);
+        for (int i = tid; i < 64 * 16; i += 256) w3[i] = bf16_to_float(net.W3[i]);
     }
     __syncthreads();
-    for (int h = 8; h > 0; h >>= 1) {
-        if ((tid >> 4) < h) psum[tid] += psum[tid + 16 * h];
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) red[q * 256 + tid] += red[q * 256 + tid + h];
         __syncthreads();
     }
     if (tid < 16) {
-        const double p = psum[tid];
+        const double p = red[tid * 256];
         double f = 0.0;
         if (count16[tid] > 0.0) {
             const double pv = p / count16[tid] / (double)V;
@@ -1239,59 +1250,113 @@ __global__ void __launch_bounds__(256) k_bands_mlp(const double* __restrict__ ba
         if (x_out) x_out[tid] = f;
     }
     __syncthreads();
-    if (!net.W1) {                     // features only: the plain factors
+    if (!net.W1) {
         if (tid < 16) s_out[tid] = 1.0;
+        __syncthreads();
         return;
     }
     if (tid < 64) {
         float a = net.b1[tid];
-        for (int i = 0; i < 16; ++i) a = fmaf(x[i], bf16_to_float(net.W1[i * 64 + tid]), a);
+        for (int i = 0; i < 16; ++i) a = fmaf(x[i], w1[i * 64 + tid], a);
         h1[tid] = a > 0.f ? a : 0.f;
     }
     __syncthreads();
+    {   // layer 2: output o, inputs [16 k, 16 k + 16) for k = tid >> 6
+        const int o = tid & 63, k = tid >> 6;
+        float a = 0.f;
+        for (int i = 16 * k; i < 16 * k + 16; ++i) a = fmaf(h1[i], w2[i * 64 + o], a);
+        part[tid] = a;
+    }
+    __syncthreads();
     if (tid < 64) {
-        float a = net.b2[tid];
-        for (int i = 0; i < 64; ++i) a = fmaf(h1[i], bf16_to_float(net.W2[i * 64 + tid]), a);
+        const float a = ((net.b2[tid] + part[tid]) + part[64 + tid]) + (part[128 + tid] + part[192 + tid]);
         h2[tid] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    {   // layer 3: output o, inputs [4 k, 4 k + 4) for k = tid >> 4
+        const int o = tid & 15, k = tid >> 4;
+        float a = 0.f;
+        for (int i = 4 * k; i < 4 * k + 4; ++i) a = fmaf(h2[i], w3[i * 16 + o], a);
+        part[tid] = a;
     }
     __syncthreads();
     if (tid < 16) {
         float a = net.b3[tid];
-        for (int i = 0; i < 64; ++i) a = fmaf(h2[i], bf16_to_float(net.W3[i * 16 + tid]), a);
+        for (int k = 0; k < 16; ++k) a += part[16 * k + tid];
         const double y = fmin(fmax((double)a, -2.3), 2.3);
         s_out[tid] = exp(y);
     }
+    __syncthreads();
 }
 
-// Learned step, decided on the device: the candidate links (F, theta from
-// the trial reduction) become current if they raise F.  Otherwise `fallback`
-// is raised and `done` held at 1, so the rest of a queued chunk does nothing,
-// until the host has run the plain update (k_fallback_begin first).
+// Features and factors of the band powers in band_partial (lgf_learned_factors).
 template <int UNUSED = 0>
-__global__ void k_decide_trial(DevState* st, double* trace)
+__global__ void __launch_bounds__(256) k_bands_mlp(const double* __restrict__ band_partial, int nblk,
+                                                   const double* __restrict__ count16, int64_t V, MlpDev net,
+                                                   double* __restrict__ s_out, double* __restrict__ x_out)
+{
+    band_factors(band_partial, nblk, count16, V, net, s_out, x_out);
+}
+
+// The reduction that ends a learned update, one block.
+//   mode 1 (candidate): F and theta of the candidate links; the network's
+//     factors for the next update from this update's band powers into s_next;
+//     the candidate is committed (the gauge and Delta buffers flip, s_cur =
+//     s_next) iff it raised F, else `fallback` is raised and `done` held at 1
+//     until the host has run the plain update.
+//   mode 2 (after a fallback's plain update): committed, s_cur = s_next.
+//   mode 3 (trial of the line search): F and theta recorded as trial values.
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(256) k_reduce_learned(const double* __restrict__ partial, int nq, int64_t V,
+                                                        DevState* st, double* __restrict__ trace, int mode,
+                                                        const double* __restrict__ band_partial, int nblk,
+                                                        const double* __restrict__ count16, MlpDev net,
+                                                        double* __restrict__ s_cur, double* __restrict__ s_next)
 {
     if (st->done) return;
-    if (st->trial_F > st->F) {
-        st->iter += 1;
-        st->cur ^= 1;
-        st->needs_measure = 0;
-        st->F = st->trial_F;
-        st->theta = st->trial_theta;
-        if (trace) {
-            trace[0] = st->F;
-            trace[1] = st->theta;
-        }
-        const double th = st->theta;
-        if (!(th == th) || th > 1e300) {
-            st->nonfinite = 1;
-            st->done = 1;
-        } else if (th < st->theta_stop || st->iter >= st->max_iter) {
-            st->done = 1;
-        }
-    } else {
-        st->fallback = 1;
-        st->done = 1;
+    __shared__ double red[2 * 256];
+    __shared__ int commit;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    double a = 0.0, b = 0.0;
+    for (int i = tid; i < nq; i += nth) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
     }
+    double fs, ts;
+    block_sum2(a, b, red, tid, nth, &fs, &ts);
+    const double F = fs / (12.0 * (double)V), th = ts / (3.0 * (double)V);
+    if (mode == 1) band_factors(band_partial, nblk, count16, V, net, s_next, nullptr);
+    if (tid == 0) {
+        commit = 0;
+        if (mode == 3) {
+            st->trial_F = F;
+            st->trial_theta = th;
+        } else if (mode == 2 || F > st->F) {
+            commit = 1;
+            st->iter += 1;
+            st->cur ^= 1;
+            st->dsel ^= 1;
+            st->F = F;
+            st->theta = th;
+            if (trace) {
+                trace[0] = F;
+                trace[1] = th;
+            }
+            if (!(th == th) || th > 1e300) {
+                st->nonfinite = 1;
+                st->done = 1;
+            } else if (th < st->theta_stop || st->iter >= st->max_iter) {
+                st->done = 1;
+            }
+        } else {
+            st->trial_F = F;
+            st->trial_theta = th;
+            st->fallback = 1;
+            st->done = 1;
+        }
+    }
+    __syncthreads();
+    if (commit && tid < 16) s_cur[tid] = s_next[tid];
 }
 
 template <int UNUSED = 0>
@@ -1302,6 +1367,13 @@ __global__ void k_fallback_begin(DevState* st)
         st->done = 0;
         st->fallbacks += 1;
     }
+}
+
+// s = 1 (the first update after a load uses the plain factors).
+template <int UNUSED = 0>
+__global__ void k_fill16(double* __restrict__ s, double v)
+{
+    if (threadIdx.x < 16) s[threadIdx.x] = v;
 }
 
 }  // namespace lgf

@@ -21,6 +21,7 @@
 #include <functional>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "runtime.hpp"
@@ -50,6 +51,8 @@ __global__ void k_state_init(DevState* st, int phase)
     st->trial_F = 0.0;
     st->trial_theta = 0.0;
     st->fallbacks = 0;
+    st->dsel = 0;
+    st->pad0 = 0;
 }
 
 __global__ void k_state_phase(DevState* st, int phase)
@@ -97,14 +100,17 @@ struct lgf_context : Runner {
     bool has_model = false;
     uint16_t* mw = nullptr;       // bf16 W1 | W2 | W3
     float* mb = nullptr;          // b1 | b2 | b3
-    double* band_partial = nullptr;
+    double* band_partial = nullptr;   // band powers per (z, t) block of the last learned pass
     double* counts16 = nullptr;
-    double* s_dev = nullptr;
+    double* s_cur = nullptr;      // factors the next learned update applies
+    double* s_next = nullptr;     // the network's factors from the last update's band powers
+    double* s_dev = nullptr;      // factors of lgf_learned_factors and of line-search trials
     double* x_dev = nullptr;
     double* ones_dev = nullptr;
-    C2<double>* D2 = nullptr;     // the (x,y,z,t) spectrum of Delta of the current links
-    C2<double>* D3 = nullptr;     // scaled, inverse-(z,t) spectrum of a step (input of k_gauge)
-    int8_t* btab = nullptr;       // band of every spectrum position (D2 chunk layout)
+    C2<double>* D2 = nullptr;     // second Delta buffer (st->dsel picks the current one)
+    C2<double>* D3 = nullptr;     // filtered Delta of a step (input of k_gauge)
+    int8_t* btab = nullptr;       // band of every spectrum position (Delta chunk layout)
+    int zt_l = 0;                 // log2 positions per (z, t) block of the learned pass
     double counts_host[16] = {};
 };
 
@@ -161,6 +167,8 @@ IterArgs<T> iter_args(lgf_context* c)
     a.accel = c->p.accel == LGF_ACCEL_FOURIER ? 1 : 0;
     a.expo = c->p.update == LGF_UPDATE_EXP ? 1 : 0;
     a.nth = c->nth_plane;
+    if constexpr (std::is_same<T, double>::value)
+        if (c->learned) a.D1 = c->D2;     // the measure writes the current one of the two Delta buffers
     return a;
 }
 
@@ -468,14 +476,13 @@ int32_t ensure_learned_buffers(lgf_context* c)
     if (c->D2) return LGF_OK;
     if (!c->use64) return fail(c, LGF_E_STATE, "the learned step and the band line search run in FP64");
     const Geo& g = c->d.geo;
+    c->zt_l = zt_part_log<double>(g);
     HIPCHK(c, hipMalloc(&c->D2, sizeof(C2<double>) * (size_t)delta_elems(g)));
     HIPCHK(c, hipMalloc(&c->D3, sizeof(C2<double>) * (size_t)delta_elems(g)));
-    const int nblk = (g.NP / g.W) * 4;
+    const int nblk = zt_blocks(g, c->zt_l);
     HIPCHK(c, hipMalloc(&c->band_partial, sizeof(double) * 16 * nblk));
-    HIPCHK(c, hipMalloc(&c->counts16, sizeof(double) * 16));
-    HIPCHK(c, hipMalloc(&c->s_dev, sizeof(double) * 16));
-    HIPCHK(c, hipMalloc(&c->x_dev, sizeof(double) * 16));
-    HIPCHK(c, hipMalloc(&c->ones_dev, sizeof(double) * 16));
+    for (double** q : {&c->counts16, &c->s_cur, &c->s_next, &c->s_dev, &c->x_dev, &c->ones_dev})
+        HIPCHK(c, hipMalloc(q, sizeof(double) * 16));
     HIPCHK(c, hipMalloc(&c->btab, (size_t)g.V));
     c->bytes += 2 * sizeof(C2<double>) * (size_t)delta_elems(g) + (size_t)g.V;
     // Bands: 16 intervals of log p^2 from the smallest nonzero p^2 of the
@@ -517,14 +524,11 @@ int32_t ensure_learned_buffers(lgf_context* c)
     HIPCHK(c, hipMemcpy(c->btab, tab.data(), tab.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->counts16, cnt, sizeof cnt, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->ones_dev, ones.data(), sizeof(double) * 16, hipMemcpyHostToDevice));
-    const size_t zl = std::max((size_t)g.NQ * g.W * sizeof(C2<double>), (size_t)16 * 512 * sizeof(double));
-    for (auto f : {reinterpret_cast<const void*>(&k_zt_fwd_bands<double, 64>),
-                   reinterpret_cast<const void*>(&k_zt_fwd_bands<double, 128>)})
-        HIPCHK(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)zl));
-    for (auto f : {reinterpret_cast<const void*>(&k_zt_inv_scaled<double, 64>),
-                   reinterpret_cast<const void*>(&k_zt_inv_scaled<double, 128>)})
-        HIPCHK(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)((size_t)g.NQ * g.W * sizeof(C2<double>))));
+    HIPCHK(c, hipMemcpy(c->s_cur, ones.data(), sizeof(double) * 16, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->s_next, ones.data(), sizeof(double) * 16, hipMemcpyHostToDevice));
+    for (auto f : {reinterpret_cast<const void*>(&k_zt_learned<double, 64>),
+                   reinterpret_cast<const void*>(&k_zt_learned<double, 128>)})
+        HIPCHK(c, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)zt_lds<double>(g, c->zt_l)));
     return LGF_OK;
 }
 
@@ -534,47 +538,36 @@ MlpDev model_ptrs(lgf_context* c, bool use_model)
     return MlpDev{c->mw, c->mw + 16 * 64, c->mw + 16 * 64 + 64 * 64, c->mb, c->mb + 64, c->mb + 128};
 }
 
-// Full 4D spectrum of Delta (in D) into D2, band sums, features and (with a
-// model) the factors s.  D keeps Delta.
-template <int LMAX>
-int32_t enqueue_bands(lgf_context* c, bool use_model)
-{
-    Bufs<double>& b = c->d;
-    const Geo& g = b.geo;
-    const int nblk = (g.NP / g.W) * 4;
-    const size_t zl = std::max((size_t)g.NQ * g.W * sizeof(C2<double>), (size_t)16 * 512 * sizeof(double));
-    TRY(launch(c, K_ZT_FWD, k_zt_fwd_bands<double, LMAX>, dim3(nblk), dim3(512), zl, g, (const C2<double>*)b.D,
-               c->D2, (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
-               (const int8_t*)c->btab, c->band_partial, (const DevState*)c->st));
-    TRY(launch(c, K_BANDS_MLP, k_bands_mlp<>, dim3(1), dim3(256), 0, (const double*)c->band_partial, nblk,
-               (const double*)c->counts16, g.V, model_ptrs(c, use_model), c->s_dev, c->x_dev, (const DevState*)c->st));
-    return LGF_OK;
-}
-
-// One update with per-band factors s from the spectrum in D2: the scaled
-// inverse into D3, the candidate gauge G[1 - cur] = reunit(g G[cur]), and the
-// Delta of the links it gives into D.  mode 2: a candidate (F and theta recorded as trial values, nothing
-// committed); mode 1: committed.
+// One update with per-band factors s (device array) from the current Delta
+// (left in place): the (z, t) pass with band powers into D3, the candidate
+// gauge G[1 - cur] = reunit(g G[cur]), the Delta of its links into the other
+// Delta buffer, and the learned reduction in `mode` (k_reduce_learned).
 template <int NE, int LMAX>
 int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double* trace_slot)
 {
     Bufs<double>& b = c->d;
     const Geo& g = b.geo;
-    TRY(launch(c, K_ZT_INV, k_zt_inv_scaled<double, LMAX>, dim3((g.NP / g.W) * 4), dim3(512),
-               (size_t)g.NQ * g.W * sizeof(C2<double>), g, (const C2<double>*)c->D2, c->D3,
+    TRY(launch(c, K_ZT_FWD, k_zt_learned<double, LMAX>, dim3(zt_blocks(g, c->zt_l)), dim3(512),
+               zt_lds<double>(g, c->zt_l), g, (const C2<double>*)b.D, (const C2<double>*)c->D2, c->D3,
                (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
-               (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), (const int8_t*)c->btab, s,
-               (const DevState*)c->st));
+               (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), c->zt_l, (const int8_t*)c->btab,
+               s, c->band_partial, (const DevState*)c->st));
     IterArgs<double> a = iter_args<double, NE, LMAX>(c);
     a.D = c->D3;
     TRY((enqueue_gauge_k<double, NE, LMAX>(c, g, a)));
-    a.D = b.D;
-    return enqueue_measure_k<double, NE, LMAX>(c, g, a, 1, trace_slot, mode);
-}
-
-int32_t bands_any(lgf_context* c, bool use_model)
-{
-    return c->lmax > 64 ? enqueue_bands<128>(c, use_model) : enqueue_bands<64>(c, use_model);
+    const int kid = K_TRANSFORM_MEASURE;
+    const size_t lds = measure_lds<double>(g, a.nth);
+    if (measure_once(g))
+        TRY(launch(c, kid, k_measure<double, NE, LMAX, true>, dim3(g.NQ), dim3(a.nth), lds, g, a.U,
+                   (const C2<double>*)b.G, (const C2<double>*)b.Gb, 1, b.D, c->D2, c->partial, a.tw[0], a.tw[1],
+                   (const DevState*)c->st));
+    else
+        TRY(launch(c, kid, k_measure<double, NE, LMAX, false>, dim3(g.NQ), dim3(a.nth), lds, g, a.U,
+                   (const C2<double>*)b.G, (const C2<double>*)b.Gb, 1, b.D, c->D2, c->partial, a.tw[0], a.tw[1],
+                   (const DevState*)c->st));
+    return launch(c, K_REDUCE, k_reduce_learned<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V,
+                  c->st, trace_slot, mode, (const double*)c->band_partial, zt_blocks(g, c->zt_l),
+                  (const double*)c->counts16, model_ptrs(c, true), c->s_cur, c->s_next);
 }
 
 int32_t scaled_update_any(lgf_context* c, const double* s, int mode, double* tr = nullptr)
@@ -585,30 +578,49 @@ int32_t scaled_update_any(lgf_context* c, const double* s, int mode, double* tr 
     return big ? enqueue_scaled_update<6, 128>(c, s, mode, tr) : enqueue_scaled_update<6, 64>(c, s, mode, tr);
 }
 
-// One learned update (Delta of the current links in D, state current): the
-// network's factors give candidate links, kept if F grows.  The choice is
-// made on the device, so updates can be queued (and captured) back to back;
-// a rejected candidate holds the state until the host runs enqueue_fallback.
-// Leaves Delta of the new links in D.
-int32_t learned_update(lgf_context* c, double* trace_slot)
+// Band powers of the current spectrum, features and (with a model) the
+// network's factors for them into x_dev and s_dev; the state is unchanged.
+template <int LMAX>
+int32_t enqueue_bands(lgf_context* c, bool use_model)
 {
-    TRY(bands_any(c, true));
-    TRY(scaled_update_any(c, c->s_dev, 2));
-    return launch(c, K_STATE, k_decide_trial<>, dim3(1), dim3(1), 0, c->st, trace_slot);
+    Bufs<double>& b = c->d;
+    const Geo& g = b.geo;
+    TRY(launch(c, K_ZT_FWD, k_zt_learned<double, LMAX>, dim3(zt_blocks(g, c->zt_l)), dim3(512),
+               zt_lds<double>(g, c->zt_l), g, (const C2<double>*)b.D, (const C2<double>*)c->D2, c->D3,
+               (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
+               (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), c->zt_l, (const int8_t*)c->btab,
+               (const double*)c->ones_dev, c->band_partial, (const DevState*)c->st));
+    return launch(c, K_BANDS_MLP, k_bands_mlp<>, dim3(1), dim3(256), 0, (const double*)c->band_partial,
+                  zt_blocks(g, c->zt_l), (const double*)c->counts16, g.V, model_ptrs(c, use_model), c->s_dev,
+                  c->x_dev);
 }
 
-// After a rejected candidate: the plain update from the spectrum in D2.
+int32_t bands_any(lgf_context* c, bool use_model)
+{
+    return c->lmax > 64 ? enqueue_bands<128>(c, use_model) : enqueue_bands<64>(c, use_model);
+}
+
+// One learned update (Delta of the current links current, state current):
+// the factors s_cur (from the network on the previous update's band powers,
+// 1 after a load) give candidate links, kept if F grows; the network's
+// factors for the next update come from this update's band powers.  The
+// choice is made on the device, so updates can be queued (and captured) back
+// to back; a rejected candidate holds the state until the host runs
+// enqueue_fallback.
+int32_t learned_update(lgf_context* c, double* trace_slot) { return scaled_update_any(c, c->s_cur, 1, trace_slot); }
+
+// After a rejected candidate: the plain update from the same Delta.
 int32_t enqueue_fallback(lgf_context* c, double* trace_slot)
 {
     TRY(launch(c, K_STATE, k_fallback_begin<>, dim3(1), dim3(1), 0, c->st));
-    return scaled_update_any(c, c->ones_dev, 1, trace_slot);
+    return scaled_update_any(c, c->ones_dev, 2, trace_slot);
 }
 
 // theta after one update with factors s, the links kept as they are.
 int32_t trial_theta(lgf_context* c, const std::vector<double>& s, double* theta)
 {
     HIPCHK(c, hipMemcpyAsync(c->s_dev, s.data(), sizeof(double) * 16, hipMemcpyHostToDevice, c->stream));
-    TRY(scaled_update_any(c, c->s_dev, 2));
+    TRY(scaled_update_any(c, c->s_dev, 3));
     TRY(sync_state(c));
     *theta = c->st_host->trial_theta;
     return LGF_OK;
@@ -888,6 +900,8 @@ int32_t lgf_load_links(lgf_ctx c, const void* links, int32_t where)
     if (rc != LGF_OK) return rc;
     c->phase = c->use64 && !c->use32 ? 1 : 0;
     c->iter_fp32 = 0;
+    // the learned step's first update after a load uses the plain factors
+    if (c->s_cur) TRY(launch(c, K_STATE, k_fill16<>, dim3(1), dim3(64), 0, c->s_cur, 1.0));
     c->loaded = true;
     return LGF_OK;
 }
@@ -956,6 +970,7 @@ int32_t lgf_load_gauge(lgf_ctx c, const void* G, int32_t where)
     int32_t rc;
     const dim3 grid((unsigned)blocks_for(V, 256));
     c->delta_valid = false;                 // the links G U0 G^dag(x+mu) change with G
+    if (c->s_cur) TRY(launch(c, K_STATE, k_fill16<>, dim3(1), dim3(64), 0, c->s_cur, 1.0));
     if (c->phase == 1)
         rc = launch(c, K_FIELD, k_field_load<double, kGE>, grid, dim3(256), 0, V, c->d.geo.VS, (const double*)src, g_cur<double>(c));
     else
@@ -997,11 +1012,13 @@ int32_t lgf_step(lgf_ctx c, int64_t n, lgf_stats* trace)
         }
         tr = c->trace_dev;
     }
-    TRY(set_stop(c, -1.0));
-    if (!c->delta_valid || trace) TRY(measure_any(c, tr));
     if (c->learned) {
         if (!c->has_model) return fail(c, LGF_E_STATE, "the learned step needs lgf_set_model first");
         TRY(ensure_learned_buffers(c));
+    }
+    TRY(set_stop(c, -1.0));
+    if (!c->delta_valid || trace) TRY(measure_any(c, tr));
+    if (c->learned) {
         for (int64_t k = 1; k <= n; ++k) {
             TRY(learned_update(c, tr ? tr + 2 * k : nullptr));
             TRY(sync_state(c));
@@ -1034,13 +1051,13 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
     for (;;) {
         const bool fp32_mixed = c->p.precision == LGF_MIXED && c->phase == 0;
         const double stop = fp32_mixed ? c->p.theta_switch : c->p.theta_stop;
-        TRY(set_stop(c, stop));
-        if (!c->delta_valid) TRY(measure_any(c, nullptr));
-        TRY(sync_state(c));
         if (c->learned) {
             if (!c->has_model) return fail(c, LGF_E_STATE, "the learned step needs lgf_set_model first");
             TRY(ensure_learned_buffers(c));
         }
+        TRY(set_stop(c, stop));
+        if (!c->delta_valid) TRY(measure_any(c, nullptr));
+        TRY(sync_state(c));
         while ((!c->st_host->done || c->st_host->fallback) && c->st_host->iter < c->p.max_iter) {
             if (c->st_host->fallback) {
                 TRY(enqueue_fallback(c, nullptr));

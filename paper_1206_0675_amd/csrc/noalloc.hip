@@ -81,6 +81,8 @@ __global__ void k_na_init(DevState* st, unsigned long long* check)
     st->trial_F = 0.0;
     st->trial_theta = 0.0;
     st->fallbacks = 0;
+    st->dsel = 0;
+    st->pad0 = 0;
     check[0] = 0;
     check[1] = 0;
     check[2] = 0;

@@ -20,11 +20,11 @@ namespace rt {
 
 enum KernelId {
     K_LOAD, K_STORE, K_MEASURE, K_TRANSFORM_MEASURE, K_ZT, K_GAUGE, K_REDUCE, K_FIELD, K_SWITCH, K_STATE,
-    K_ZT_FWD, K_BANDS_MLP, K_ZT_INV, K_MLP, K_COUNT
+    K_ZT_FWD, K_BANDS_MLP, K_MLP, K_COUNT
 };
 inline const char* const kKernelNames[K_COUNT] = {
     "load",  "store", "measure", "transform_measure", "zt_fft_scale", "gauge",         "reduce",
-    "field", "precision_switch", "state", "zt_fft_bands", "bands_mlp", "zt_scale_ifft", "mlp"};
+    "field", "precision_switch", "state", "zt_learned", "bands_mlp", "mlp"};
 
 // Learned-step model blob: int32 header {magic, 1, 16, 64, 64, 16, 0, 0},
 // bf16 W1[16][64], W2[64][64], W3[64][16], float32 b1[64], b2[64], b3[16].
@@ -271,6 +271,7 @@ struct IterArgs {
     C2<T>* G0 = nullptr;         // gauge pair; G[cur] current
     C2<T>* G1 = nullptr;
     C2<T>* D = nullptr;          // packed Delta (tiled)
+    C2<T>* D1 = nullptr;         // learned step: second Delta buffer (state's dsel picks the current one)
     const C2<T>* tw[4] = {};     // twiddles per axis
     const double* ptab = nullptr;
     double* partial = nullptr;   // per-plane F, theta partials
@@ -323,10 +324,10 @@ int32_t enqueue_measure_k(Runner* r, const Geo& g, const IterArgs<T>& a, int nex
     const size_t lds = measure_lds<T>(g, a.nth);
     if (measure_once(g))
         TRY(launch(r, kid, k_measure<T, NE, LMAX, true>, dim3(g.NQ), dim3(a.nth), lds, g, a.U, (const C2<T>*)a.G0,
-                   (const C2<T>*)a.G1, next, a.D, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st));
+                   (const C2<T>*)a.G1, next, a.D, a.D1, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st));
     else
         TRY(launch(r, kid, k_measure<T, NE, LMAX, false>, dim3(g.NQ), dim3(a.nth), lds, g, a.U, (const C2<T>*)a.G0,
-                   (const C2<T>*)a.G1, next, a.D, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st));
+                   (const C2<T>*)a.G1, next, a.D, a.D1, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st));
     return launch(r, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)a.partial, g.NQ, g.V, a.st, trace,
                   counts_update);
 }

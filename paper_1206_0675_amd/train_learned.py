@@ -4,17 +4,17 @@
 
 1. Generate the training fields (seeds 2000, 2001, ... of the seeded
    generator, 16^4, plaquette 0.6).
-2. Round 0: run the plain FP64 method on each; every `--every` iterations,
-   until theta < 1e-14, record the band features of Delta and the log factor
-   that minimises theta after one update (lgf_linesearch_bands, a
-   golden-section search on the GPU).  Train the 16-64-64-16 network on these
-   samples with the library's own forward, backward and Adam kernels
+2. Round 0: run the plain FP64 method on each; at every iteration until
+   theta < 1e-14, record the band features of Delta and the log factor that
+   minimises theta after one update (lgf_linesearch_bands, a golden-section
+   search on the GPU).  An update's factors come from the band powers of the
+   previous update's spectrum, so each sample pairs the features of iteration
+   n - 1 with the target of iteration n.  Train the 16-64-64-16 network on
+   these samples with the library's own forward, backward and Adam kernels
    (lgf_mlp_train).
 3. Later rounds (--rounds > 1, off by default): collect the same way along
    the trajectories of the learned step with the current network, add them to
-   the samples and train again.  On 32^3 x 64 a one-round network needed
-   43-48 iterations with one fallback per run; a two-round one 44-49 with 7-13
-   fallbacks, and a three-round one 68-85.
+   the samples and train again.
 4. Write the model blob and a JSON record of the run.
 """
 from __future__ import annotations
@@ -62,9 +62,11 @@ def generate(dims, seeds, workers=8):
         return list(ex.map(synth.random_links, [dims] * len(seeds), seeds))
 
 
-def collect(dims, fields, every=3, theta_min=1e-14, lib=None, log=print, blob=None):
+def collect(dims, fields, every=1, theta_min=1e-14, lib=None, log=print, blob=None):
     """Samples along the plain trajectories, or along those of the learned
-    step with model `blob`."""
+    step with model `blob`.  The factors of an update come from the band
+    powers of the previous update's spectrum, so a sample pairs the features
+    of iteration n - 1 with the line-search target of iteration n."""
     X, Y = [], []
     mask = band_mask(dims)
     kw = {} if blob is None else {"step": lgf.STEP_LEARNED}
@@ -73,15 +75,16 @@ def collect(dims, fields, every=3, theta_min=1e-14, lib=None, log=print, blob=No
             if blob is not None:
                 c.set_model(blob)
             c.load(U)
-            it = 0
+            it, x_prev = 0, None
             while it < 200:
                 st = c.measure()
                 if st.theta < theta_min:
                     break
-                if it % every == 0:
-                    x, ls = c.linesearch_bands()
-                    X.append(x)
+                x, ls = c.linesearch_bands()
+                if x_prev is not None and it % every == 0:
+                    X.append(x_prev)
                     Y.append(ls)
+                x_prev = x
                 c.step(1)
                 it += 1
         if log and (k % 64 == 0 or k == len(fields) - 1):
@@ -96,7 +99,7 @@ def main(argv=None):
     ap.add_argument("--configs", type=int, default=256)
     ap.add_argument("--seed0", type=int, default=2000)
     ap.add_argument("--dims", type=int, nargs=4, default=[16, 16, 16, 16])
-    ap.add_argument("--every", type=int, default=3)
+    ap.add_argument("--every", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)

@@ -41,7 +41,8 @@ def rand_blob(seed, scale=0.3, b3=None):
 
 
 def oracle_learned(dims, U, s):
-    """The oracle's update for given factors s, with the accept rule."""
+    """The oracle's update for given factors s (those the GPU applied), with
+    the accept rule."""
     F0 = oracle.measure(dims, U)[0]
     Uc = omlp.update_with(dims, U, s)
     return Uc if oracle.measure(dims, Uc)[0] > F0 else oracle.step(dims, U, 1)[0]
@@ -64,28 +65,38 @@ def test_zero_model_is_plain(L):
 @pytest.mark.parametrize("dims,seed,scale,b3", [((8, 4, 4, 8), 8, 0.2, None), ((16, 8, 8, 16), 21, 0.2, 0.4),
                                                 ((8, 8, 16, 4), 22, 0.1, -0.5)])
 def test_learned_factors_and_update(L, dims, seed, scale, b3):
-    announce(f"learned update dims={dims} seed={seed}")
+    """Three learned updates.  Before each, the features of the current links'
+    band powers (1e-12) and the network's factors for them (1e-5: bf16
+    weights, float32 arithmetic) against the oracle; those factors are the
+    ones the next update applies (the first applies s = 1).  The links after
+    every update equal the oracle's update with the factors the GPU used and
+    its accept rule, to 1e-12."""
+    announce(f"learned updates dims={dims} seed={seed}")
     V = synth.volume(dims)
     U = synth.random_links(dims, seed)
     blob = rand_blob(seed + 1, scale=scale, b3=b3)
     p = omlp.params_from_blob(blob)
+    Uo, s_use = U, np.ones(16)
     with lgf.Context(dims, lib=L, step=1) as c:
         c.set_model(blob)
         c.load(U)
-        x, s = c.learned_factors()
-        _, _, delta = oracle.measure(dims, U)
-        P, cnt = oracle.band_powers(dims, delta)
-        xo = omlp.features(P, cnt, V)
-        assert np.max(np.abs(x - xo)) <= 1e-12
-        assert np.max(np.abs(s / omlp.factors(p, xo) - 1)) <= 1e-5
-        c.step(1)
-        Ug = c.store()
-    assert np.max(np.abs(Ug - oracle_learned(dims, U, s))) <= 1e-12
+        for _ in range(3):
+            x, s_next = c.learned_factors()
+            _, _, delta = oracle.measure(dims, Uo)
+            P, cnt = oracle.band_powers(dims, delta)
+            xo = omlp.features(P, cnt, V)
+            assert np.max(np.abs(x - xo)) <= 1e-12
+            assert np.max(np.abs(s_next / omlp.factors(p, xo) - 1)) <= 1e-5
+            c.step(1)
+            Uo = oracle_learned(dims, Uo, s_use)
+            assert np.max(np.abs(c.store() - Uo)) <= 1e-12
+            s_use = s_next
 
 
 def test_learned_fallback_taken(L):
-    """Factors far too large in the linear regime lower F: the plain update
-    must be taken and counted."""
+    """Factors far too large in the linear regime lower F: the first update
+    (s = 1) is kept, the second (s = e^2.3 from the network) must fall back to
+    the plain update and be counted."""
     dims = (8, 8, 8, 8)
     announce("learned fallback")
     U = synth.small_field(dims, 31, 1e-3)
@@ -93,11 +104,11 @@ def test_learned_fallback_taken(L):
     with lgf.Context(dims, lib=L, step=1) as c:
         c.set_model(blob)
         c.load(U)
-        c.step(1)
+        c.step(2)
         Ug = c.store()
         st = c.measure()
     assert st.fallbacks == 1
-    assert np.max(np.abs(Ug - oracle.step(dims, U, 1)[0])) <= 1e-12
+    assert np.max(np.abs(Ug - oracle.step(dims, U, 2)[0])) <= 1e-12
 
 
 def test_learned_fix_converges(L):

@@ -64,13 +64,17 @@ def test_band_powers_parseval_and_counts(oracle_lib):
 
 
 def test_zero_network_is_the_plain_step(oracle_lib):
+    """A network that outputs 0 gives s = 1 everywhere: every learned update
+    is the plain update, bit for bit."""
     dims = (4, 4, 8, 4)
     U = synth.random_links(dims, 5)
     p = {k: np.zeros(s) for k, s in mlp.SHAPES}
-    U1, acc, s, x = mlp.learned_step(dims, U, p)
+    U1, acc, s, x = mlp.learned_step(dims, U, p, None)
     assert np.all(s == 1.0)
     Up, _, _, _ = oracle.step(dims, U, 1)
     assert np.array_equal(U1, Up)
+    U3, it, fb, _, _ = mlp.learned_run(dims, U, p, n=3)
+    assert it == 3 and np.array_equal(U3, oracle.step(dims, U, 3)[0])
 
 
 def test_factor_too_large_falls_back(oracle_lib):
@@ -80,11 +84,30 @@ def test_factor_too_large_falls_back(oracle_lib):
     U = synth.small_field(dims, 5, eps=1e-3)
     p = {k: np.zeros(s) for k, s in mlp.SHAPES}
     p["b3"] = np.full(16, 2.3)
-    U1, acc, s, x = mlp.learned_step(dims, U, p)
+    U1, acc, s, x = mlp.learned_step(dims, U, p, np.full(16, np.exp(2.3)))
     assert not acc
     assert np.array_equal(U1, oracle.step(dims, U, 1)[0])
+    assert np.allclose(s, np.exp(2.3))
 
 
+def test_factors_lag_the_spectrum_by_one_update(oracle_lib):
+    """The first update after a load applies s = 1; update n + 1 applies the
+    network's factors for the band powers of update n's spectrum."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 11)
+    rng = np.random.default_rng(12)
+    p = {k: rng.normal(scale=0.2, size=sh) for k, sh in mlp.SHAPES}
+    V = synth.volume(dims)
+    U1, _, s1, x0 = mlp.learned_step(dims, U, p, None)
+    assert np.array_equal(U1, oracle.step(dims, U, 1)[0])      # s = 1: the plain update
+    _, _, d0 = oracle.measure(dims, U)
+    P0, c0 = oracle.band_powers(dims, d0)
+    assert np.array_equal(x0, mlp.features(P0, c0, V)) and np.array_equal(s1, mlp.factors(p, x0))
+    U2, acc, s2, x1 = mlp.learned_step(dims, U1, p, s1)
+    cand = mlp.update_with(dims, U1, s1)
+    assert np.array_equal(U2, cand if acc else oracle.step(dims, U1, 1)[0])
+    Ur, it, fb, F, th = mlp.learned_run(dims, U, p, n=2)
+    assert np.array_equal(Ur, U2) and it == 2
 def test_linesearch_never_worse_than_plain(oracle_lib):
     dims = (4, 4, 4, 4)
     U = synth.random_links(dims, 6)
