@@ -77,8 +77,8 @@ extern "C" {
 #define LGF_STEP_LEARNED 1  /* s_b (alpha/2) p2max/p2 with per-band factors s_b from the
                                network set by lgf_set_model, applied to the band powers of
                                the previous update's spectrum (s = 1 for the first update
-                               after a load); an update that does not increase F is
-                               replaced by the plain one (FP64 only)                       */
+                               after a load); an update that neither increases F nor
+                               lowers theta is replaced by the plain one (FP64 only)       */
 
 /* how g(x) is formed from the filtered Delta (eq. gx) */
 #define LGF_UPDATE_FIRST_ORDER 0  /* g = reunit(1 + (alpha/2) dtilde): first order in alpha, then
@@ -119,7 +119,8 @@ typedef struct lgf_stats {
     int64_t iter;           /* gauge transformations applied since the last load         */
     int64_t iter_fp32;      /* ... of which in FP32                                      */
     int64_t iter_fp64;      /* ... of which in FP64                                      */
-    int64_t fallbacks;      /* learned steps replaced by the plain step (F did not grow) */
+    int64_t fallbacks;      /* learned steps replaced by the plain step (neither F rose nor
+                               theta fell) */
     double F;               /* functional of the current links                           */
     double theta;           /* convergence measure of the current links                  */
     double seconds;         /* wall time of the call                                     */

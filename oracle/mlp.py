@@ -21,8 +21,10 @@ exact values.  The factors an update applies come from the network on the band p
 of the previous update's spectrum (s = 1 for the first update after a load):
 the spectrum of the current links is only known once the update's own
 (z, t) pass has run, so the factors lag it by one update.  An update with
-factors s is accepted only if it increases F; otherwise the plain update
-(s = 1) is taken.
+factors s is accepted if it increases F or lowers theta; otherwise the plain
+update (s = 1) is taken.  (Near convergence the gain in F per update falls
+below the rounding of F while theta still resolves it, so a test on F alone
+would reject good candidates there.)
 
 Training targets: the one factor s, common to all bands, that minimises theta
 after one update (theta is what the stop test reads, and it stays resolvable
@@ -31,7 +33,7 @@ golden-section search on ln s in [-2.3, 2.3] and kept only if it beats the
 plain step; it is the target of every band that holds modes.  (Choosing each
 band's factor greedily starves the slow low-momentum bands and lengthens the
 run.)  The loss is the masked mean squared error over the bands that hold
-modes.  The accept rule (F must grow) is unchanged.
+modes.
 """
 from __future__ import annotations
 
@@ -157,17 +159,19 @@ def update_with(dims, U, s, alpha=0.08):
 def learned_step(dims, U, p: dict, s, alpha=0.08):
     """One learned update with the factors s it was handed (s = None: the
     plain factors).  Returns (U', accepted, s_next, x): the candidate from s
-    is kept iff it raises F, else the plain update is taken; x are the
+    is kept iff it raises F or lowers theta, else the plain update is taken;
+    x are the
     features of the band powers of U's spectrum and s_next the network's
     factors for them, which the next update uses (the factors lag the
     spectrum by one update)."""
     V = int(np.prod(dims))
-    F0, _, delta = lgfo.measure(dims, U)
+    F0, th0, delta = lgfo.measure(dims, U)
     P, cnt = lgfo.band_powers(dims, delta)
     x = features(P, cnt, V)
     s_next = factors(p, x)
     U1 = update_with(dims, U, s, alpha)
-    if lgfo.measure(dims, U1)[0] > F0:
+    F1, th1, _ = lgfo.measure(dims, U1)
+    if F1 > F0 or th1 < th0:
         return U1, True, s_next, x
     return update_with(dims, U, None, alpha), False, s_next, x
 

@@ -97,8 +97,8 @@ struct DevState {
     int32_t needs_measure; // Delta, F, theta of the current links are not computed yet
     int32_t switch_pending;// batched mixed runs: FP32 phase finished, rebuild in FP64
     int32_t mixed;         // batched runs: FP32 phase followed by FP64
-    int32_t fallback;      // learned step: candidate rejected; `done` is held at 1 until
-                           // the host has run the plain update
+    int32_t fallback;      // learned step: the last candidate was rejected, so the next
+                           // update is the plain one from the same Delta
     double trial_F, trial_theta;   // learned step: F, theta of the candidate links
     int64_t fallbacks;     // learned step: updates that fell back to the plain factors
     int32_t dsel;          // learned step: Delta of the current links is in the Delta buffer dsel
@@ -568,11 +568,23 @@ __device__ __forceinline__ SpectralScale make_scale(const Geo& geo, const double
                          c0, accel, nullptr, nullptr};
 }
 
+// Bands of the modes one t-axis task holds: G bytes, aligned to G.
+template <int G>
+struct alignas(G) BandBytes {
+    int8_t b[G];
+};
+
+// Values per register group of the t-axis DFT of a line of L points.
+__host__ __device__ constexpr int zt_group(int L) { return fft_r2(L) > 1 ? fft_r2(L) : fft_r1(L); }
+
 // The t axis of the (z, t) block: forward DFT, spectral factor and inverse
 // DFT of each contiguous group in registers, between the two A passes.
 // LEARNED: the factor is multiplied by s_b of the mode's band, and the
-// thread adds |Dhat(p)|^2 (before scaling) to bands[b] (a7's band powers for
-// the next update's factors).
+// thread adds |Dhat(p)|^2 (before scaling) to bands[b] (the band powers the
+// next update's factors come from).  The band table of a tile holds the
+// bands of one task's G modes together: byte ((g Lz + z) W + w) G + k is
+// the band of t position g G + k, z position z, plane position w of the
+// tile (-1 for the zero mode); sc.sb points to the 16 factors in LDS.
 template <typename T, int LT, bool LEARNED = false>
 __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ tw, int tid, int nth,
                           const SpectralScale& sc, const Geo& geo, int logWb, int pxy0, double* bands = nullptr)
@@ -589,6 +601,12 @@ __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ t
         const int pxy = pxy0 + w;
         const double base = sc.tx[pxy & (geo.L[0] - 1)] + sc.ty[pxy >> geo.logL[0]] + sc.tz[zp];
         C2<T>* p = buf + lo + j1 * R2 * es;
+        BandBytes<G> bb;
+        if constexpr (LEARNED) {
+            static_assert(G == zt_group(LT), "band table groups follow the t-axis register groups");
+            bb = *reinterpret_cast<const BandBytes<G>*>(
+                sc.btab + ((int64_t)(((j1 << geo.logL[2]) + zp) * geo.W + (pxy & (geo.W - 1))) * G));
+        }
         C2<T> u[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) u[k] = p[k * es];
@@ -597,8 +615,7 @@ __device__ void zt_t_axis(C2<T>* buf, const Lines a, const C2<T>* __restrict__ t
         for (int k = 0; k < G; ++k) {
             double f = sc.factor(base + sc.tt[j1 * R2 + k]);
             if constexpr (LEARNED) {
-                // chunk position of this mode: (t position * Lz + z) * W + plane offset in the tile
-                const int b = sc.btab[(((j1 * R2 + k) << geo.logL[2]) + zp) * geo.W + (pxy & (geo.W - 1))];
+                const int b = bb.b[k];
                 if (b >= 0) {
                     const double pw = (double)u[k].x * u[k].x + (double)u[k].y * u[k].y;
 #pragma unroll
@@ -866,6 +883,136 @@ __device__ __forceinline__ void reduce_state(const double* __restrict__ partial,
 }
 
 // ===========================================================================
+// learned step: network on the band powers
+// ===========================================================================
+__device__ __forceinline__ float bf16_to_float(uint16_t b)
+{
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// Network 16 -> 64 -> 64 -> 16 (ReLU), bf16 weights [in][out] row-major,
+// float32 biases, float32 accumulation.
+struct MlpDev {
+    const uint16_t* W1;
+    const uint16_t* W2;
+    const uint16_t* W3;
+    const float* b1;
+    const float* b2;
+    const float* b3;
+};
+
+// LDS bytes band_factors works in.
+constexpr int kBandLdsBytes = 256 * 8 + (16 + 64 + 64 + 256) * 4;
+
+// Band powers -> features -> factors s_b = exp(clip(y_b, -2.3, 2.3)), by one
+// block of any size (a multiple of 64): the work is laid out for 256 virtual
+// threads, which the block's threads take in turn, so the result does not
+// depend on the block size.  The per-block band sums (nblk rows of 16) are
+// added in a fixed order: virtual thread v adds elements v, v + 256, ... of
+// the flat array (all of band v mod 16, four running sums), then a tree over
+// the virtual threads of each band.  Empty bands (count 0) get feature 0.
+// Each layer's dot products are split over the virtual threads and their
+// parts added in a fixed order.  Without a network (net.W1 NULL) s = 1.
+// lds: kBandLdsBytes.  Ends with a barrier.
+__device__ __forceinline__ void band_factors(const double* __restrict__ band_partial, int nblk,
+                                             const double* __restrict__ count16, int64_t V, const MlpDev& net,
+                                             double* __restrict__ s_out, double* __restrict__ x_out, double* lds)
+{
+    double* red = lds;
+    float* x = reinterpret_cast<float*>(lds + 256);
+    float* h1 = x + 16;
+    float* h2 = h1 + 64;
+    float* part = h2 + 64;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t n = (int64_t)nblk * 16;
+    for (int v = tid; v < 256; v += nth) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int64_t e = v;
+        for (; e + 768 < n; e += 1024) {
+            a0 += band_partial[e];
+            a1 += band_partial[e + 256];
+            a2 += band_partial[e + 512];
+            a3 += band_partial[e + 768];
+        }
+        for (; e < n; e += 256) a0 += band_partial[e];
+        red[v] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+    for (int h = 128; h >= 16; h >>= 1) {
+        for (int v = tid; v < h; v += nth) red[v] += red[v + h];
+        __syncthreads();
+    }
+    if (tid < 16) {
+        const double p = red[tid];
+        double f = 0.0;
+        if (count16[tid] > 0.0) {
+            const double pv = p / count16[tid] / (double)V;
+            f = log10(pv > 1e-300 ? pv : 1e-300) / 8.0;
+        }
+        x[tid] = (float)f;
+        if (x_out) x_out[tid] = f;
+    }
+    __syncthreads();
+    if (!net.W1) {
+        if (tid < 16) s_out[tid] = 1.0;
+        __syncthreads();
+        return;
+    }
+    if (tid < 64) {
+        float a = net.b1[tid];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a = fmaf(x[i], bf16_to_float(net.W1[i * 64 + tid]), a);
+        h1[tid] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    for (int v = tid; v < 256; v += nth) {   // layer 2: output v mod 64, inputs [16 k, 16 k + 16), k = v / 64
+        const int o = v & 63, k = v >> 6;
+        float a = 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a = fmaf(h1[16 * k + i], bf16_to_float(net.W2[(16 * k + i) * 64 + o]), a);
+        part[v] = a;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const float a = ((net.b2[tid] + part[tid]) + part[64 + tid]) + (part[128 + tid] + part[192 + tid]);
+        h2[tid] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    for (int v = tid; v < 256; v += nth) {   // layer 3: output v mod 16, inputs [4 k, 4 k + 4), k = v / 16
+        const int o = v & 15, k = v >> 4;
+        float a = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a = fmaf(h2[4 * k + i], bf16_to_float(net.W3[(4 * k + i) * 16 + o]), a);
+        part[v] = a;
+    }
+    __syncthreads();
+    if (tid < 16) {
+        float a = net.b3[tid];
+        for (int k = 0; k < 16; ++k) a += part[16 * k + tid];
+        const double y = fmin(fmax((double)a, -2.3), 2.3);
+        s_out[tid] = exp(y);
+    }
+    __syncthreads();
+}
+
+// Work of the block that computes the next update's factors inside the
+// candidate's measure launch of a learned update (s_out NULL: none), and the
+// blocks that launch gets in front of its planes.
+constexpr int kBandSideBlocks = 8;
+struct BandJob {
+    const double* band_partial;
+    int nblk;
+    int pad;
+    const double* count16;
+    int64_t V;
+    MlpDev net;
+    double* s_out;
+};
+
+// ===========================================================================
 // single-configuration kernels (one lattice per launch)
 // ===========================================================================
 // The links are never stored: they are G(x) Uref(x) G^dag(x+mu) for the
@@ -878,17 +1025,29 @@ __device__ __forceinline__ void reduce_state(const double* __restrict__ partial,
 // current links is in D if st->dsel = 0, else in D1, and the links of the
 // gauge just formed (next = 1) write the other one, so a rejected candidate
 // leaves the current Delta in place.
+// job.s_out (learned step's candidate only, else NULL): the launch has
+// kBandSideBlocks more blocks in front of the planes (the plane to XCD map is
+// kept); the first of them runs band_factors for the next update's factors,
+// the others return.
 template <typename T, int NE, int LMAX, bool ONCE>
 __global__ void __launch_bounds__(256) k_measure(Geo geo, const C2<T>* __restrict__ Uref, const C2<T>* G0,
                                                  const C2<T>* G1, int next, C2<T>* D0, C2<T>* D1,
                                                  double* __restrict__ partial, const C2<T>* __restrict__ twx,
-                                                 const C2<T>* __restrict__ twy, const DevState* __restrict__ st)
+                                                 const C2<T>* __restrict__ twy, const DevState* __restrict__ st,
+                                                 BandJob job)
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
+    int b = blockIdx.x;
+    if (job.s_out) {
+        if (b == 0)
+            band_factors(job.band_partial, job.nblk, job.count16, job.V, job.net, job.s_out, nullptr, lds_raw);
+        if (b < kBandSideBlocks) return;
+        b -= kBandSideBlocks;
+    }
     const C2<T>* G = (st->cur ^ next) ? G1 : G0;
     C2<T>* D = (D1 && ((st->dsel ^ next) & 1)) ? D1 : D0;
-    const int q = plane_of_block(blockIdx.x, geo);
+    const int q = plane_of_block(b, geo);
     C2<T>* buf = reinterpret_cast<C2<T>*>(lds_raw + 2 * blockDim.x);
     if constexpr (ONCE) measure_plane_once<T, NE, LMAX>(geo, q, Uref, G, D, partial, twx, twy, lds_raw, buf);
     else measure_plane<T, NE, LMAX>(geo, q, Uref, G, D, partial, twx, twy, lds_raw, buf);
@@ -1134,46 +1293,75 @@ __global__ void kb_switch_done(const BatchCfg<double>* __restrict__ c64, int ncf
 // the spectrum it transforms, and the network runs in the one-block
 // reduction that follows the update.
 
-// Wavefront-then-block sum of 16 per-thread values in a fixed order; thread 0
-// writes them to out.  wred: 16 * (blockDim / 64) doubles of LDS.
+// Block sum of 16 per-thread values in a fixed order; the 16 sums go to out.
+// Within a wavefront the values are halved over lanes four times (lane bit
+// 5, 4, 3, 2 selects which half of the remaining values a lane keeps and
+// adds its partner's share to), which leaves band
+// q = 8 b5 + 4 b4 + 2 b3 + b2 on lanes with those bits; two more exchanges
+// add the four lanes of each band.  wred: 16 * (blockDim / 64) doubles of
+// LDS.
+// One halving step of block_sum16: H values kept of 2 H, partner lane ^ 4 H.
+// (A template per step: every index into v is a constant, so v stays in
+// registers.)
+template <int H>
+__device__ __forceinline__ void halve_over_lanes(double* v, int lane)
+{
+    constexpr int m = 4 * H;
+    const bool upper = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double give = upper ? v[i] : v[i + H];
+        const double keep = upper ? v[i + H] : v[i];
+        v[i] = keep + __shfl(give, lane ^ m);
+    }
+}
+
 __device__ __forceinline__ void block_sum16(double* v, double* wred, double* __restrict__ out)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] += __shfl(v[q], lane ^ m);
-    if (lane == 0)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) wred[q * nw + wave] = v[q];
+    halve_over_lanes<8>(v, lane);
+    halve_over_lanes<4>(v, lane);
+    halve_over_lanes<2>(v, lane);
+    halve_over_lanes<1>(v, lane);
+    double a = v[0];
+    a += __shfl(a, lane ^ 2);
+    a += __shfl(a, lane ^ 1);
+    const int q = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+    if ((lane & 3) == 0) wred[q * nw + wave] = a;
     __syncthreads();
     if (tid < 16) {
-        double a = 0.0;
-        for (int w = 0; w < nw; ++w) a += wred[tid * nw + w];
-        out[tid] = a;
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += wred[tid * nw + w];
+        out[tid] = t;
     }
 }
 
 // One block per (tile, field, part) as k_zt: forward (z, t) FFT of the
 // current Delta (buffer st->dsel of D0, D1), band powers of the spectrum into
 // band_partial[block][16], factors s_b (alpha/2) p2max/(p^2 V), inverse
-// (z, t) FFT into Dout.  The current Delta is left as it is.
+// (z, t) FFT into Dout.  The current Delta is left as it is.  With
+// plain_after_reject, s = 1 while st->fallback is raised (the plain update
+// that replaces a rejected candidate).
 template <typename T, int LMAX>
-__global__ void __launch_bounds__(512) k_zt_learned(Geo geo, const C2<T>* D0, const C2<T>* D1, C2<T>* __restrict__ Dout,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LMAX == 64 ? 4 : 1))) k_zt_learned(Geo geo, const C2<T>* D0, const C2<T>* D1, C2<T>* __restrict__ Dout,
                                                     const C2<T>* __restrict__ twz, const C2<T>* __restrict__ twt,
                                                     const double* __restrict__ ptab, double c0, int accel, int logWb,
                                                     const int8_t* __restrict__ btab, const double* __restrict__ sb,
-                                                    double* __restrict__ band_partial, const DevState* __restrict__ st)
+                                                    int plain_after_reject, double* __restrict__ band_partial,
+                                                    const DevState* __restrict__ st)
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
     __shared__ double wred[16 * 8];
+    __shared__ double s_lds[16];
+    // read after the forward z pass's barrier
+    if (threadIdx.x < 16) s_lds[threadIdx.x] = (plain_after_reject && st->fallback) ? 1.0 : sb[threadIdx.x];
     int h, chunk;
     zt_part_of_block(blockIdx.x, (geo.NP >> geo.logW) * 4, geo.logW - logWb, h, chunk);
     const int j = chunk >> 2;
     SpectralScale sc = make_scale(geo, ptab, c0, accel);
     sc.btab = btab + (int64_t)j * geo.NQ * geo.W;
-    sc.sb = sb;
+    sc.sb = s_lds;
     double bands[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) bands[q] = 0.0;
@@ -1182,136 +1370,30 @@ __global__ void __launch_bounds__(512) k_zt_learned(Geo geo, const C2<T>* D0, co
     block_sum16(bands, wred, band_partial + (int64_t)blockIdx.x * 16);
 }
 
-__device__ __forceinline__ float bf16_to_float(uint16_t b)
-{
-    const uint32_t u = (uint32_t)b << 16;
-    float f;
-    __builtin_memcpy(&f, &u, 4);
-    return f;
-}
-
-// Network 16 -> 64 -> 64 -> 16 (ReLU), bf16 weights [in][out] row-major,
-// float32 biases, float32 accumulation.
-struct MlpDev {
-    const uint16_t* W1;
-    const uint16_t* W2;
-    const uint16_t* W3;
-    const float* b1;
-    const float* b2;
-    const float* b3;
-};
-
-// Band powers -> features -> factors s_b = exp(clip(y_b, -2.3, 2.3)), by one
-// block of 256 threads.  The per-block band sums are added in a fixed order:
-// thread t adds rows t, t + 256, ... (16 bands each), then a tree over the
-// threads.  Empty bands (count 0) get feature 0.  The network runs with its
-// weights staged in LDS as floats, each layer's dot products split over all
-// threads and their parts added in a fixed order.  Without a network (net.W1
-// NULL) s = 1.  Ends with a barrier.
-__device__ __forceinline__ void band_factors(const double* __restrict__ band_partial, int nblk,
-                                             const double* __restrict__ count16, int64_t V, const MlpDev& net,
-                                             double* __restrict__ s_out, double* __restrict__ x_out)
-{
-    __shared__ double red[16 * 256];
-    __shared__ float w1[16 * 64], w2[64 * 64], w3[64 * 16], part[256];
-    __shared__ float x[16], h1[64], h2[64];
-    const int tid = threadIdx.x;        // blockDim.x == 256
-    {
-        double acc[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-        for (int r = tid; r < nblk; r += 256) {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q] += band_partial[(int64_t)r * 16 + q];
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) red[q * 256 + tid] = acc[q];
-    }
-    if (net.W1) {
-        for (int i = tid; i < 16 * 64; i += 256) w1[i] = bf16_to_float(net.W1[i]);
-        for (int i = tid; i < 64 * 64; i += 256) w2[i] = bf16_to_float(net.W2[i]);
-        for (int i = tid; i < 64 * 16; i += 256) w3[i] = bf16_to_float(net.W3[i]);
-    }
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) red[q * 256 + tid] += red[q * 256 + tid + h];
-        __syncthreads();
-    }
-    if (tid < 16) {
-        const double p = red[tid * 256];
-        double f = 0.0;
-        if (count16[tid] > 0.0) {
-            const double pv = p / count16[tid] / (double)V;
-            f = log10(pv > 1e-300 ? pv : 1e-300) / 8.0;
-        }
-        x[tid] = (float)f;
-        if (x_out) x_out[tid] = f;
-    }
-    __syncthreads();
-    if (!net.W1) {
-        if (tid < 16) s_out[tid] = 1.0;
-        __syncthreads();
-        return;
-    }
-    if (tid < 64) {
-        float a = net.b1[tid];
-        for (int i = 0; i < 16; ++i) a = fmaf(x[i], w1[i * 64 + tid], a);
-        h1[tid] = a > 0.f ? a : 0.f;
-    }
-    __syncthreads();
-    {   // layer 2: output o, inputs [16 k, 16 k + 16) for k = tid >> 6
-        const int o = tid & 63, k = tid >> 6;
-        float a = 0.f;
-        for (int i = 16 * k; i < 16 * k + 16; ++i) a = fmaf(h1[i], w2[i * 64 + o], a);
-        part[tid] = a;
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const float a = ((net.b2[tid] + part[tid]) + part[64 + tid]) + (part[128 + tid] + part[192 + tid]);
-        h2[tid] = a > 0.f ? a : 0.f;
-    }
-    __syncthreads();
-    {   // layer 3: output o, inputs [4 k, 4 k + 4) for k = tid >> 4
-        const int o = tid & 15, k = tid >> 4;
-        float a = 0.f;
-        for (int i = 4 * k; i < 4 * k + 4; ++i) a = fmaf(h2[i], w3[i * 16 + o], a);
-        part[tid] = a;
-    }
-    __syncthreads();
-    if (tid < 16) {
-        float a = net.b3[tid];
-        for (int k = 0; k < 16; ++k) a += part[16 * k + tid];
-        const double y = fmin(fmax((double)a, -2.3), 2.3);
-        s_out[tid] = exp(y);
-    }
-    __syncthreads();
-}
-
 // Features and factors of the band powers in band_partial (lgf_learned_factors).
 template <int UNUSED = 0>
 __global__ void __launch_bounds__(256) k_bands_mlp(const double* __restrict__ band_partial, int nblk,
                                                    const double* __restrict__ count16, int64_t V, MlpDev net,
                                                    double* __restrict__ s_out, double* __restrict__ x_out)
 {
-    band_factors(band_partial, nblk, count16, V, net, s_out, x_out);
+    __shared__ double lds[kBandLdsBytes / 8];
+    band_factors(band_partial, nblk, count16, V, net, s_out, x_out, lds);
 }
 
 // The reduction that ends a learned update, one block.
-//   mode 1 (candidate): F and theta of the candidate links; the network's
-//     factors for the next update from this update's band powers into s_next;
-//     the candidate is committed (the gauge and Delta buffers flip, s_cur =
-//     s_next) iff it raised F, else `fallback` is raised and `done` held at 1
-//     until the host has run the plain update.
-//   mode 2 (after a fallback's plain update): committed, s_cur = s_next.
+//   mode 1 (update): F and theta of the new links.  A candidate (st->fallback
+//     clear) is committed iff it raised F or lowered theta (near convergence
+//     the gain in F is below its rounding; theta still resolves it); a
+//     rejected one raises
+//     st->fallback, and the next update (its (z, t) pass then takes s = 1)
+//     is the plain update from the same Delta, committed as it is.  On
+//     commit the gauge and Delta buffers flip and s_cur = s_next (the
+//     factors the update's measure launch computed from its band powers).
 //   mode 3 (trial of the line search): F and theta recorded as trial values.
 template <int UNUSED = 0>
 __global__ void __launch_bounds__(256) k_reduce_learned(const double* __restrict__ partial, int nq, int64_t V,
                                                         DevState* st, double* __restrict__ trace, int mode,
-                                                        const double* __restrict__ band_partial, int nblk,
-                                                        const double* __restrict__ count16, MlpDev net,
-                                                        double* __restrict__ s_cur, double* __restrict__ s_next)
+                                                        double* __restrict__ s_cur, const double* __restrict__ s_next)
 {
     if (st->done) return;
     __shared__ double red[2 * 256];
@@ -1325,14 +1407,14 @@ __global__ void __launch_bounds__(256) k_reduce_learned(const double* __restrict
     double fs, ts;
     block_sum2(a, b, red, tid, nth, &fs, &ts);
     const double F = fs / (12.0 * (double)V), th = ts / (3.0 * (double)V);
-    if (mode == 1) band_factors(band_partial, nblk, count16, V, net, s_next, nullptr);
     if (tid == 0) {
         commit = 0;
         if (mode == 3) {
             st->trial_F = F;
             st->trial_theta = th;
-        } else if (mode == 2 || F > st->F) {
+        } else if (st->fallback || F > st->F || th < st->theta) {
             commit = 1;
+            st->fallback = 0;
             st->iter += 1;
             st->cur ^= 1;
             st->dsel ^= 1;
@@ -1352,21 +1434,11 @@ __global__ void __launch_bounds__(256) k_reduce_learned(const double* __restrict
             st->trial_F = F;
             st->trial_theta = th;
             st->fallback = 1;
-            st->done = 1;
+            st->fallbacks += 1;
         }
     }
     __syncthreads();
     if (commit && tid < 16) s_cur[tid] = s_next[tid];
-}
-
-template <int UNUSED = 0>
-__global__ void k_fallback_begin(DevState* st)
-{
-    if (st->fallback) {
-        st->fallback = 0;
-        st->done = 0;
-        st->fallbacks += 1;
-    }
 }
 
 // s = 1 (the first update after a load uses the plain factors).

@@ -13,6 +13,7 @@
 // the host reads back only at poll points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -488,9 +489,11 @@ int32_t ensure_learned_buffers(lgf_context* c)
     // Bands: 16 intervals of log p^2 from the smallest nonzero p^2 of the
     // lattice to p2max, b = floor(16 ln(p^2 / pmin) / ln(p2max / pmin)) clipped
     // to [0, 15], none for p = 0.  The band of every spectrum position is
-    // tabulated once, in the layout of one field of a Delta chunk (tile j of W
-    // plane positions, then (z, t) position, then the position in the tile);
-    // the mode counts come from the same table.
+    // tabulated once per tile j of W plane positions, the bands of the G
+    // t positions one task of the (z, t) pass's t axis holds side by side:
+    // byte ((g Lz + z) W + w) G + k of tile j is the band of t position
+    // g G + k, z position z, plane position j W + w.  The mode counts come
+    // from the same table.
     double p2max = 0.0;
     const std::vector<double> pt = momentum_tables(c->p.dims, &p2max);
     double pmin = 1e300;
@@ -504,21 +507,23 @@ int32_t ensure_learned_buffers(lgf_context* c)
     const double* ty = tx + L[0];
     const double* tz = ty + L[1];
     const double* tt = tz + L[2];
-    const int W = g.W, NQ = g.NQ, n = NQ * W;
+    const int W = g.W, NQ = g.NQ, n = NQ * W, G = zt_group(L[3]);
     std::vector<int8_t> tab((size_t)g.V);
     double cnt[16] = {};
     for (int j = 0; j < g.NP / W; ++j)
-        for (int i = 0; i < n; ++i) {
-            const int pxy = j * W + (i & (W - 1)), qq = i / W;
-            const double p2 = tx[pxy % L[0]] + ty[pxy / L[0]] + tz[qq % L[2]] + tt[qq / L[2]];
-            int b = -1;
-            if (p2 > 0.0) {
-                b = (int)std::floor(16.0 * std::log(p2 / pmin) / log_range);
-                b = b < 0 ? 0 : (b > 15 ? 15 : b);
-                cnt[b] += 1.0;
-            }
-            tab[(size_t)j * n + i] = (int8_t)b;
-        }
+        for (int t = 0; t < L[3]; ++t)
+            for (int z = 0; z < L[2]; ++z)
+                for (int w = 0; w < W; ++w) {
+                    const int pxy = j * W + w;
+                    const double p2 = tx[pxy % L[0]] + ty[pxy / L[0]] + tz[z] + tt[t];
+                    int b = -1;
+                    if (p2 > 0.0) {
+                        b = (int)std::floor(16.0 * std::log(p2 / pmin) / log_range);
+                        b = b < 0 ? 0 : (b > 15 ? 15 : b);
+                        cnt[b] += 1.0;
+                    }
+                    tab[(size_t)j * n + ((size_t)((t / G) * L[2] + z) * W + w) * G + t % G] = (int8_t)b;
+                }
     std::memcpy(c->counts_host, cnt, sizeof cnt);
     std::vector<double> ones(16, 1.0);
     HIPCHK(c, hipMemcpy(c->btab, tab.data(), tab.size(), hipMemcpyHostToDevice));
@@ -551,23 +556,27 @@ int32_t enqueue_scaled_update(lgf_context* c, const double* s, int mode, double*
                zt_lds<double>(g, c->zt_l), g, (const C2<double>*)b.D, (const C2<double>*)c->D2, c->D3,
                (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
                (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), c->zt_l, (const int8_t*)c->btab,
-               s, c->band_partial, (const DevState*)c->st));
+               s, (int)(mode == 1), c->band_partial, (const DevState*)c->st));
     IterArgs<double> a = iter_args<double, NE, LMAX>(c);
     a.D = c->D3;
     TRY((enqueue_gauge_k<double, NE, LMAX>(c, g, a)));
+    // the candidate's measure launch also computes the next update's factors
+    // from this update's band powers (one block in front of the planes)
+    const BandJob job{(const double*)c->band_partial, zt_blocks(g, c->zt_l), 0, (const double*)c->counts16, g.V,
+                      model_ptrs(c, true), c->s_next};
     const int kid = K_TRANSFORM_MEASURE;
-    const size_t lds = measure_lds<double>(g, a.nth);
+    const size_t lds = std::max(measure_lds<double>(g, a.nth), (size_t)kBandLdsBytes);
+    const dim3 grid(g.NQ + kBandSideBlocks);
     if (measure_once(g))
-        TRY(launch(c, kid, k_measure<double, NE, LMAX, true>, dim3(g.NQ), dim3(a.nth), lds, g, a.U,
+        TRY(launch(c, kid, k_measure<double, NE, LMAX, true>, grid, dim3(a.nth), lds, g, a.U,
                    (const C2<double>*)b.G, (const C2<double>*)b.Gb, 1, b.D, c->D2, c->partial, a.tw[0], a.tw[1],
-                   (const DevState*)c->st));
+                   (const DevState*)c->st, job));
     else
-        TRY(launch(c, kid, k_measure<double, NE, LMAX, false>, dim3(g.NQ), dim3(a.nth), lds, g, a.U,
+        TRY(launch(c, kid, k_measure<double, NE, LMAX, false>, grid, dim3(a.nth), lds, g, a.U,
                    (const C2<double>*)b.G, (const C2<double>*)b.Gb, 1, b.D, c->D2, c->partial, a.tw[0], a.tw[1],
-                   (const DevState*)c->st));
+                   (const DevState*)c->st, job));
     return launch(c, K_REDUCE, k_reduce_learned<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V,
-                  c->st, trace_slot, mode, (const double*)c->band_partial, zt_blocks(g, c->zt_l),
-                  (const double*)c->counts16, model_ptrs(c, true), c->s_cur, c->s_next);
+                  c->st, trace_slot, mode, c->s_cur, (const double*)c->s_next);
 }
 
 int32_t scaled_update_any(lgf_context* c, const double* s, int mode, double* tr = nullptr)
@@ -589,7 +598,7 @@ int32_t enqueue_bands(lgf_context* c, bool use_model)
                zt_lds<double>(g, c->zt_l), g, (const C2<double>*)b.D, (const C2<double>*)c->D2, c->D3,
                (const C2<double>*)(b.tw + b.tw_off[2]), (const C2<double>*)(b.tw + b.tw_off[3]),
                (const double*)c->ptab, c->c0, (int)(c->p.accel == LGF_ACCEL_FOURIER), c->zt_l, (const int8_t*)c->btab,
-               (const double*)c->ones_dev, c->band_partial, (const DevState*)c->st));
+               (const double*)c->ones_dev, 0, c->band_partial, (const DevState*)c->st));
     return launch(c, K_BANDS_MLP, k_bands_mlp<>, dim3(1), dim3(256), 0, (const double*)c->band_partial,
                   zt_blocks(g, c->zt_l), (const double*)c->counts16, g.V, model_ptrs(c, use_model), c->s_dev,
                   c->x_dev);
@@ -603,18 +612,12 @@ int32_t bands_any(lgf_context* c, bool use_model)
 // One learned update (Delta of the current links current, state current):
 // the factors s_cur (from the network on the previous update's band powers,
 // 1 after a load) give candidate links, kept if F grows; the network's
-// factors for the next update come from this update's band powers.  The
-// choice is made on the device, so updates can be queued (and captured) back
-// to back; a rejected candidate holds the state until the host runs
-// enqueue_fallback.
+// factors for the next update come from this update's band powers.  A
+// rejected candidate leaves the state as it was and raises st->fallback, and
+// the next learned update is the plain one from the same Delta.  Every choice
+// is made on the device, so updates can be queued (and captured) back to
+// back.
 int32_t learned_update(lgf_context* c, double* trace_slot) { return scaled_update_any(c, c->s_cur, 1, trace_slot); }
-
-// After a rejected candidate: the plain update from the same Delta.
-int32_t enqueue_fallback(lgf_context* c, double* trace_slot)
-{
-    TRY(launch(c, K_STATE, k_fallback_begin<>, dim3(1), dim3(1), 0, c->st));
-    return scaled_update_any(c, c->ones_dev, 2, trace_slot);
-}
 
 // theta after one update with factors s, the links kept as they are.
 int32_t trial_theta(lgf_context* c, const std::vector<double>& s, double* theta)
@@ -1022,7 +1025,7 @@ int32_t lgf_step(lgf_ctx c, int64_t n, lgf_stats* trace)
         for (int64_t k = 1; k <= n; ++k) {
             TRY(learned_update(c, tr ? tr + 2 * k : nullptr));
             TRY(sync_state(c));
-            if (c->st_host->fallback) TRY(enqueue_fallback(c, tr ? tr + 2 * k : nullptr));
+            if (c->st_host->fallback) TRY(learned_update(c, tr ? tr + 2 * k : nullptr));   // the plain update
         }
     } else {
         for (int64_t k = 1; k <= n; ++k) TRY(update_any(c, tr ? tr + 2 * k : nullptr));
@@ -1058,13 +1061,9 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
         TRY(set_stop(c, stop));
         if (!c->delta_valid) TRY(measure_any(c, nullptr));
         TRY(sync_state(c));
-        while ((!c->st_host->done || c->st_host->fallback) && c->st_host->iter < c->p.max_iter) {
-            if (c->st_host->fallback) {
-                TRY(enqueue_fallback(c, nullptr));
-            } else {
-                const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
-                TRY(enqueue_chunk(c, chunk));
-            }
+        while (!c->st_host->done && c->st_host->iter < c->p.max_iter) {
+            const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
+            TRY(enqueue_chunk(c, chunk));
             TRY(sync_state(c));
         }
         if (c->st_host->nonfinite) {

@@ -324,10 +324,12 @@ int32_t enqueue_measure_k(Runner* r, const Geo& g, const IterArgs<T>& a, int nex
     const size_t lds = measure_lds<T>(g, a.nth);
     if (measure_once(g))
         TRY(launch(r, kid, k_measure<T, NE, LMAX, true>, dim3(g.NQ), dim3(a.nth), lds, g, a.U, (const C2<T>*)a.G0,
-                   (const C2<T>*)a.G1, next, a.D, a.D1, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st));
+                   (const C2<T>*)a.G1, next, a.D, a.D1, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st,
+                   BandJob{}));
     else
         TRY(launch(r, kid, k_measure<T, NE, LMAX, false>, dim3(g.NQ), dim3(a.nth), lds, g, a.U, (const C2<T>*)a.G0,
-                   (const C2<T>*)a.G1, next, a.D, a.D1, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st));
+                   (const C2<T>*)a.G1, next, a.D, a.D1, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st,
+                   BandJob{}));
     return launch(r, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)a.partial, g.NQ, g.V, a.st, trace,
                   counts_update);
 }

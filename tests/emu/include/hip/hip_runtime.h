@@ -24,6 +24,8 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+// AMDGPU occupancy attributes carry no meaning on the CPU.
+#define amdgpu_waves_per_eu(...) unused
 #define __restrict__ __restrict
 #define __align__(n) __attribute__((aligned(n)))
 // one block runs at a time, so a function-static array is exactly the

@@ -271,14 +271,15 @@ def test_emulated_learned_factors_and_update_match_oracle(E, oracle_lib):
         c.load(U)
         for _ in range(3):
             x, s_next = c.learned_factors()
-            F0, _, delta = oracle.measure(dims, Uo)
+            F0, th0, delta = oracle.measure(dims, Uo)
             P, cnt = oracle.band_powers(dims, delta)
             xo = omlp.features(P, cnt, V)
             assert np.max(np.abs(x - xo)) <= 1e-12
             assert np.max(np.abs(s_next / omlp.factors(p, xo) - 1)) <= 1e-5
             c.step(1)
             Uc = omlp.update_with(dims, Uo, s_use)
-            Uo = Uc if oracle.measure(dims, Uc)[0] > F0 else oracle.step(dims, Uo, 1)[0]
+            F1, th1, _ = oracle.measure(dims, Uc)
+            Uo = Uc if (F1 > F0 or th1 < th0) else oracle.step(dims, Uo, 1)[0]
             assert np.max(np.abs(c.store() - Uo)) <= 1e-12
             s_use = s_next
 

@@ -78,8 +78,9 @@ def test_zero_network_is_the_plain_step(oracle_lib):
 
 
 def test_factor_too_large_falls_back(oracle_lib):
-    # linear regime: the factor multiplies D by 1 - 0.08 * 16 * s; s = e^2.3 ~ 10
-    # gives |1 - 12.8 s / s| > 1, so F drops and the plain step is taken
+    # linear regime: the update multiplies every mode of Delta by 1 - 0.08 * 16 * s;
+    # s = e^2.3 ~ 10 gives |1 - 12.8| > 1, so F drops and theta grows, and the
+    # plain step is taken
     dims = (4, 4, 8, 4)
     U = synth.small_field(dims, 5, eps=1e-3)
     p = {k: np.zeros(s) for k, s in mlp.SHAPES}
