@@ -10,7 +10,8 @@ LIB = os.path.join(HERE, "liblgfo.so")
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp", "-fcx-limited-range",
            "-Wall", "-Wextra", "-Wno-unused-parameter",
-           os.path.join(HERE, "lgfo.c"), "-o", LIB + ".tmp", "-lm"]
+           "-ffp-contract=off", os.path.join(HERE, "lgfo.c"), os.path.join(HERE, "wilson.c"),
+           "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
