@@ -20,11 +20,11 @@ namespace rt {
 
 enum KernelId {
     K_LOAD, K_STORE, K_MEASURE, K_TRANSFORM_MEASURE, K_ZT, K_GAUGE, K_REDUCE, K_FIELD, K_SWITCH, K_STATE,
-    K_ZT_FWD, K_BANDS_MLP, K_MLP, K_COUNT
+    K_ZT_FWD, K_BANDS_MLP, K_MLP, K_HEATBATH, K_OVERRELAX, K_PLAQUETTE, K_COUNT
 };
 inline const char* const kKernelNames[K_COUNT] = {
-    "load",  "store", "measure", "transform_measure", "zt_fft_scale", "gauge",         "reduce",
-    "field", "precision_switch", "state", "zt_learned", "bands_mlp", "mlp"};
+    "load",  "store", "measure", "transform_measure", "zt_fft_scale", "gauge",    "reduce",   "field",
+    "precision_switch", "state", "zt_learned", "bands_mlp", "mlp", "heatbath", "overrelax", "plaquette"};
 
 // Learned-step model blob: int32 header {magic, 1, 16, 64, 64, 16, 0, 0},
 // bf16 W1[16][64], W2[64][64], W3[64][16], float32 b1[64], b2[64], b3[16].

@@ -113,6 +113,19 @@ def load_library(path: str | None = None):
         "lgf_mlp_grad": ([C.c_char_p, C.c_size_t] + [C.POINTER(C.c_float)] * 3 + [I64, C.POINTER(C.c_float),
                          C.POINTER(C.c_double)], I32),
         "lgf_mlp_eval": ([C.c_char_p, C.c_size_t, C.POINTER(C.c_float), I64, C.POINTER(C.c_float)], I32),
+        "lgf_wilson_create": ([C.POINTER(C.c_int32), C.c_double, C.c_uint64, ctx_p], I32),
+        "lgf_wilson_destroy": ([V], I32),
+        "lgf_wilson_cold": ([V], I32),
+        "lgf_wilson_load": ([V, V, I32], I32),
+        "lgf_wilson_sweep": ([V, I32], I32),
+        "lgf_wilson_update": ([V, I64, I32], I32),
+        "lgf_wilson_get_sweep": ([V, C.POINTER(C.c_uint64)], I32),
+        "lgf_wilson_set_sweep": ([V, C.c_uint64], I32),
+        "lgf_wilson_plaquette": ([V, C.POINTER(C.c_double)], I32),
+        "lgf_wilson_store": ([V, V, I32], I32),
+        "lgf_wilson_device_links": ([V], C.c_void_p),
+        "lgf_wilson_skipped": ([V, C.POINTER(I64)], I32),
+        "lgf_wilson_last_error": ([V], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -201,6 +214,10 @@ class Context:
     def load(self, links):
         ptr, where, _keep = _buffer(links)
         self._check(self.lib.lgf_load_links(self.h, C.c_void_p(ptr), where))
+
+    def load_device(self, ptr: int):
+        """Load links already in device memory (canonical layout) at address ptr."""
+        self._check(self.lib.lgf_load_links(self.h, C.c_void_p(int(ptr)), DEVICE))
 
     def store(self, out=None):
         if out is None:
@@ -431,3 +448,96 @@ def mlp_eval(blob, X, lib=None):
     if rc != OK:
         raise LgfError(rc, L.lgf_last_error(None).decode())
     return Y
+
+
+# ---------------------------------------------------------------------------
+# Wilson-action configuration generator (include/lgf_wilson.h)
+# ---------------------------------------------------------------------------
+HEATBATH, OVERRELAX = 0, 1
+
+
+class WilsonGenerator:
+    """Heatbath + overrelaxation generator of Wilson-action SU(3) links on the
+    GPU (lgf_wilson_create ... lgf_wilson_destroy); links start cold."""
+
+    def __init__(self, dims, beta: float, seed: int, lib=None):
+        self.lib = lib or load_library()
+        self.dims = tuple(int(d) for d in dims)
+        h = C.c_void_p()
+        d = (C.c_int32 * 4)(*self.dims)
+        rc = self.lib.lgf_wilson_create(d, float(beta), int(seed), C.byref(h))
+        if rc != OK:
+            raise LgfError(rc, self.lib.lgf_wilson_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lgf_wilson_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LgfError(rc, self.lib.lgf_wilson_last_error(self.h).decode())
+        return rc
+
+    @property
+    def shape(self):
+        lx, ly, lz, lt = self.dims
+        return (lt, lz, ly, lx, 4, 3, 3)
+
+    def cold(self):
+        self._check(self.lib.lgf_wilson_cold(self.h))
+
+    def load(self, links):
+        ptr, where, _keep = _buffer(links)
+        self._check(self.lib.lgf_wilson_load(self.h, C.c_void_p(ptr), where))
+
+    def sweep(self, kind: int = HEATBATH):
+        self._check(self.lib.lgf_wilson_sweep(self.h, int(kind)))
+
+    def update(self, n_update: int, n_or: int = 4):
+        self._check(self.lib.lgf_wilson_update(self.h, int(n_update), int(n_or)))
+
+    @property
+    def sweep_index(self) -> int:
+        n = C.c_uint64()
+        self._check(self.lib.lgf_wilson_get_sweep(self.h, C.byref(n)))
+        return n.value
+
+    @sweep_index.setter
+    def sweep_index(self, n: int):
+        self._check(self.lib.lgf_wilson_set_sweep(self.h, int(n)))
+
+    def plaquette(self) -> float:
+        p = C.c_double()
+        self._check(self.lib.lgf_wilson_plaquette(self.h, C.byref(p)))
+        return p.value
+
+    def store(self, out=None):
+        if out is None:
+            out = np.empty(self.shape, dtype=np.complex128)
+        ptr, where, _keep = _buffer(out)
+        self._check(self.lib.lgf_wilson_store(self.h, C.c_void_p(ptr), where))
+        return out
+
+    @property
+    def device_links(self) -> int:
+        """Device address of the links (canonical layout), for Context.load_device."""
+        return self.lib.lgf_wilson_device_links(self.h)
+
+    def skipped(self) -> int:
+        n = C.c_int64()
+        self._check(self.lib.lgf_wilson_skipped(self.h, C.byref(n)))
+        return n.value

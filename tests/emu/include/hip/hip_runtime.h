@@ -81,6 +81,13 @@ using std::fmax;
 using std::fma;
 using std::sqrt;
 
+struct alignas(16) double2 {
+    double x, y;
+};
+inline double2 make_double2(double x, double y) { return double2{x, y}; }
+
+inline uint64_t __umul64hi(uint64_t a, uint64_t b) { return (uint64_t)(((unsigned __int128)a * b) >> 64); }
+
 template <typename T>
 inline T atomicAdd(T* p, T v)
 {

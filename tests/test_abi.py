@@ -1,5 +1,5 @@
 """The C ABI on a machine without a GPU: the gfx950 library loads, exports
-every function include/lgf.h declares, and its host-only paths (defaults,
+every function include/*.h declares, and its host-only paths (defaults,
 validation, argument checks before any device call, error strings) behave
 as documented."""
 import ctypes as C
@@ -13,7 +13,8 @@ import synth
 from paper_1206_0675_amd import lgf
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lgf.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +26,7 @@ def L():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(lgf_[a-z_0-9]+)\s*\(", text)))
 
@@ -33,7 +34,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["lgf_create", "lgf_destroy", "lgf_load_links", "lgf_store_links", "lgf_step", "lgf_fix",
-                     "lgf_measure", "lgf_validate_links", "lgf_default_params"]:
+                     "lgf_measure", "lgf_validate_links", "lgf_default_params", "lgf_wilson_create",
+                     "lgf_wilson_update", "lgf_wilson_store", "lgf_wilson_plaquette"]:
         assert required in names
 
 
@@ -134,3 +136,15 @@ def test_malformed_model_rejected_before_touching_the_device(L):
 def test_product_path_has_no_fallback(tmp_path):
     with pytest.raises(ImportError):
         lgf.load_library(str(tmp_path / "missing.so"))
+
+
+def test_wilson_generator_argument_checks_before_device_calls(L):
+    h = C.c_void_p()
+    for dims, beta, code in (((3, 4, 4, 4), 6.0, lgf.E_UNSUPPORTED_SHAPE), ((4, 4, 4, 2048), 6.0, lgf.E_UNSUPPORTED_SHAPE),
+                             ((4, 4, 4, 4), -0.5, lgf.E_INVALID_ARG), ((4, 4, 4, 4), float("nan"), lgf.E_INVALID_ARG)):
+        d = (C.c_int32 * 4)(*dims)
+        assert L.lgf_wilson_create(d, beta, 1, C.byref(h)) == code
+        assert L.lgf_wilson_last_error(None)
+    assert L.lgf_wilson_create(None, 6.0, 1, C.byref(h)) == lgf.E_INVALID_ARG
+    assert L.lgf_wilson_destroy(None) == lgf.E_INVALID_ARG
+    assert L.lgf_wilson_device_links(None) is None

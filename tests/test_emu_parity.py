@@ -370,3 +370,49 @@ def test_emulated_linesearch_matches_oracle(E, oracle_lib):
     thg = oracle.measure(dims, omlp.update_with(dims, U, np.exp(ls)))[1]
     assert abs(thg / best - 1) <= 1e-6
     assert thg < oracle.measure(dims, oracle.step(dims, U, 1)[0])[1]
+
+
+# ---------------------------------------------------------------------------
+# Wilson-action generator
+# ---------------------------------------------------------------------------
+from oracle import wilson as owil  # noqa: E402
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (2, 4, 6, 4)])
+def test_emulated_wilson_generator_matches_oracle(E, oracle_lib, dims):
+    """Heatbath, overrelaxation and a generate run of the library (emulated)
+    against the reference: same links (same libm on the CPU)."""
+    U = synth.random_links(dims, 3) if dims == (4, 4, 4, 4) else owil.cold(dims)
+    with lgf.WilsonGenerator(dims, 5.9, 77, lib=E) as g:
+        g.load(U)
+        g.sweep(lgf.HEATBATH)
+        Uo, sk = owil.sweep(dims, U, 5.9, 77, 0, owil.HEATBATH)
+        assert np.max(np.abs(g.store() - Uo)) <= 1e-13 and g.skipped() == sk == 0
+        assert g.sweep_index == 1
+        g.sweep(lgf.OVERRELAX)
+        Uo, _ = owil.sweep(dims, Uo, 5.9, 77, 0, owil.OVERRELAX)
+        assert np.max(np.abs(g.store() - Uo)) <= 1e-13
+        g.update(2, 2)
+        Uo, _ = owil.generate(dims, Uo, 5.9, 77, 1, 2, 2)
+        assert np.max(np.abs(g.store() - Uo)) <= 1e-13
+        if dims == (4, 4, 4, 4):
+            assert abs(g.plaquette() - oracle.plaquette(dims, Uo)) <= 1e-14
+        g.cold()
+        assert g.sweep_index == 0 and np.array_equal(g.store(), owil.cold(dims))
+
+
+def test_emulated_wilson_small_beta_and_errors(E, oracle_lib):
+    """beta < 3/k runs the plain-rejection branch of the x0 sampler; invalid
+    arguments are refused."""
+    dims = (4, 4, 2, 2)
+    with lgf.WilsonGenerator(dims, 0.2, 5, lib=E) as g:
+        g.update(2, 1)
+        Uo, sk = owil.generate(dims, owil.cold(dims), 0.2, 5, 0, 2, 1)
+        assert np.max(np.abs(g.store() - Uo)) <= 1e-13 and g.skipped() == sk == 0
+        with pytest.raises(lgf.LgfError):
+            g.sweep(7)
+    for bad in ((3, 4, 4, 4), (4, 4, 4, 0)):
+        with pytest.raises(lgf.LgfError):
+            lgf.WilsonGenerator(bad, 6.0, 1, lib=E)
+    with pytest.raises(lgf.LgfError):
+        lgf.WilsonGenerator((4, 4, 4, 4), -1.0, 1, lib=E)
