@@ -26,6 +26,13 @@ resident in HBM.  Printed as one JSON line:
   update_variants  16^4: iterations and time to theta for first-order and
                    exact-exponential updates over a sweep of alpha, and plain
                    steepest descent (no Fourier acceleration)
+  wilson_32        the paper's workload class: Wilson-action fields at 32^4,
+                   beta 5.8, 6.0, 6.2 (cold start, 102 updates of one heatbath
+                   and four overrelaxation sweeps, all on the GPU), their
+                   plaquette and time to theta for FP64, mixed and learned;
+                   heatbath and overrelaxation sweep times with the
+                   algorithmic bytes of a sweep (every link read and each
+                   updated link written, per class launch)
   cpu_baseline     the FP64 oracle on this host's cores, a bounded sample of
                    the headline workload; oracle_time_to_theta: full oracle
                    runs at 8^4 and 16^4 with all cores and with one
@@ -291,6 +298,57 @@ def learned_vs_plain(L, fields, blob, torch):
             "learned_seconds": round(tl, 5), "speedup": round(tp / tl, 4) if tl > 0 else None}
 
 
+def wilson_32(L, blob, torch):
+    """Wilson-action fields at 32^4 from the GPU generator, then gauge fixing."""
+    from paper_1206_0675_amd import lgf
+    V = vol(HEADLINE_DIMS)
+    sweep_bytes = 8 * (4 * V + V // 2) * 144          # 8 class launches: read all links, write half of one direction
+    out = {"dims": list(HEADLINE_DIMS), "updates": 102, "or_per_update": 4, "runs": []}
+    for i, beta in enumerate((5.8, 6.0, 6.2)):
+        with lgf.WilsonGenerator(HEADLINE_DIMS, beta, 5000 + i, lib=L) as g:
+            t = time.perf_counter()
+            g.update(102, 4)
+            t_gen = time.perf_counter() - t
+            if i == 1:
+                t = time.perf_counter()
+                g.update(10, 0)
+                t_hb = (time.perf_counter() - t) / 10
+                t = time.perf_counter()
+                for _ in range(10):
+                    g.sweep(lgf.OVERRELAX)
+                t_or = (time.perf_counter() - t) / 10
+                out["heatbath_sweep_ms"] = round(t_hb * 1e3, 3)
+                out["overrelax_sweep_ms"] = round(t_or * 1e3, 3)
+                out["sweep_alg_bytes"] = sweep_bytes
+                out["heatbath_alg_gbps"] = round(sweep_bytes / t_hb / 1e9, 1)
+                out["heatbath_frac"] = round(sweep_bytes / t_hb / 1e9 / HBM_PEAK_GBPS, 4)
+                out["overrelax_alg_gbps"] = round(sweep_bytes / t_or / 1e9, 1)
+                g.sweep_index = 0
+                g.cold()
+                g.update(102, 4)
+            rec = {"beta": beta, "seed": 5000 + i, "plaquette": round(g.plaquette(), 6),
+                   "generate_s": round(t_gen, 3), "skipped": g.skipped()}
+            modes = [("fp64_12real", dict(storage=12)), ("mixed_12real", dict(storage=12, precision=lgf.MIXED))]
+            if blob is not None:
+                modes.append(("learned_12real", dict(storage=12, step=lgf.STEP_LEARNED)))
+            for label, kw in modes:
+                with lgf.Context(HEADLINE_DIMS, lib=L, max_iter=100000, **kw) as ctx:
+                    if "step" in kw:
+                        ctx.set_model(blob)
+                    ctx.load_device(g.device_links)
+                    torch.cuda.synchronize()
+                    s = ctx.fix(raise_on_error=False)
+                rec[label] = {"status": s.status, "iters": s.iter, "seconds": round(s.seconds, 4),
+                              "theta": s.theta, "F": s.F}
+                if "step" in kw:
+                    rec[label]["fallbacks"] = s.fallbacks
+            out["runs"].append(rec)
+            print(f"# wilson beta {beta}: P {rec['plaquette']}, FP64 {rec['fp64_12real']['iters']} iterations "
+                  f"{rec['fp64_12real']['seconds']} s, mixed {rec['mixed_12real']['seconds']} s", file=sys.stderr,
+                  flush=True)
+    return out
+
+
 def update_variants(L, U, torch):
     """16^4 seed 1: iterations and time to theta < 1e-15 over alpha, for the
     first-order update (the paper's) and the exact exponential; and plain
@@ -394,6 +452,9 @@ def main():
     ap.add_argument("--batch-sample", action="store_true",
                     help="run only the batch of 64 (one lgf_batch fix, then the lattices one by one) and print "
                          "its JSON; for profiling")
+    ap.add_argument("--wilson-sample", action="store_true",
+                    help="run only a 32^4 beta 6.0 Wilson-action generation (20 updates of one heatbath and four "
+                         "overrelaxation sweeps) and its FP64 gauge fixing; no JSON; for profiling")
     ap.add_argument("--gen-workers", type=int, default=min(8, os.cpu_count() or 1),
                     help="worker processes for input generation (started before this program touches the GPU; "
                          "use 1 under a profiler, which sets up the GPU before this program starts)")
@@ -408,10 +469,10 @@ def main():
     import synth
 
     # ---- inputs, generated before this program touches the GPU -------------
-    extras = not (args.no_extras or args.pmc_sample or args.batch_sample)
+    extras = not (args.no_extras or args.pmc_sample or args.batch_sample or args.wilson_sample)
     gw = args.gen_workers
     t = time.time()
-    U = None if args.batch_sample else synth.random_links(HEADLINE_DIMS, args.seed, workers=gw)
+    U = None if (args.batch_sample or args.wilson_sample) else synth.random_links(HEADLINE_DIMS, args.seed, workers=gw)
     seeds32 = []
     small = med = None
     mixed16 = []
@@ -435,7 +496,7 @@ def main():
     cpu = None
     oracle_ttt = None
     oracle_F8 = None
-    if not args.no_cpu_baseline and not (args.pmc_sample or args.batch_sample):
+    if not args.no_cpu_baseline and not (args.pmc_sample or args.batch_sample or args.wilson_sample):
         cpu = cpu_baseline(U, args.storage, HEADLINE_DIMS)
         print(f"# cpu baseline: {cpu['value']} iters/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
         if extras:
@@ -470,6 +531,15 @@ def main():
     if args.batch_sample:
         print(json.dumps(batch_run(L, batch_in[0], batch_in[1], torch)), flush=True)
         return
+    if args.wilson_sample:
+        with lgf.WilsonGenerator(HEADLINE_DIMS, 6.0, 5001, lib=L) as g:
+            g.update(20, 4)
+            P = g.plaquette()
+            with lgf.Context(HEADLINE_DIMS, lib=L, storage=R, max_iter=100000) as ctx:
+                ctx.load_device(g.device_links)
+                s = ctx.fix(raise_on_error=False)
+        print(f"# wilson sample: P {P:.6f}, {s.iter} iterations, {s.seconds:.3f} s", file=sys.stderr, flush=True)
+        return
 
     # ---- headline: timed iterations, then the profiled pass ---------------
     iters_per_s, t_it, prof, launch_shape = rate_and_kernels(L, HEADLINE_DIMS, U, args.steps, args.warmup, torch,
@@ -490,6 +560,11 @@ def main():
             with open(model_path, "rb") as fh:
                 blob = fh.read()
             line_extra["learned_vs_plain"] = learned_vs_plain(L, learned_fields, blob, torch)
+        blob = None
+        if os.path.exists(model_path):
+            with open(model_path, "rb") as fh:
+                blob = fh.read()
+        line_extra["wilson_32"] = wilson_32(L, blob, torch)
         b = batch_run(L, batch_in[0], batch_in[1], torch)
         line_extra["batch"] = b
         print(f"# batch of {b['configs']}: {b['seconds']:.4f} s, {b['configs_per_s']} configs/s, "

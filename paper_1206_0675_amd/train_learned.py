@@ -2,8 +2,12 @@
 
     python -m paper_1206_0675_amd.train_learned [--configs 256] [--rounds 1] [--out DIR]
 
-1. Generate the training fields (seeds 2000, 2001, ... of the seeded
-   generator, 16^4, plaquette 0.6).
+1. Generate the training fields: seeds 2000, 2001, ... of the seeded
+   synthetic generator (16^4, plaquette 0.6), and with --wilson N, N
+   Wilson-action fields per beta of --betas from the library's heatbath
+   generator (--wilson-dims, 32^4 by default; cold start, --updates updates
+   of one heatbath and four overrelaxation sweeps, Philox seeds 7000 + 100 b
+   + k), sampled every --wilson-every iterations.
 2. Round 0: run the plain FP64 method on each; at every iteration until
    theta < 1e-14, record the band features of Delta and the log factor that
    minimises theta after one update (lgf_linesearch_bands, a golden-section
@@ -62,7 +66,18 @@ def generate(dims, seeds, workers=8):
         return list(ex.map(synth.random_links, [dims] * len(seeds), seeds))
 
 
-def collect(dims, fields, every=1, theta_min=1e-14, lib=None, log=print, blob=None):
+def generate_wilson(dims, betas, per_beta, updates, lib=None):
+    """Wilson-action fields from the GPU generator (cold start)."""
+    out = []
+    for b, beta in enumerate(betas):
+        for k in range(per_beta):
+            with lgf.WilsonGenerator(dims, beta, 7000 + 100 * b + k, lib=lib) as g:
+                g.update(updates, 4)
+                out.append(g.store())
+    return out
+
+
+def collect(dims, fields, every=1, theta_min=1e-14, lib=None, log=print, blob=None, max_iter=200):
     """Samples along the plain trajectories, or along those of the learned
     step with model `blob`.  The factors of an update come from the band
     powers of the previous update's spectrum, so a sample pairs the features
@@ -76,7 +91,7 @@ def collect(dims, fields, every=1, theta_min=1e-14, lib=None, log=print, blob=No
                 c.set_model(blob)
             c.load(U)
             it, x_prev = 0, None
-            while it < 200:
+            while it < max_iter:
                 st = c.measure()
                 if st.theta < theta_min:
                     break
@@ -87,7 +102,7 @@ def collect(dims, fields, every=1, theta_min=1e-14, lib=None, log=print, blob=No
                 x_prev = x
                 c.step(1)
                 it += 1
-        if log and (k % 64 == 0 or k == len(fields) - 1):
+        if log and (k % 64 == 0 or k == len(fields) - 1 or len(fields) <= 64):
             log(f"# collected {len(X)} samples from {k + 1} fields")
     X, Y = np.array(X), np.array(Y)
     M = np.broadcast_to(mask.astype(np.float64), X.shape).copy()
@@ -104,6 +119,12 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--rounds", type=int, default=1)
+    ap.add_argument("--wilson", type=int, default=0, help="Wilson-action fields per beta (0: none)")
+    ap.add_argument("--betas", type=float, nargs="+", default=[5.8, 6.0, 6.2])
+    ap.add_argument("--wilson-dims", type=int, nargs=4, default=[32, 32, 32, 32])
+    ap.add_argument("--updates", type=int, default=100)
+    ap.add_argument("--wilson-every", type=int, default=8, help="sample every n-th iteration of those runs")
+    ap.add_argument("--wilson-max-iter", type=int, default=20000)
     ap.add_argument("--out", default=MODEL_DIR)
     args = ap.parse_args(argv)
     t0 = time.time()
@@ -112,11 +133,19 @@ def main(argv=None):
     print(f"# generated {len(fields)} fields in {time.time() - t0:.1f}s", flush=True)
     L = lgf.load_library()
     say = lambda m: print(m, flush=True)    # noqa: E731
+    wdims = tuple(args.wilson_dims)
+    wfields = generate_wilson(wdims, args.betas, args.wilson, args.updates, lib=L) if args.wilson > 0 else []
+    if wfields:
+        say(f"# generated {len(wfields)} Wilson-action fields")
     Xs, Ys, Ms, blob, trace, rounds = [], [], [], None, None, []
     for r in range(args.rounds):
         t1 = time.time()
         X, Y, M = collect(dims, fields, args.every, lib=L, log=say, blob=blob)
         Xs.append(X), Ys.append(Y), Ms.append(M)
+        if wfields:
+            X, Y, M = collect(wdims, wfields, args.wilson_every, lib=L, log=say, blob=blob,
+                              max_iter=args.wilson_max_iter)
+            Xs.append(X), Ys.append(Y), Ms.append(M)
         X, Y, M = np.concatenate(Xs), np.concatenate(Ys), np.concatenate(Ms)
         t2 = time.time()
         blob, trace = lgf.mlp_train(X, Y, M, steps=args.steps, batch=args.batch, seed=1, lr=args.lr, lib=L)
@@ -130,6 +159,8 @@ def main(argv=None):
     with open(os.path.join(args.out, "learned_step.bin"), "wb") as f:
         f.write(blob)
     rec = {"dims": list(dims), "seeds": [args.seed0, args.seed0 + args.configs - 1], "every": args.every,
+           "wilson": {"dims": list(wdims), "per_beta": args.wilson, "betas": args.betas, "updates": args.updates,
+                      "every": args.wilson_every} if args.wilson > 0 else None,
            "samples": int(X.shape[0]), "steps": args.steps, "batch": args.batch, "lr": args.lr,
            "train_mse": rounds[-1]["train_mse"], "plain_step_mse": base, "loss_first": float(trace[0]),
            "loss_last": float(trace[-1]), "rounds": rounds, "seconds": round(time.time() - t0, 1),
