@@ -33,6 +33,9 @@ resident in HBM.  Printed as one JSON line:
                    heatbath and overrelaxation sweep times with the
                    algorithmic bytes of a sweep (every link read and each
                    updated link written, per class launch)
+  fft_study        32^4: the filter's 4D FFT as 1D x4, 2D+1D+1D and 2D+2D passes
+                   over HBM, and 2D+1D+1D with the t DFTs on the matrix cores
+                   (lgf_fft_study), ms per application
   cpu_baseline     the FP64 oracle on this host's cores, a bounded sample of
                    the headline workload; oracle_time_to_theta: full oracle
                    runs at 8^4 and 16^4 with all cores and with one
@@ -349,6 +352,37 @@ def wilson_32(L, blob, torch):
     return out
 
 
+def fft_study_32(L, torch, kernels):
+    """The filter's 4D FFT split three ways at 32^4 (four FP64 complex fields
+    in the plain layout), ms per application and bandwidth on the passes'
+    bytes (each pass reads and writes 64 V bytes); beside them, the
+    iteration's own (z, t) kernel, which is all the filter adds to HBM traffic
+    there (its (x, y) passes ride in the transform and gauge kernels)."""
+    from paper_1206_0675_amd import lgf
+    V = vol(HEADLINE_DIMS)
+    g = torch.Generator(device="cpu").manual_seed(7)
+    shape = (4, HEADLINE_DIMS[3], HEADLINE_DIMS[2], HEADLINE_DIMS[1], HEADLINE_DIMS[0])
+    f = torch.complex(torch.randn(shape, dtype=torch.float64, generator=g),
+                      torch.randn(shape, dtype=torch.float64, generator=g)).cuda()
+    out = {"dims": list(HEADLINE_DIMS), "fields": 4, "reps": 20}
+    for name, v, passes in (("1d_x4", lgf.FFT_1DX4, 7), ("2d_1d_1d", lgf.FFT_2D1D1D, 5), ("2d_2d", lgf.FFT_2D2D, 3),
+                            ("2d_1d_1d_mfma_t", lgf.FFT_2D1D1D_MFMA, 5)):
+        _, ms = lgf.fft_study(HEADLINE_DIMS, v, f, reps=20, lib=L)
+        b = passes * 2 * 64 * V
+        out[name] = {"ms": round(ms, 4), "passes": passes, "alg_bytes": b, "gbps": round(b / ms / 1e6, 1),
+                     "frac": round(b / ms / 1e6 / HBM_PEAK_GBPS, 4)}
+    out["2d_2d_faster_than_1d_x4"] = round(out["1d_x4"]["ms"] / out["2d_2d"]["ms"], 3)
+    out["2d_2d_faster_than_2d_1d_1d"] = round(out["2d_1d_1d"]["ms"] / out["2d_2d"]["ms"], 3)
+    out["mfma_t_vs_fft_t"] = round(out["2d_1d_1d"]["ms"] / out["2d_1d_1d_mfma_t"]["ms"], 3)
+    zt = kernels.get("zt_fft_scale", {})
+    out["iteration_zt_ms"] = round(zt.get("avg_us", 0.0) / 1e3, 4)
+    del f
+    print(f"# fft study 32^4: 1D x4 {out['1d_x4']['ms']} ms, 2D+1D+1D {out['2d_1d_1d']['ms']} ms, "
+          f"2D+2D {out['2d_2d']['ms']} ms, 2D+1D+1D with MFMA t {out['2d_1d_1d_mfma_t']['ms']} ms", file=sys.stderr,
+          flush=True)
+    return out
+
+
 def update_variants(L, U, torch):
     """16^4 seed 1: iterations and time to theta < 1e-15 over alpha, for the
     first-order update (the paper's) and the exact exponential; and plain
@@ -455,6 +489,8 @@ def main():
     ap.add_argument("--wilson-sample", action="store_true",
                     help="run only a 32^4 beta 6.0 Wilson-action generation (20 updates of one heatbath and four "
                          "overrelaxation sweeps) and its FP64 gauge fixing; no JSON; for profiling")
+    ap.add_argument("--fft-sample", action="store_true",
+                    help="run only the 32^4 FFT decomposition study and print its JSON; for profiling")
     ap.add_argument("--gen-workers", type=int, default=min(8, os.cpu_count() or 1),
                     help="worker processes for input generation (started before this program touches the GPU; "
                          "use 1 under a profiler, which sets up the GPU before this program starts)")
@@ -469,10 +505,12 @@ def main():
     import synth
 
     # ---- inputs, generated before this program touches the GPU -------------
-    extras = not (args.no_extras or args.pmc_sample or args.batch_sample or args.wilson_sample)
+    samples = args.pmc_sample or args.batch_sample or args.wilson_sample or args.fft_sample
+    extras = not (args.no_extras or samples)
     gw = args.gen_workers
     t = time.time()
-    U = None if (args.batch_sample or args.wilson_sample) else synth.random_links(HEADLINE_DIMS, args.seed, workers=gw)
+    U = None if (args.batch_sample or args.wilson_sample or args.fft_sample) else \
+        synth.random_links(HEADLINE_DIMS, args.seed, workers=gw)
     seeds32 = []
     small = med = None
     mixed16 = []
@@ -496,7 +534,7 @@ def main():
     cpu = None
     oracle_ttt = None
     oracle_F8 = None
-    if not args.no_cpu_baseline and not (args.pmc_sample or args.batch_sample or args.wilson_sample):
+    if not args.no_cpu_baseline and not samples:
         cpu = cpu_baseline(U, args.storage, HEADLINE_DIMS)
         print(f"# cpu baseline: {cpu['value']} iters/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
         if extras:
@@ -531,6 +569,9 @@ def main():
     if args.batch_sample:
         print(json.dumps(batch_run(L, batch_in[0], batch_in[1], torch)), flush=True)
         return
+    if args.fft_sample:
+        print(json.dumps(fft_study_32(L, torch, {})), flush=True)
+        return
     if args.wilson_sample:
         with lgf.WilsonGenerator(HEADLINE_DIMS, 6.0, 5001, lib=L) as g:
             g.update(20, 4)
@@ -556,6 +597,7 @@ def main():
         line_extra["small_8"] = small_8(L, small, torch, oracle_F8)
         line_extra["mixed_16"] = mixed_16(L, mixed16, torch)
         line_extra["update_variants"] = update_variants(L, med, torch)
+        line_extra["fft_study"] = fft_study_32(L, torch, kernels)
         if learned_fields:
             with open(model_path, "rb") as fh:
                 blob = fh.read()

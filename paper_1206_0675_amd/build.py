@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblgf.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lgf.hip", "batch.hip", "mlp.hip", "noalloc.hip", "wilson.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lgf.hip", "batch.hip", "mlp.hip", "noalloc.hip", "wilson.hip", "fft_study.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

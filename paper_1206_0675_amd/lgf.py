@@ -126,6 +126,7 @@ def load_library(path: str | None = None):
         "lgf_wilson_device_links": ([V], C.c_void_p),
         "lgf_wilson_skipped": ([V, C.POINTER(I64)], I32),
         "lgf_wilson_last_error": ([V], C.c_char_p),
+        "lgf_fft_study": ([C.POINTER(C.c_int32), I32, V, V, I32, I32, C.POINTER(C.c_double)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -541,3 +542,27 @@ class WilsonGenerator:
         n = C.c_int64()
         self._check(self.lib.lgf_wilson_skipped(self.h, C.byref(n)))
         return n.value
+
+
+# ---------------------------------------------------------------------------
+# FFT decomposition study (include/lgf_study.h)
+# ---------------------------------------------------------------------------
+FFT_1DX4, FFT_2D1D1D, FFT_2D2D, FFT_2D1D1D_MFMA = 0, 1, 2, 3
+
+
+def fft_study(dims, variant: int, fields, out=None, reps: int = 0, lib=None):
+    """(out, ms per filter): F^-1 (p2max/p^2) F / V of four complex fields in
+    the plain layout (4, Lt, Lz, Ly, Lx), by the given decomposition."""
+    L = lib or load_library()
+    if out is None:
+        out = np.empty_like(fields) if isinstance(fields, np.ndarray) else fields.new_empty(fields.shape)
+    pin, win, _k1 = _buffer(fields)
+    pout, wout, _k2 = _buffer(out)
+    if win != wout:
+        raise ValueError("fields and out must both be host or both be device memory")
+    ms = C.c_double()
+    d = (C.c_int32 * 4)(*[int(x) for x in dims])
+    rc = L.lgf_fft_study(d, int(variant), C.c_void_p(pin), C.c_void_p(pout), win, int(reps), C.byref(ms))
+    if rc != OK:
+        raise LgfError(rc, L.lgf_last_error(None).decode())
+    return out, ms.value

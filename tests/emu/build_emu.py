@@ -12,7 +12,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
-SRCS = [os.path.join(ROOT, "paper_1206_0675_amd", "csrc", f) for f in ("lgf.hip", "batch.hip", "mlp.hip", "noalloc.hip", "wilson.hip")]
+SRCS = [os.path.join(ROOT, "paper_1206_0675_amd", "csrc", f) for f in ("lgf.hip", "batch.hip", "mlp.hip", "noalloc.hip", "wilson.hip", "fft_study.hip")]
 
 
 def _inputs():

@@ -70,6 +70,27 @@ inline double __shfl(double v, int src_lane, int width = 64)
 }
 inline float __shfl(float v, int src_lane, int width = 64) { return (float)__shfl((double)v, src_lane, width); }
 
+// v_mfma_f64_16x16x4f64 of one wavefront: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; register j of lane l receives
+// C + sum_k A[r][k] B[k][c] for r = l / 16 + 4 j, c = l % 16.  Every lane of
+// the wavefront must call it (it exchanges values through __shfl).
+template <typename V>
+inline V __builtin_amdgcn_mfma_f64_16x16x4f64(double a, double b, V c, int, int, int)
+{
+    const int l = (int)(threadIdx.x & 63);
+    double av[4][4], bv[4];
+    for (int k = 0; k < 4; ++k) {
+        for (int j = 0; j < 4; ++j) av[k][j] = __shfl(a, k * 16 + (l >> 4) + 4 * j);
+        bv[k] = __shfl(b, k * 16 + (l & 15));
+    }
+    for (int j = 0; j < 4; ++j) {
+        double s = c[j];
+        for (int k = 0; k < 4; ++k) s += av[k][j] * bv[k];
+        c[j] = s;
+    }
+    return c;
+}
+
 inline long long __double_as_longlong(double d)
 {
     long long r;
@@ -131,6 +152,7 @@ inline hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
 inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { std::memmove(d, s, n); return hipSuccess; }
 inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { std::memmove(d, s, n); return hipSuccess; }
 inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) { std::memset(d, v, n); return hipSuccess; }
+inline hipError_t hipMemset(void* d, int v, size_t n) { std::memset(d, v, n); return hipSuccess; }
 inline hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = reinterpret_cast<hipStream_t>(0x1); return hipSuccess; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 inline hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }

@@ -416,3 +416,31 @@ def test_emulated_wilson_small_beta_and_errors(E, oracle_lib):
             lgf.WilsonGenerator(bad, 6.0, 1, lib=E)
     with pytest.raises(lgf.LgfError):
         lgf.WilsonGenerator((4, 4, 4, 4), -1.0, 1, lib=E)
+
+
+# ---------------------------------------------------------------------------
+# FFT decomposition study
+# ---------------------------------------------------------------------------
+def _pack(D):
+    """(..., 3, 3) Delta -> the four complex fields (4, ...) the filter runs on."""
+    return np.ascontiguousarray(np.stack([D[..., 0, 1], D[..., 0, 2], D[..., 1, 2],
+                                          D[..., 0, 0].imag + 1j * D[..., 1, 1].imag]))
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 16, 4), (4, 8, 4, 8), (4, 4, 4, 16), (4, 4, 4, 32)])
+def test_emulated_fft_study_matches_oracle_filter(E, oracle_lib, dims):
+    """The decompositions apply the oracle's filter (K real and even, so
+    filtering the packed fields is the packed filter of Delta); the matrix-core
+    t pass runs for Lt >= 16."""
+    U = synth.random_links(dims, 2)
+    _, _, delta = oracle.measure(dims, U)
+    ref = _pack(oracle.filter_delta(dims, delta))
+    f = _pack(delta)
+    variants = [lgf.FFT_1DX4, lgf.FFT_2D1D1D, lgf.FFT_2D2D] + ([lgf.FFT_2D1D1D_MFMA] if dims[3] >= 16 else [])
+    for v in variants:
+        out, _ = lgf.fft_study(dims, v, f, lib=E)
+        assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref)), v
+    with pytest.raises(lgf.LgfError):
+        lgf.fft_study((4, 4, 4, 128), 0, np.zeros((4, 128, 4, 4, 4), complex), lib=E)
+    with pytest.raises(lgf.LgfError):
+        lgf.fft_study(dims, 4, f, lib=E)
