@@ -18,6 +18,7 @@
 #include <cstring>
 #include <functional>
 #include <vector>
+#include <random>
 
 #define __global__
 #define __device__
@@ -313,7 +314,16 @@ void launch(K kernel, dim3 grid, dim3 block, size_t lds, Args... args)
     for (unsigned t = 0; t < nth; ++t)
         if (!fibers[t].stack) fibers[t].stack = static_cast<char*>(std::malloc(kFiberStack));
     body = [&] { kernel(args...); };
-    for (unsigned k = 0; k < nblk; ++k) {
+    // Block order: ascending, or (LGF_EMU_BLOCK_ORDER) reversed or shuffled,
+    // so a kernel whose result depends on the order of its blocks shows it.
+    std::vector<unsigned> order(nblk);
+    for (unsigned k = 0; k < nblk; ++k) order[k] = k;
+    if (const char* o = std::getenv("LGF_EMU_BLOCK_ORDER")) {
+        if (std::strcmp(o, "reverse") == 0) std::reverse(order.begin(), order.end());
+        else if (std::strcmp(o, "shuffle") == 0) std::shuffle(order.begin(), order.end(), std::mt19937(12345u + nblk));
+    }
+    for (unsigned kk = 0; kk < nblk; ++kk) {
+        const unsigned k = order[kk];
         bidx = dim3(k % grid.x, (k / grid.x) % grid.y, k / (grid.x * grid.y));
         std::memset(dyn_lds.data(), 0xff, dyn_lds.size());
         for (unsigned t = 0; t < nth; ++t) {
