@@ -29,8 +29,9 @@ resident in HBM.  Printed as one JSON line:
   wilson_32        the paper's workload class: Wilson-action fields at 32^4,
                    beta 5.8, 6.0, 6.2 (cold start, 102 updates of one heatbath
                    and four overrelaxation sweeps, all on the GPU), their
-                   plaquette and time to theta for FP64, mixed and learned;
-                   heatbath and overrelaxation sweep times with the
+                   plaquette and time to theta for FP64, mixed and learned
+                   (and an alpha sweep at beta 6.0); heatbath and
+                   overrelaxation sweep times with the
                    algorithmic bytes of a sweep (every link read and each
                    updated link written, per class launch)
   fft_study        32^4: the filter's 4D FFT as 1D x4, 2D+1D+1D and 2D+2D passes
@@ -345,6 +346,16 @@ def wilson_32(L, blob, torch):
                               "theta": s.theta, "F": s.F}
                 if "step" in kw:
                     rec[label]["fallbacks"] = s.fallbacks
+            if i == 1:
+                sweep = []
+                for alpha in (0.06, 0.07, 0.075, 0.08):
+                    with lgf.Context(HEADLINE_DIMS, lib=L, storage=12, max_iter=20000, alpha=alpha) as ctx:
+                        ctx.load_device(g.device_links)
+                        torch.cuda.synchronize()
+                        s = ctx.fix(raise_on_error=False)
+                    sweep.append({"alpha": alpha, "status": s.status, "iters": s.iter, "seconds": round(s.seconds, 4),
+                                  "F": s.F})
+                rec["alpha_sweep_fp64_12real"] = sweep
             out["runs"].append(rec)
             print(f"# wilson beta {beta}: P {rec['plaquette']}, FP64 {rec['fp64_12real']['iters']} iterations "
                   f"{rec['fp64_12real']['seconds']} s, mixed {rec['mixed_12real']['seconds']} s", file=sys.stderr,
