@@ -206,3 +206,29 @@ def test_committed_model_saves_iterations(L):
         it_plain += sp.iter
         it_learned += sq.iter
     assert it_learned <= 0.9 * it_plain, (it_learned, it_plain)
+
+
+def test_committed_model_full_size_properties(L):
+    """The learned step at 32^3 x 64 (the learned benchmark's shape) with the
+    committed model: the run reaches theta < 1e-15, the oracle's measure of
+    the stored links agrees with the GPU's F and theta, the plaquette is
+    unchanged (the links stay on the input's gauge orbit), and F matches the
+    plain step's to 1e-9."""
+    import os
+    dims = (32, 32, 32, 64)
+    announce("committed model at 32^3x64, seed 3000")
+    blob = open(os.path.join(os.path.dirname(lgf.__file__), "models", "learned_step.bin"), "rb").read()
+    U = synth.random_links(dims, 3000, workers=8)
+    with lgf.Context(dims, lib=L, storage=12, step=1) as q:
+        q.set_model(blob)
+        q.load(U)
+        sq = q.fix()
+        Uq = q.store()
+    with lgf.Context(dims, lib=L, storage=12) as p:
+        p.load(U)
+        sp = p.fix()
+    assert sq.theta < 1e-15 and sp.theta < 1e-15
+    Fo, tho, _ = oracle.measure(dims, Uq)
+    assert abs(Fo - sq.F) <= 1e-12 and tho < 1e-15
+    assert abs(oracle.plaquette(dims, Uq) - oracle.plaquette(dims, U)) <= 1e-12
+    assert abs(sq.F - sp.F) <= 1e-9
