@@ -842,14 +842,17 @@ __device__ void gauge_plane_2f(const Geo& geo, int q, const C2<T>* __restrict__ 
 // (cur flips).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void reduce_state(const double* __restrict__ partial, int nq, int64_t V, DevState* st,
-                             double* __restrict__ trace, int counts_update, double* red)
+                             double* __restrict__ trace, int counts_update, double* red, int nsum = 0)
 {
-    const int tid = threadIdx.x, nth = blockDim.x;
+    // the sums run over the first nsum threads (all of them when 0), so a
+    // larger block adds in the same order as a 256-thread k_reduce
+    const int tid = threadIdx.x, nth = nsum > 0 ? nsum : (int)blockDim.x;
     double a = 0.0, b = 0.0;
-    for (int i = tid; i < nq; i += nth) {
-        a += partial[2 * i];
-        b += partial[2 * i + 1];
-    }
+    if (tid < nth)
+        for (int i = tid; i < nq; i += nth) {
+            a += partial[2 * i];
+            b += partial[2 * i + 1];
+        }
     double fs, ts;
     block_sum2(a, b, red, tid, nth, &fs, &ts);
     if (tid == 0 && counts_update == 2) {          // candidate links of a learned step: no commit
@@ -1081,6 +1084,30 @@ __global__ void __launch_bounds__(512) k_zt(Geo geo, C2<T>* __restrict__ D, cons
 {
     if (st->done) return;
     HIP_DYNAMIC_SHARED(double, lds_raw)
+    int h, chunk;
+    zt_part_of_block(blockIdx.x, (geo.NP >> geo.logW) * 4, geo.logW - logWb, h, chunk);
+    zt_block<T, LMAX>(geo, chunk >> 2, chunk & 3, h, logWb, D, D, twz, twt, make_scale(geo, ptab, c0, accel),
+                      reinterpret_cast<C2<T>*>(lds_raw));
+}
+
+// k_zt preceded, in block 0, by the reduction of the F and theta partials of
+// the measure launched before it, committed as k_reduce with counts_update = 1
+// commits them.  Inside a captured chunk of updates, update n's reduction
+// thus runs in update n + 1's (z, t) launch instead of a launch of its own.
+// The blocks that start after block 0 has raised `done` return; those that
+// started before transform D all the same, so after a chunk that ends done D
+// no longer holds the Delta of the current links.  The sums run over 256
+// threads, as in k_reduce, so F and theta come out bit for bit the same.
+// LDS: at least 2 * 512 doubles for the reduction.
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(512) k_zt_reduce(Geo geo, C2<T>* __restrict__ D, const C2<T>* __restrict__ twz,
+                                                   const C2<T>* __restrict__ twt, const double* __restrict__ ptab,
+                                                   double c0, int accel, int logWb, DevState* st,
+                                                   const double* __restrict__ partial)
+{
+    if (st->done) return;
+    HIP_DYNAMIC_SHARED(double, lds_raw)
+    if (blockIdx.x == 0) reduce_state(partial, geo.NQ, geo.V, st, nullptr, 1, lds_raw, 256);
     int h, chunk;
     zt_part_of_block(blockIdx.x, (geo.NP >> geo.logW) * 4, geo.logW - logWb, h, chunk);
     zt_block<T, LMAX>(geo, chunk >> 2, chunk & 3, h, logWb, D, D, twz, twt, make_scale(geo, ptab, c0, accel),

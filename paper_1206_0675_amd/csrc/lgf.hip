@@ -98,6 +98,7 @@ struct lgf_context : Runner {
     hipGraphExec_t gexec_learned = nullptr;                  // poll_every learned updates
     // learned spectral step (FP64): model, band sums, factors, spare Delta buffers
     bool learned = false;
+    int chunk_pos = kUpdateAlone;   // where the next plain update sits in a captured chunk
     bool has_model = false;
     uint16_t* mw = nullptr;       // bf16 W1 | W2 | W3
     float* mb = nullptr;          // b1 | b2 | b3
@@ -191,7 +192,18 @@ int32_t enqueue_measure(lgf_context* c, double* trace_slot)
 template <typename T, int NE, int LMAX>
 int32_t enqueue_update(lgf_context* c, double* trace_slot)
 {
-    return enqueue_plain_update<T, NE, LMAX>(c, bufs<T>(c).geo, iter_args<T, NE, LMAX>(c), trace_slot);
+    return enqueue_plain_update<T, NE, LMAX>(c, bufs<T>(c).geo, iter_args<T, NE, LMAX>(c), trace_slot,
+                                             c->chunk_pos);
+}
+
+// The reduction that ends a captured chunk of plain updates (k_reduce,
+// counts_update 1, on the last update's partials).
+template <typename T, int NE, int LMAX>
+int32_t enqueue_chunk_end(lgf_context* c)
+{
+    const Geo& g = bufs<T>(c).geo;
+    return launch(c, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)c->partial, g.NQ, g.V, c->st,
+                  (double*)nullptr, 1);
 }
 
 // Kernel variant for the current phase, storage and longest lattice axis.
@@ -216,8 +228,14 @@ struct OpUpdate {
     static int32_t run(lgf_context* c, double* tr) { return enqueue_update<T, NE, LMAX>(c, tr); }
 };
 
+template <typename T, int NE, int LMAX>
+struct OpChunkEnd {
+    static int32_t run(lgf_context* c) { return enqueue_chunk_end<T, NE, LMAX>(c); }
+};
+
 int32_t measure_any(lgf_context* c, double* trace_slot) { return dispatch<OpMeasure>(c, trace_slot); }
 int32_t update_any(lgf_context* c, double* trace_slot) { return dispatch<OpUpdate>(c, trace_slot); }
+int32_t chunk_end_any(lgf_context* c) { return dispatch<OpChunkEnd>(c); }
 
 int32_t learned_update(lgf_context* c, double* trace_slot);
 
@@ -243,7 +261,14 @@ int32_t enqueue_chunk(lgf_context* c, int64_t n)
         if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = fail(c, LGF_E_DEVICE, "hipStreamBeginCapture failed");
         } else {
-            for (int64_t k = 0; k < n && rc == LGF_OK; ++k) rc = one_update(c);
+            // plain updates: each update's reduction runs in the next update's
+            // (z, t) launch, and one reduction ends the chunk
+            for (int64_t k = 0; k < n && rc == LGF_OK; ++k) {
+                if (!c->learned) c->chunk_pos = k == 0 ? kChunkFirst : kChunkNext;
+                rc = one_update(c);
+            }
+            c->chunk_pos = kUpdateAlone;
+            if (rc == LGF_OK && !c->learned) rc = chunk_end_any(c);
             const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
             if (rc == LGF_OK && e != hipSuccess) rc = fail(c, LGF_E_DEVICE, "hipStreamEndCapture failed");
         }
@@ -1027,10 +1052,17 @@ int32_t lgf_step(lgf_ctx c, int64_t n, lgf_stats* trace)
             TRY(sync_state(c));
             if (c->st_host->fallback) TRY(learned_update(c, tr ? tr + 2 * k : nullptr));   // the plain update
         }
+    } else if (!trace) {
+        // captured chunks of poll_every updates (as lgf_fix), then single updates
+        int64_t k = 0;
+        if (c->p.poll_every > 0)
+            for (; n - k >= c->p.poll_every; k += c->p.poll_every) TRY(enqueue_chunk(c, c->p.poll_every));
+        for (; k < n; ++k) TRY(update_any(c, nullptr));
     } else {
         for (int64_t k = 1; k <= n; ++k) TRY(update_any(c, tr ? tr + 2 * k : nullptr));
     }
     TRY(sync_state(c));
+    if (c->st_host->done) c->delta_valid = false;   // a chunk may have passed its last reduction
     if (c->st_host->nonfinite) return fail(c, LGF_E_NONFINITE, "theta became non-finite");
     if (trace) {
         std::vector<double> h(2 * (size_t)(n + 1));
@@ -1066,6 +1098,9 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
             TRY(enqueue_chunk(c, chunk));
             TRY(sync_state(c));
         }
+        // a captured chunk that ended done has transformed D after the last
+        // reduction (k_zt_reduce), so D no longer holds the current Delta
+        if (c->st_host->done) c->delta_valid = false;
         if (c->st_host->nonfinite) {
             fill_stats(c, out, LGF_E_NONFINITE, t0);
             return fail(c, LGF_E_NONFINITE, "theta became non-finite");

@@ -304,6 +304,8 @@ int32_t set_plane_lds(Runner* r, const Geo& g, int nth)
                           reinterpret_cast<const void*>(&k_gauge2f<T, NE, LMAX, true>)})
         HIPCHK(r, hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)(plane_lds_elems(g) * sizeof(C2<T>) / 2)));
+    HIPCHK(r, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt_reduce<T, LMAX>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsZt));
     HIPCHK(r, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zt<T, LMAX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)zt_lds<T>(g, g.logW)));
     return LGF_OK;
@@ -318,7 +320,8 @@ inline bool measure_once(const Geo& g) { return g.L[0] <= 64; }
 // current gauge G[cur]; next = 1: those of G[1 - cur] just formed.
 // counts_update as for reduce_state.
 template <typename T, int NE, int LMAX>
-int32_t enqueue_measure_k(Runner* r, const Geo& g, const IterArgs<T>& a, int next, double* trace, int counts_update)
+int32_t enqueue_measure_k(Runner* r, const Geo& g, const IterArgs<T>& a, int next, double* trace, int counts_update,
+                          bool reduce = true)
 {
     const int kid = next ? K_TRANSFORM_MEASURE : K_MEASURE;
     const size_t lds = measure_lds<T>(g, a.nth);
@@ -330,6 +333,7 @@ int32_t enqueue_measure_k(Runner* r, const Geo& g, const IterArgs<T>& a, int nex
         TRY(launch(r, kid, k_measure<T, NE, LMAX, false>, dim3(g.NQ), dim3(a.nth), lds, g, a.U, (const C2<T>*)a.G0,
                    (const C2<T>*)a.G1, next, a.D, a.D1, a.partial, a.tw[0], a.tw[1], (const DevState*)a.st,
                    BandJob{}));
+    if (!reduce) return LGF_OK;
     return launch(r, K_REDUCE, k_reduce<>, dim3(1), dim3(256), 0, (const double*)a.partial, g.NQ, g.V, a.st, trace,
                   counts_update);
 }
@@ -358,15 +362,26 @@ int32_t enqueue_plain_measure(Runner* r, const Geo& g, const IterArgs<T>& a, dou
 }
 
 // Filter ((z, t) FFT, spectral scale, inverse), g and G, then the Delta of
-// the new links; the reduction flips cur.
+// the new links; the reduction flips cur.  Within a captured chunk
+// (chunk_pos > 0) the new links' reduction is left to the next update's
+// (z, t) launch (k_zt_reduce, chunk_pos 2) or to the reduction that ends the
+// chunk; chunk_pos 1 is the chunk's first update, whose (z, t) launch has no
+// reduction to run.
+enum ChunkPos { kUpdateAlone = 0, kChunkFirst = 1, kChunkNext = 2 };
+
 template <typename T, int NE, int LMAX>
-int32_t enqueue_plain_update(Runner* r, const Geo& g, const IterArgs<T>& a, double* trace)
+int32_t enqueue_plain_update(Runner* r, const Geo& g, const IterArgs<T>& a, double* trace, int chunk_pos = kUpdateAlone)
 {
     const int l = zt_part_log<T>(g);
-    TRY(launch(r, K_ZT, k_zt<T, LMAX>, dim3(zt_blocks(g, l)), dim3(512), zt_lds<T>(g, l), g, a.D, a.tw[2], a.tw[3],
-               a.ptab, a.c0, a.accel, l, (const DevState*)a.st));
+    if (chunk_pos == kChunkNext)
+        TRY(launch(r, K_ZT, k_zt_reduce<T, LMAX>, dim3(zt_blocks(g, l)), dim3(512),
+                   std::max(zt_lds<T>(g, l), (size_t)(2 * 512 * sizeof(double))), g, a.D, a.tw[2], a.tw[3], a.ptab,
+                   a.c0, a.accel, l, a.st, (const double*)a.partial));
+    else
+        TRY(launch(r, K_ZT, k_zt<T, LMAX>, dim3(zt_blocks(g, l)), dim3(512), zt_lds<T>(g, l), g, a.D, a.tw[2],
+                   a.tw[3], a.ptab, a.c0, a.accel, l, (const DevState*)a.st));
     TRY((enqueue_gauge_k<T, NE, LMAX>(r, g, a)));
-    return enqueue_measure_k<T, NE, LMAX>(r, g, a, 1, trace, 1);
+    return enqueue_measure_k<T, NE, LMAX>(r, g, a, 1, trace, 1, chunk_pos == kUpdateAlone);
 }
 
 template <typename T>

@@ -444,3 +444,22 @@ def test_emulated_fft_study_matches_oracle_filter(E, oracle_lib, dims):
         lgf.fft_study((4, 4, 4, 128), 0, np.zeros((4, 128, 4, 4, 4), complex), lib=E)
     with pytest.raises(lgf.LgfError):
         lgf.fft_study(dims, 4, f, lib=E)
+
+
+@pytest.mark.parametrize("dims, kw", [((8, 8, 8, 8), {}), ((8, 8, 8, 8), {"precision": 2, "storage": 12}),
+                                      ((4, 8, 4, 8), {"poll_every": 4})])
+def test_emulated_captured_chunks_equal_single_updates(E, dims, kw):
+    """In a captured chunk each update's reduction runs in the next update's
+    (z, t) launch; the run must equal the one launched update by update, bit
+    for bit, and leave a context that measures the same."""
+    U = synth.random_links(dims, 5)
+    res = []
+    for ng in (0, 1):
+        with lgf.Context(dims, lib=E, no_graph=ng, **kw) as c:
+            c.load(U)
+            s = c.fix()
+            m = c.measure()
+            res.append((s.iter, s.F, s.theta, c.store(), m.F, m.theta))
+    a, b = res
+    assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2] and np.array_equal(a[3], b[3])
+    assert a[4] == b[4] and a[5] == b[5]

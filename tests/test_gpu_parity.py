@@ -355,3 +355,23 @@ def test_exact_exponential_fix(L, oracle_lib, dims, seed):
     mu, md = oracle.unitarity(Ug)
     assert mu <= 1e-12 and md <= 1e-12
     assert abs(oracle.plaquette(dims, Ug) - oracle.plaquette(dims, U)) <= 1e-12
+
+
+@pytest.mark.parametrize("dims, kw", [((16, 16, 16, 16), {}), ((16, 16, 16, 16), {"precision": lgf.MIXED}),
+                                      ((32, 32, 32, 32), {"storage": 12})])
+def test_captured_chunks_equal_single_updates(L, dims, kw):
+    """Captured chunks defer each update's reduction into the next update's
+    (z, t) launch; fix() must give the same bits as the run launched update by
+    update (no_graph), and a context that measures the same afterwards."""
+    print(f"\n[gpu] captured chunks vs single updates dims={dims} {kw}", flush=True)
+    U = synth.random_links(dims, 6, workers=8)
+    res = []
+    for ng in (0, 1):
+        with lgf.Context(dims, lib=L, no_graph=ng, **kw) as c:
+            c.load(U)
+            s = c.fix()
+            m = c.measure()
+            res.append((s.iter, s.F, s.theta, c.store(), m.F, m.theta))
+    a, b = res
+    assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2] and np.array_equal(a[3], b[3])
+    assert a[4] == b[4] and a[5] == b[5]
