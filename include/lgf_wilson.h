@@ -38,8 +38,9 @@
  * Conventions as lgf.h: return LGF_OK or a negative LGF_E_* code; the
  * canonical FP64 link layout; `where` is LGF_HOST or LGF_DEVICE.  Extents
  * must be even, in [2, 1024], with at most 2^31 sites (else
- * LGF_E_UNSUPPORTED_SHAPE).  The generator owns its device memory and its
- * stream; every call below returns with its device work finished.
+ * LGF_E_UNSUPPORTED_SHAPE).  The generator owns its device memory (two
+ * copies of the links, 1152 bytes per site) and its stream; every call below
+ * returns with its device work finished.
  */
 #ifndef LGF_WILSON_H
 #define LGF_WILSON_H
@@ -84,8 +85,14 @@ int32_t lgf_wilson_plaquette(lgf_wilson_t g, double *plaq);
 /* Copy the links out (canonical layout). */
 int32_t lgf_wilson_store(lgf_wilson_t g, void *links, int32_t where);
 
-/* Device address of the links (canonical layout), valid until the
- * generator is destroyed; e.g. for lgf_load_links(ctx, p, LGF_DEVICE). */
+/* Device address of the links in the canonical layout, valid until the
+ * generator is destroyed; e.g. for lgf_load_links(ctx, p, LGF_DEVICE).
+ * The sweeps work on a second, even-odd copy of the links; this call first
+ * rewrites the canonical copy from it when a sweep or cold start has changed
+ * the links since (one device pass, then a stream synchronisation), so the
+ * buffer holds the current links when the call returns and until the next
+ * sweep, update or cold start.  Returns NULL on a device error (message in
+ * lgf_wilson_last_error). */
 const void *lgf_wilson_device_links(lgf_wilson_t g);
 
 /* Subgroup steps skipped since creation (sampler out of attempts). */

@@ -63,6 +63,31 @@ __device__ __forceinline__ void store_link(double* __restrict__ U, int64_t l, co
     for (int k = 0; k < 9; ++k) p[k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
 }
 
+// The sweeps keep the links in an even-odd layout of separate matrix
+// elements: element k of link (site s, direction mu) at
+// E[((mu * 9 + k) * 2 + parity(s)) * Vh + s / 2] (Vh = V / 2; s / 2 numbers
+// the sites of one parity, x fastest, since Lx is even).  The threads of a
+// class launch take consecutive s / 2, so every load and store of a link
+// element is one contiguous run across the wavefront.
+__device__ __forceinline__ M load_eo(const double2* __restrict__ E, int64_t Vh, int64_t s, int mu, int par)
+{
+    const double2* p = E + ((int64_t)(mu * 9) * 2 + par) * Vh + (s >> 1);
+    M m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double2 v = p[(int64_t)k * 2 * Vh];
+        m.e[k / 3][k % 3] = Cx{v.x, v.y};
+    }
+    return m;
+}
+
+__device__ __forceinline__ void store_eo(double2* __restrict__ E, int64_t Vh, int64_t s, int mu, int par, const M& m)
+{
+    double2* p = E + ((int64_t)(mu * 9) * 2 + par) * Vh + (s >> 1);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) p[(int64_t)k * 2 * Vh] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+}
+
 // a b with the dagger taken of a (da) and/or b (db); each element summed over
 // k = 0, 1, 2 in order
 template <bool DA, bool DB>
@@ -199,10 +224,11 @@ __device__ __forceinline__ int64_t site_of(const WGeo& g, int x, int y, int z, i
 // one (direction, parity) class of links
 // ---------------------------------------------------------------------------
 template <int KIND>
-__global__ void __launch_bounds__(256) k_wilson_links(WGeo g, double* __restrict__ U, double beta, uint64_t seed,
+__global__ void __launch_bounds__(256) k_wilson_links(WGeo g, double2* __restrict__ E, double beta, uint64_t seed,
                                                       uint64_t sweep, int mu, int par,
                                                       unsigned long long* __restrict__ skipped)
 {
+    const int64_t Vh = g.V / 2;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.V / 2) return;
     // the idx-th site of parity par, x fastest
@@ -232,16 +258,16 @@ __global__ void __launch_bounds__(256) k_wilson_links(WGeo g, double* __restrict
         if (nu == mu) continue;
         const int64_t xm = nb(mu, 1, -1, 0), xn = nb(nu, 1, -1, 0), xmn = nb(mu, 1, nu, -1), xdn = nb(nu, -1, -1, 0);
         M up, dn;
-        {
-            const M a = load_link(U, xm * 4 + nu), b = load_link(U, xn * 4 + mu);
+        {   // x + mu and x + nu have the other parity, x - nu too, x + mu - nu this one
+            const M a = load_eo(E, Vh, xm, nu, par ^ 1), b = load_eo(E, Vh, xn, mu, par ^ 1);
             const M ab = mul<false, true>(a, b);
-            const M cc = load_link(U, s * 4 + nu);
+            const M cc = load_eo(E, Vh, s, nu, par);
             up = mul<false, true>(ab, cc);
         }
         {
-            const M e = load_link(U, xmn * 4 + nu), f = load_link(U, xdn * 4 + mu);
+            const M e = load_eo(E, Vh, xmn, nu, par), f = load_eo(E, Vh, xdn, mu, par ^ 1);
             const M ef = mul<true, true>(e, f);
-            const M gg = load_link(U, xdn * 4 + nu);
+            const M gg = load_eo(E, Vh, xdn, nu, par ^ 1);
             dn = mul<false, false>(ef, gg);
         }
 #pragma unroll
@@ -250,7 +276,7 @@ __global__ void __launch_bounds__(256) k_wilson_links(WGeo g, double* __restrict
             for (int j = 0; j < 3; ++j) A.e[i][j] = cadd(A.e[i][j], cadd(up.e[i][j], dn.e[i][j]));
     }
     const int64_t l = s * 4 + mu;
-    M u = load_link(U, l);
+    M u = load_eo(E, Vh, s, mu, par);
     M w = mul<false, false>(u, A);
     unsigned nskip = 0;
 #pragma unroll
@@ -281,28 +307,54 @@ __global__ void __launch_bounds__(256) k_wilson_links(WGeo g, double* __restrict
         rotate_rows(w, i, j, r);
     }
     project_su3(u);
-    store_link(U, l, u);
+    store_eo(E, Vh, s, mu, par, u);
     if (nskip) atomicAdd(skipped, (unsigned long long)nskip);
 }
 
-// All links 1.
-__global__ void k_wilson_cold(double* __restrict__ U, int64_t nlinks)
+__device__ __forceinline__ int parity_of(const WGeo& g, int64_t s)
+{
+    int p = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        p += (int)(s % g.L[m]);
+        s /= g.L[m];
+    }
+    return p & 1;
+}
+
+// All links 1 (even-odd layout).
+__global__ void k_wilson_cold(WGeo g, double2* __restrict__ E)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= nlinks) return;
+    if (l >= g.V * 4) return;
+    const int64_t s = l >> 2;
+    const int mu = (int)(l & 3);
     M m;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) m.e[i][j] = Cx{i == j ? 1.0 : 0.0, 0.0};
-    store_link(U, l, m);
+    store_eo(E, g.V / 2, s, mu, parity_of(g, s), m);
+}
+
+// Canonical links U <-> even-odd links E, one thread per link.
+template <bool TO_EO>
+__global__ void k_wilson_layout(WGeo g, double* __restrict__ U, double2* __restrict__ E)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= g.V * 4) return;
+    const int64_t s = l >> 2;
+    const int mu = (int)(l & 3), par = parity_of(g, s);
+    if (TO_EO) store_eo(E, g.V / 2, s, mu, par, load_link(U, l));
+    else store_link(U, l, load_eo(E, g.V / 2, s, mu, par));
 }
 
 // Per block: the sum over its sites (one per thread) of the six plaquettes'
 // Re Tr, in a fixed order; partial[block].
-__global__ void __launch_bounds__(256) k_wilson_plaquette(WGeo g, const double* __restrict__ U,
+__global__ void __launch_bounds__(256) k_wilson_plaquette(WGeo g, const double2* __restrict__ E,
                                                           double* __restrict__ partial)
 {
+    const int64_t Vh = g.V / 2;
     __shared__ double red[256];
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
@@ -314,6 +366,7 @@ __global__ void __launch_bounds__(256) k_wilson_plaquette(WGeo g, const double* 
             c[m] = (int)(r % g.L[m]);
             r /= g.L[m];
         }
+        const int par = (c[0] + c[1] + c[2] + c[3]) & 1;
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu)
 #pragma unroll 1
@@ -324,11 +377,11 @@ __global__ void __launch_bounds__(256) k_wilson_plaquette(WGeo g, const double* 
                 q[mu] = c[mu];
                 q[nu] = (q[nu] + 1) % g.L[nu];
                 const int64_t xn = site_of(g, q[0], q[1], q[2], q[3]);
-                const M a = load_link(U, s * 4 + mu), b = load_link(U, xm * 4 + nu);
+                const M a = load_eo(E, Vh, s, mu, par), b = load_eo(E, Vh, xm, nu, par ^ 1);
                 const M ab = mul<false, false>(a, b);
-                const M cc = load_link(U, xn * 4 + mu);
+                const M cc = load_eo(E, Vh, xn, mu, par ^ 1);
                 const M abc = mul<false, true>(ab, cc);
-                const M d = load_link(U, s * 4 + nu);
+                const M d = load_eo(E, Vh, s, nu, par);
                 // Re Tr(abc d^dag) = sum_ij Re(abc_ij conj(d_ij))
                 double tr = 0.0;
 #pragma unroll
@@ -372,7 +425,9 @@ struct lgf_wilson_gen : lgf::rt::Runner {
     double beta = 0.0;
     uint64_t seed = 0;
     uint64_t next_sweep = 0;
-    double* U = nullptr;
+    double* U = nullptr;      // canonical links, for load, store and hand-off
+    double2* E = nullptr;     // even-odd links, what the sweeps work on
+    bool canon = true;        // U holds the links of E
     double* partial = nullptr;
     double* out = nullptr;
     unsigned long long* skipped = nullptr;
@@ -397,11 +452,12 @@ int32_t sweep_once(lgf_wilson_gen* w, int kind)
         for (int p = 0; p < 2; ++p) {
             if (kind == LGF_WILSON_HEATBATH)
                 TRY(lgf::rt::launch(w, lgf::rt::K_HEATBATH, k_wilson_links<LGF_WILSON_HEATBATH>, grid, block, 0, w->g,
-                                    w->U, w->beta, w->seed, num, mu, p, w->skipped));
+                                    w->E, w->beta, w->seed, num, mu, p, w->skipped));
             else
                 TRY(lgf::rt::launch(w, lgf::rt::K_OVERRELAX, k_wilson_links<LGF_WILSON_OVERRELAX>, grid, block, 0,
-                                    w->g, w->U, w->beta, w->seed, num, mu, p, w->skipped));
+                                    w->g, w->E, w->beta, w->seed, num, mu, p, w->skipped));
         }
+    w->canon = false;
     if (kind == LGF_WILSON_HEATBATH) ++w->next_sweep;
     return LGF_OK;
 }
@@ -410,14 +466,27 @@ int32_t cold(lgf_wilson_gen* w)
 {
     const int64_t nl = w->g.V * 4;
     TRY(lgf::rt::launch(w, lgf::rt::K_LOAD, k_wilson_cold, dim3((unsigned)lgf::rt::blocks_for(nl, 256)), dim3(256), 0,
-                        w->U, nl));
+                        w->g, w->E));
+    w->canon = false;
     w->next_sweep = 0;
     return sync(w);
 }
 
+// Rewrites U from E when a sweep or cold start has changed the links.
+int32_t to_canonical(lgf_wilson_gen* w)
+{
+    if (w->canon) return LGF_OK;
+    const int64_t nl = w->g.V * 4;
+    TRY(lgf::rt::launch(w, lgf::rt::K_STORE, k_wilson_layout<false>, dim3((unsigned)lgf::rt::blocks_for(nl, 256)),
+                        dim3(256), 0, w->g, w->U, w->E));
+    TRY(sync(w));
+    w->canon = true;
+    return LGF_OK;
+}
+
 void release(lgf_wilson_gen* w)
 {
-    for (void* p : {(void*)w->U, (void*)w->partial, (void*)w->out, (void*)w->skipped})
+    for (void* p : {(void*)w->U, (void*)w->E, (void*)w->partial, (void*)w->out, (void*)w->skipped})
         if (p) (void)hipFree(p);
     lgf::rt::release_events(w);
     if (w->stream) (void)hipStreamDestroy(w->stream);
@@ -454,6 +523,7 @@ int32_t lgf_wilson_create(const int32_t dims[4], double beta, uint64_t seed, lgf
     };
     chk(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking), "hipStreamCreateWithFlags");
     chk(hipMalloc(&w->U, sizeof(double) * 72 * (size_t)V), "hipMalloc(links)");
+    chk(hipMalloc(&w->E, sizeof(double) * 72 * (size_t)V), "hipMalloc(even-odd links)");
     chk(hipMalloc(&w->partial, sizeof(double) * (size_t)w->nblk_plaq), "hipMalloc(partial)");
     chk(hipMalloc(&w->out, sizeof(double)), "hipMalloc(out)");
     chk(hipMalloc(&w->skipped, sizeof(unsigned long long)), "hipMalloc(counter)");
@@ -491,8 +561,12 @@ int32_t lgf_wilson_load(lgf_wilson_t w, const void* links, int32_t where)
     if (!w) return LGF_E_INVALID_ARG;
     if (!links || (where != LGF_HOST && where != LGF_DEVICE))
         return fail(w, LGF_E_INVALID_ARG, "links must not be NULL; where is LGF_HOST or LGF_DEVICE");
+    const int64_t nl = w->g.V * 4;
     HIPCHK(w, hipMemcpyAsync(w->U, links, sizeof(double) * 72 * (size_t)w->g.V,
                              where == LGF_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, w->stream));
+    TRY(lgf::rt::launch(w, lgf::rt::K_LOAD, k_wilson_layout<true>, dim3((unsigned)lgf::rt::blocks_for(nl, 256)),
+                        dim3(256), 0, w->g, w->U, w->E));
+    w->canon = true;
     return sync(w);
 }
 
@@ -535,7 +609,7 @@ int32_t lgf_wilson_plaquette(lgf_wilson_t w, double* plaq)
 {
     if (!w || !plaq) return LGF_E_INVALID_ARG;
     TRY(lgf::rt::launch(w, lgf::rt::K_PLAQUETTE, k_wilson_plaquette, dim3((unsigned)w->nblk_plaq), dim3(256), 0, w->g,
-                        (const double*)w->U, w->partial));
+                        (const double2*)w->E, w->partial));
     TRY(lgf::rt::launch(w, lgf::rt::K_PLAQUETTE, k_wilson_plaquette_final, dim3(1), dim3(256), 0,
                         (const double*)w->partial, w->nblk_plaq, w->g.V, w->out));
     HIPCHK(w, hipMemcpyAsync(plaq, w->out, sizeof(double), hipMemcpyDeviceToHost, w->stream));
@@ -547,12 +621,17 @@ int32_t lgf_wilson_store(lgf_wilson_t w, void* links, int32_t where)
     if (!w) return LGF_E_INVALID_ARG;
     if (!links || (where != LGF_HOST && where != LGF_DEVICE))
         return fail(w, LGF_E_INVALID_ARG, "links must not be NULL; where is LGF_HOST or LGF_DEVICE");
+    TRY(to_canonical(w));
     HIPCHK(w, hipMemcpyAsync(links, w->U, sizeof(double) * 72 * (size_t)w->g.V,
                              where == LGF_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, w->stream));
     return sync(w);
 }
 
-const void* lgf_wilson_device_links(lgf_wilson_t w) { return w ? w->U : nullptr; }
+const void* lgf_wilson_device_links(lgf_wilson_t w)
+{
+    if (!w) return nullptr;
+    return to_canonical(w) == LGF_OK ? w->U : nullptr;
+}
 
 int32_t lgf_wilson_skipped(lgf_wilson_t w, int64_t* n)
 {

@@ -535,8 +535,12 @@ class WilsonGenerator:
 
     @property
     def device_links(self) -> int:
-        """Device address of the links (canonical layout), for Context.load_device."""
-        return self.lib.lgf_wilson_device_links(self.h)
+        """Device address of the links (canonical layout), for Context.load_device;
+        holds the links of the last sweep, cold start or load."""
+        p = self.lib.lgf_wilson_device_links(self.h)
+        if not p:
+            raise LgfError(E_DEVICE, self.lib.lgf_wilson_last_error(self.h).decode())
+        return p
 
     def skipped(self) -> int:
         n = C.c_int64()

@@ -6,6 +6,7 @@ launch sequencing without a GPU, so layout and bounds mistakes are caught
 before a GPU run; the GPU parity tests repeat the comparison on the MI355X.
 One case also runs under AddressSanitizer.
 """
+import ctypes
 import os
 import subprocess
 import sys
@@ -395,6 +396,13 @@ def test_emulated_wilson_generator_matches_oracle(E, oracle_lib, dims):
         g.update(2, 2)
         Uo, _ = owil.generate(dims, Uo, 5.9, 77, 1, 2, 2)
         assert np.max(np.abs(g.store() - Uo)) <= 1e-13
+        # the hand-off buffer (emulated device memory is host memory) is
+        # rewritten from the sweeps' even-odd copy
+        g.sweep(lgf.OVERRELAX)
+        Uo, _ = owil.sweep(dims, Uo, 5.9, 77, 3, owil.OVERRELAX)
+        n = 2 * Uo.size
+        Ud = np.ctypeslib.as_array((ctypes.c_double * n).from_address(g.device_links))
+        assert np.max(np.abs(Ud.view(np.complex128).reshape(Uo.shape) - Uo)) <= 1e-13
         if dims == (4, 4, 4, 4):
             assert abs(g.plaquette() - oracle.plaquette(dims, Uo)) <= 1e-14
         g.cold()
