@@ -38,8 +38,9 @@
  * Conventions as lgf.h: return LGF_OK or a negative LGF_E_* code; the
  * canonical FP64 link layout; `where` is LGF_HOST or LGF_DEVICE.  Extents
  * must be even, in [2, 1024], with at most 2^31 sites (else
- * LGF_E_UNSUPPORTED_SHAPE).  The generator owns its device memory (two
- * copies of the links, 1152 bytes per site) and its stream; every call below
+ * LGF_E_UNSUPPORTED_SHAPE).  The generator owns its device memory (the
+ * links twice: 576 bytes per site in the canonical layout, 384 in the sweeps'
+ * two-row layout) and its stream; every call below
  * returns with its device work finished.
  */
 #ifndef LGF_WILSON_H
@@ -65,7 +66,12 @@ int32_t lgf_wilson_destroy(lgf_wilson_t g);
 /* All links 1 and the heatbath sweep counter 0. */
 int32_t lgf_wilson_cold(lgf_wilson_t g);
 
-/* Replace the links (canonical layout, copied; not checked for unitarity). */
+/* Replace the links (canonical layout, copied; not checked for unitarity).
+ * The sweeps and the plaquette keep rows 0 and 1 of each link and rebuild
+ * row 2 as the complex conjugate of their cross product, which for SU(3)
+ * links is the same matrix up to rounding; until the next sweep or cold
+ * start, lgf_wilson_store and lgf_wilson_device_links return the loaded
+ * links as they were given. */
 int32_t lgf_wilson_load(lgf_wilson_t g, const void *links, int32_t where);
 
 /* One sweep: LGF_WILSON_HEATBATH (numbered by the sweep counter, which then

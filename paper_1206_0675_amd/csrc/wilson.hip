@@ -63,29 +63,46 @@ __device__ __forceinline__ void store_link(double* __restrict__ U, int64_t l, co
     for (int k = 0; k < 9; ++k) p[k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
 }
 
+// Row 2 of an SU(3) matrix from rows 0 and 1: the complex conjugate of
+// their cross product (the last step of project_su3).
+__device__ __forceinline__ void third_row(M& m)
+{
+    const Cx* a = m.e[0];
+    const Cx* b = m.e[1];
+    m.e[2][0] = cconj(csub(cmul(a[1], b[2]), cmul(a[2], b[1])));
+    m.e[2][1] = cconj(csub(cmul(a[2], b[0]), cmul(a[0], b[2])));
+    m.e[2][2] = cconj(csub(cmul(a[0], b[1]), cmul(a[1], b[0])));
+}
+
 // The sweeps keep the links in an even-odd layout of separate matrix
-// elements: element k of link (site s, direction mu) at
-// E[((mu * 9 + k) * 2 + parity(s)) * Vh + s / 2] (Vh = V / 2; s / 2 numbers
-// the sites of one parity, x fastest, since Lx is even).  The threads of a
-// class launch take consecutive s / 2, so every load and store of a link
-// element is one contiguous run across the wavefront.
+// elements, rows 0 and 1 only: element k < 6 (row k / 3, column k % 3) of
+// link (site s, direction mu) at E[((mu * 6 + k) * 2 + parity(s)) * Vh + s / 2]
+// (Vh = V / 2; s / 2 numbers the sites of one parity, x fastest, since Lx is
+// even), and row 2 is rebuilt on load.  Every link a sweep writes has just
+// been projected to SU(3), whose row 2 is that same function of rows 0 and 1.
+// The threads of a class launch take consecutive s / 2, so every load and
+// store of a link element is one contiguous run across the wavefront.
+constexpr int kEoElems = 6;
+
 __device__ __forceinline__ M load_eo(const double2* __restrict__ E, int64_t Vh, int64_t s, int mu, int par)
 {
-    const double2* p = E + ((int64_t)(mu * 9) * 2 + par) * Vh + (s >> 1);
+    const double2* p = E + ((int64_t)(mu * kEoElems) * 2 + par) * Vh + (s >> 1);
     M m;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
+    for (int k = 0; k < kEoElems; ++k) {
         const double2 v = p[(int64_t)k * 2 * Vh];
         m.e[k / 3][k % 3] = Cx{v.x, v.y};
     }
+    third_row(m);
     return m;
 }
 
 __device__ __forceinline__ void store_eo(double2* __restrict__ E, int64_t Vh, int64_t s, int mu, int par, const M& m)
 {
-    double2* p = E + ((int64_t)(mu * 9) * 2 + par) * Vh + (s >> 1);
+    double2* p = E + ((int64_t)(mu * kEoElems) * 2 + par) * Vh + (s >> 1);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) p[(int64_t)k * 2 * Vh] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+    for (int k = 0; k < kEoElems; ++k)
+        p[(int64_t)k * 2 * Vh] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
 }
 
 // a b with the dagger taken of a (da) and/or b (db); each element summed over
@@ -210,9 +227,7 @@ __device__ __forceinline__ void project_su3(M& m)
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) b[j] = Cx{b[j].re / nb, b[j].im / nb};
-    m.e[2][0] = cconj(csub(cmul(a[1], b[2]), cmul(a[2], b[1])));
-    m.e[2][1] = cconj(csub(cmul(a[2], b[0]), cmul(a[0], b[2])));
-    m.e[2][2] = cconj(csub(cmul(a[0], b[1]), cmul(a[1], b[0])));
+    third_row(m);
 }
 
 __device__ __forceinline__ int64_t site_of(const WGeo& g, int x, int y, int z, int t)
@@ -523,7 +538,7 @@ int32_t lgf_wilson_create(const int32_t dims[4], double beta, uint64_t seed, lgf
     };
     chk(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking), "hipStreamCreateWithFlags");
     chk(hipMalloc(&w->U, sizeof(double) * 72 * (size_t)V), "hipMalloc(links)");
-    chk(hipMalloc(&w->E, sizeof(double) * 72 * (size_t)V), "hipMalloc(even-odd links)");
+    chk(hipMalloc(&w->E, sizeof(double2) * 4 * kEoElems * (size_t)V), "hipMalloc(even-odd links)");
     chk(hipMalloc(&w->partial, sizeof(double) * (size_t)w->nblk_plaq), "hipMalloc(partial)");
     chk(hipMalloc(&w->out, sizeof(double)), "hipMalloc(out)");
     chk(hipMalloc(&w->skipped, sizeof(unsigned long long)), "hipMalloc(counter)");
