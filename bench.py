@@ -306,7 +306,8 @@ def wilson_32(L, blob, torch):
     """Wilson-action fields at 32^4 from the GPU generator, then gauge fixing."""
     from paper_1206_0675_amd import lgf
     V = vol(HEADLINE_DIMS)
-    sweep_bytes = 8 * (4 * V + V // 2) * 144          # 8 class launches: read all links, write half of one direction
+    sweep_bytes = 8 * (4 * V + V // 2) * 96           # 8 class launches: read all links, write half of one direction
+    #                                                   (rows 0 and 1 of each link, as the sweeps store them)
     out = {"dims": list(HEADLINE_DIMS), "updates": 102, "or_per_update": 4, "runs": []}
     for i, beta in enumerate((5.8, 6.0, 6.2)):
         with lgf.WilsonGenerator(HEADLINE_DIMS, beta, 5000 + i, lib=L) as g:
