@@ -117,3 +117,25 @@ def test_generated_field_is_gauge_fixed(L):
     assert st.theta < 1e-15 and st.iter > 200
     assert abs(oracle.plaquette(dims, Uf) - P) <= 1e-12
     assert oracle.measure(dims, Uf)[1] < 1e-15
+
+
+def test_hand_off_of_loaded_and_swept_links(L):
+    """The sweeps keep rows 0 and 1 of each link and rebuild row 2; the
+    canonical copy behind store and the device hand-off holds the loaded
+    links unchanged until a sweep, then the swept ones."""
+    dims = (4, 4, 4, 8)
+    announce("wilson hand-off of loaded and swept links")
+    U = synth.random_links(dims, 6)
+    with lgf.WilsonGenerator(dims, 6.0, 3, lib=L) as g:
+        g.load(U)
+        assert np.array_equal(g.store(), U)
+        with lgf.Context(dims, lib=L, storage=18) as c:
+            c.load_device(g.device_links)
+            assert np.max(np.abs(c.store() - U)) <= 1e-15
+        g.sweep(lgf.OVERRELAX)
+        Ug = g.store()
+        Uo, _ = owil.sweep(dims, U, 6.0, 3, 0, owil.OVERRELAX)
+        assert np.max(np.abs(Ug - Uo)) <= 1e-12
+        with lgf.Context(dims, lib=L, storage=18) as c:
+            c.load_device(g.device_links)
+            assert np.max(np.abs(c.store() - Ug)) <= 1e-15
