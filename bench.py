@@ -30,16 +30,21 @@ resident in HBM.  Printed as one JSON line:
                    beta 5.8, 6.0, 6.2 (cold start, 102 updates of one heatbath
                    and four overrelaxation sweeps, all on the GPU), their
                    plaquette and time to theta for FP64, mixed and learned
-                   (and an alpha sweep at beta 6.0); heatbath and
+                   (and an alpha sweep at beta 6.0), then three more fields
+                   per beta in FP64 (four per beta, as in Table 3); heatbath and
                    overrelaxation sweep times with the
                    algorithmic bytes of a sweep (every link read and each
                    updated link written, per class launch)
   fft_study        32^4: the filter's 4D FFT as 1D x4, 2D+1D+1D and 2D+2D passes
                    over HBM, and 2D+1D+1D with the t DFTs on the matrix cores
                    (lgf_fft_study), ms per application
+  rate_repeats     five more timed runs of K iterations: median, min, max
+  copy_ceiling     a 1 GiB device copy's GB/s, and the transform kernel's and
+                   the iteration's algorithmic GB/s as fractions of it
   cpu_baseline     the FP64 oracle on this host's cores, a bounded sample of
                    the headline workload; oracle_time_to_theta: full oracle
-                   runs at 8^4 and 16^4 with all cores and with one
+                   runs at 8^4, 16^4 and 32^4 with all cores, and at 8^4 with
+                   one (16^4 per iteration)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -142,9 +147,11 @@ def fix_runs(ctx, U, tries, torch):
     return min(runs, key=lambda r: r.seconds), runs[0]
 
 
-def rate_and_kernels(L, dims, U, steps, warmup, torch, **kw):
+def rate_and_kernels(L, dims, U, steps, warmup, torch, repeats=0, **kw):
     """Iteration rate over `steps` plain lgf_step iterations, then a profiled
-    pass with per-kernel mean durations (HIP events)."""
+    pass with per-kernel mean durations (HIP events).  With repeats > 0 the
+    shape also carries the rates of that many further timed runs of `steps`
+    (median, min, max), beside the one timed region the rate comes from."""
     from paper_1206_0675_amd import lgf
     with lgf.Context(dims, lib=L, **kw) as ctx:
         shape = dict(zip(("plane_threads", "tile_bytes"), ctx.config()))
@@ -155,6 +162,16 @@ def rate_and_kernels(L, dims, U, steps, warmup, torch, **kw):
         ctx.step(steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        if repeats:
+            rates = []
+            for _ in range(repeats):
+                t1 = time.perf_counter()
+                ctx.step(steps)
+                torch.cuda.synchronize()
+                rates.append(steps / (time.perf_counter() - t1))
+            rates.sort()
+            shape["repeats"] = {"n": repeats, "median_iters_per_s": round(rates[len(rates) // 2], 2),
+                                "min": round(rates[0], 2), "max": round(rates[-1], 2)}
     with lgf.Context(dims, lib=L, profile=1, **kw) as ctx:
         ctx.load(U)
         ctx.step(warmup)
@@ -357,6 +374,20 @@ def wilson_32(L, blob, torch):
                     sweep.append({"alpha": alpha, "status": s.status, "iters": s.iter, "seconds": round(s.seconds, 4),
                                   "F": s.F})
                 rec["alpha_sweep_fp64_12real"] = sweep
+            # three more fields at this beta (Table 3 has four per beta), FP64 only
+            more = []
+            for k in range(3):
+                seed = 5100 + 10 * i + k
+                with lgf.WilsonGenerator(HEADLINE_DIMS, beta, seed, lib=L) as g2:
+                    g2.update(102, 4)
+                    P2 = g2.plaquette()
+                    with lgf.Context(HEADLINE_DIMS, lib=L, max_iter=100000, storage=12) as ctx:
+                        ctx.load_device(g2.device_links)
+                        torch.cuda.synchronize()
+                        s = ctx.fix(raise_on_error=False)
+                more.append({"seed": seed, "plaquette": round(P2, 6), "status": s.status, "iters": s.iter,
+                             "seconds": round(s.seconds, 4), "F": s.F})
+            rec["more_fields_fp64_12real"] = more
             out["runs"].append(rec)
             print(f"# wilson beta {beta}: P {rec['plaquette']}, FP64 {rec['fp64_12real']['iters']} iterations "
                   f"{rec['fp64_12real']['seconds']} s, mixed {rec['mixed_12real']['seconds']} s", file=sys.stderr,
@@ -446,7 +477,28 @@ def cpu_baseline(U, R, dims):
                       f"{t_a + t_b:.1f}s of CPU work"}
 
 
-def oracle_time_to_theta(small, med):
+def copy_ceiling(torch, mib=1024, reps=5):
+    """GB/s (bytes read + written) of a plain device-to-device copy of `mib`
+    MiB, best of `reps`, timed with events on torch's stream, which the copy
+    runs on: the stream-copy ceiling the kernels are set against."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return {"mib": mib, "gbps": round(2 * n * 8 / (best * 1e-3) / 1e9, 1)}
+
+
+def oracle_time_to_theta(small, med, big=None):
     import oracle
     nproc = oracle.threads()
     out = {"nproc": nproc}
@@ -457,7 +509,10 @@ def oracle_time_to_theta(small, med):
         out["cpu_model"] = model
     except OSError:
         pass
-    for label, dims, U in (("8^4", SMALL_DIMS, small), ("16^4", MIXED16_DIMS, med)):
+    cases = [("8^4", SMALL_DIMS, small), ("16^4", MIXED16_DIMS, med)]
+    if big is not None:
+        cases.append(("x".join(map(str, HEADLINE_DIMS)), HEADLINE_DIMS, big))
+    for label, dims, U in cases:
         t = time.perf_counter()
         _, it, F, th, ok, _ = oracle.fix(dims, U)
         out[label] = {"threads": nproc, "seconds": round(time.perf_counter() - t, 3), "iters": it, "F": F,
@@ -550,7 +605,7 @@ def main():
         cpu = cpu_baseline(U, args.storage, HEADLINE_DIMS)
         print(f"# cpu baseline: {cpu['value']} iters/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
         if extras:
-            oracle_ttt = oracle_time_to_theta(small, med)
+            oracle_ttt = oracle_time_to_theta(small, med, U)
             oracle_F8 = oracle_ttt["8^4"]["F"]
     elif extras:
         import oracle
@@ -596,9 +651,11 @@ def main():
 
     # ---- headline: timed iterations, then the profiled pass ---------------
     iters_per_s, t_it, prof, launch_shape = rate_and_kernels(L, HEADLINE_DIMS, U, args.steps, args.warmup, torch,
-                                                             storage=R)
+                                                             repeats=5 if extras else 0, storage=R)
+    repeats = launch_shape.pop("repeats", None)
     print(f"# {args.steps} iterations at {t_it * 1e3:.4f} ms", file=sys.stderr, flush=True)
     kernels = kernel_table(prof, ab)
+    copy = copy_ceiling(torch)
     dom = kernels["transform_measure"]
     traffic = measured_traffic("transform_measure", HEADLINE_DIMS, R)
 
@@ -651,6 +708,9 @@ def main():
         "iteration_frac": round(it_bytes / t_it / 1e9 / HBM_PEAK_GBPS, 4),
         "iteration_survey_frac": round(sb / t_it / 1e9 / HBM_PEAK_GBPS, 4),
         "kernels": kernels,
+        "rate_repeats": repeats,
+        "copy_ceiling": {**copy, "transform_measure_frac": round(dom["gbps"] / copy["gbps"], 4),
+                         "iteration_frac": round(it_bytes / t_it / 1e9 / copy["gbps"], 4)},
         **line_extra,
         "cpu_baseline": cpu,
         "oracle_time_to_theta": oracle_ttt,
