@@ -498,7 +498,7 @@ def copy_ceiling(torch, mib=1024, reps=5):
     return {"mib": mib, "gbps": round(2 * n * 8 / (best * 1e-3) / 1e9, 1)}
 
 
-def oracle_time_to_theta(small, med, big=None):
+def oracle_time_to_theta(small, med, big=None, long_run=False):
     import oracle
     nproc = oracle.threads()
     out = {"nproc": nproc}
@@ -512,6 +512,9 @@ def oracle_time_to_theta(small, med, big=None):
     cases = [("8^4", SMALL_DIMS, small), ("16^4", MIXED16_DIMS, med)]
     if big is not None:
         cases.append(("x".join(map(str, HEADLINE_DIMS)), HEADLINE_DIMS, big))
+    if long_run:
+        import synth
+        cases.append(("x".join(map(str, LEARNED_DIMS)), LEARNED_DIMS, synth.random_links(LEARNED_DIMS, 3000)))
     for label, dims, U in cases:
         t = time.perf_counter()
         _, it, F, th, ok, _ = oracle.fix(dims, U)
@@ -550,6 +553,8 @@ def main():
                     help="for hardware counters: a few iterations, then one plain device copy of "
                          "--copy-mib MiB (a kernel of known traffic that scales FETCH_SIZE/WRITE_SIZE); no JSON")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--oracle-long", action="store_true",
+                    help="also time the oracle's full fix at 32^3x64 (seed 3000, about 25 s of CPU work)")
     ap.add_argument("--batch-sample", action="store_true",
                     help="run only the batch of 64 (one lgf_batch fix, then the lattices one by one) and print "
                          "its JSON; for profiling")
@@ -605,7 +610,7 @@ def main():
         cpu = cpu_baseline(U, args.storage, HEADLINE_DIMS)
         print(f"# cpu baseline: {cpu['value']} iters/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
         if extras:
-            oracle_ttt = oracle_time_to_theta(small, med, U)
+            oracle_ttt = oracle_time_to_theta(small, med, U, args.oracle_long)
             oracle_F8 = oracle_ttt["8^4"]["F"]
     elif extras:
         import oracle
