@@ -85,7 +85,7 @@ def alg_bytes(V, s, R):
     }
 
 
-def survey_bytes(V, s, R, with_G=False):
+def rewrite_design_bytes(V, s, R, with_G=False):
     """The reference byte count of one iteration of a design that reads and
     rewrites the links: V s (8R + 2R_g + 32), R_g = R; the FP32 phase of a
     mixed run adds the accumulated gauge (+2R_g)."""
@@ -205,12 +205,12 @@ def per_precision(L, U, args, torch):
             rate, t_it, prof, _ = rate_and_kernels(L, HEADLINE_DIMS, U, args.steps, args.warmup, torch,
                                                    precision=prec, storage=R)
             ab = alg_bytes(V, s, R)
-            sb = survey_bytes(V, s, R, with_G=(s == 4))
+            sb = rewrite_design_bytes(V, s, R, with_G=(s == 4))
             out[f"{pname}_{R}real"] = {
                 "iters_per_s": round(rate, 2), "ms_per_iter": round(t_it * 1e3, 4),
                 "iteration_alg_bytes": ab["iteration"],
                 "iteration_frac": round(ab["iteration"] / t_it / 1e9 / HBM_PEAK_GBPS, 4),
-                "survey_bytes": sb, "survey_frac": round(sb / t_it / 1e9 / HBM_PEAK_GBPS, 4),
+                "rewrite_design_bytes": sb, "rewrite_design_frac": round(sb / t_it / 1e9 / HBM_PEAK_GBPS, 4),
                 "kernels": kernel_table(prof, ab)}
             print(f"# {pname} {R}-real: {rate:.1f} iters/s", file=sys.stderr, flush=True)
     return out
@@ -688,7 +688,7 @@ def main():
               flush=True)
 
     it_bytes = ab["iteration"]
-    sb = survey_bytes(V, 8, R)
+    sb = rewrite_design_bytes(V, 8, R)
     line = {
         "metric": "FA-SD iters/s and time to theta<1e-15 on 32^4 SU(3); HBM GB/s; learned vs plain",
         "value": round(iters_per_s, 2),
@@ -711,7 +711,7 @@ def main():
                      "kernel": "transform_measure", "alg_bytes_per_launch": ab["transform_measure"]},
         "iteration_alg_gbps": round(it_bytes / t_it / 1e9, 1),
         "iteration_frac": round(it_bytes / t_it / 1e9 / HBM_PEAK_GBPS, 4),
-        "iteration_survey_frac": round(sb / t_it / 1e9 / HBM_PEAK_GBPS, 4),
+        "iteration_rewrite_design_frac": round(sb / t_it / 1e9 / HBM_PEAK_GBPS, 4),
         "kernels": kernels,
         "rate_repeats": repeats,
         "copy_ceiling": {**copy, "transform_measure_frac": round(dom["gbps"] / copy["gbps"], 4),
