@@ -21,6 +21,8 @@ resident in HBM.  Printed as one JSON line:
   batch            64 lattices of three shapes in one lgf_batch (mixed), with
                    its aggregate algorithmic bandwidth, against the same
                    lattices fixed one by one in single contexts
+  rate_32x32x32x64 the iteration rate and kernel times at 32^3x64 (seed 3000),
+                   FP64, 12-real: the second HBM-resident shape
   learned_vs_plain 32^3x64, seeds 3000-3003: the committed learned step
                    against the plain step
   update_variants  16^4: iterations and time to theta for first-order and
@@ -214,6 +216,19 @@ def per_precision(L, U, args, torch):
                 "kernels": kernel_table(prof, ab)}
             print(f"# {pname} {R}-real: {rate:.1f} iters/s", file=sys.stderr, flush=True)
     return out
+
+
+def rate_32x64(L, U, args, torch):
+    """The other HBM point: iteration rate and kernel times at 32^3 x 64 (seed
+    3000), FP64, 12-real, as the headline measures 32^4."""
+    V = vol(LEARNED_DIMS)
+    rate, t_it, prof, _ = rate_and_kernels(L, LEARNED_DIMS, U, args.steps, args.warmup, torch, storage=12)
+    ab = alg_bytes(V, 8, 12)
+    print(f"# 32^3x64 FP64 12-real: {rate:.1f} iters/s", file=sys.stderr, flush=True)
+    return {"dims": list(LEARNED_DIMS), "storage": 12, "seed": 3000, "iters_per_s": round(rate, 2),
+            "ms_per_iter": round(t_it * 1e3, 4), "iteration_alg_bytes": ab["iteration"],
+            "iteration_frac": round(ab["iteration"] / t_it / 1e9 / HBM_PEAK_GBPS, 4),
+            "kernels": kernel_table(prof, ab)}
 
 
 def time_to_theta_32(L, fields, torch):
@@ -673,6 +688,7 @@ def main():
         line_extra["update_variants"] = update_variants(L, med, torch)
         line_extra["fft_study"] = fft_study_32(L, torch, kernels)
         if learned_fields:
+            line_extra["rate_32x32x32x64"] = rate_32x64(L, learned_fields[0][1], args, torch)
             with open(model_path, "rb") as fh:
                 blob = fh.read()
             line_extra["learned_vs_plain"] = learned_vs_plain(L, learned_fields, blob, torch)
