@@ -15,7 +15,8 @@ resident in HBM.  Printed as one JSON line:
                    FP64 and FP32, 12- and 18-real links
   time_to_theta    32^4, seeds 1-4: wall time of lgf_fix to theta < 1e-15 from
                    freshly loaded links (Algorithm 1's first measurement
-                   included) for FP64 and mixed FP32/FP64, 12- and 18-real
+                   included) for FP64 and mixed FP32/FP64, 12- and 18-real,
+                   and mixed 12-real with the switch to FP64 at theta 1e-12
   small_8          8^4: iteration rate and time to theta, F against the oracle
   mixed_16         16^4, seeds 1-4: plain FP64 against FP32 bulk + FP64 finish
   batch            64 lattices of three shapes in one lgf_batch (mixed), with
@@ -31,8 +32,9 @@ resident in HBM.  Printed as one JSON line:
   wilson_32        the paper's workload class: Wilson-action fields at 32^4,
                    beta 5.8, 6.0, 6.2 (cold start, 102 updates of one heatbath
                    and four overrelaxation sweeps, all on the GPU), their
-                   plaquette and time to theta for FP64, mixed and learned
-                   (and an alpha sweep at beta 6.0), then three more fields
+                   plaquette and time to theta for FP64, mixed (switch to
+                   FP64 at theta 1e-6, 1e-10, 1e-12) and learned (and an
+                   alpha sweep at beta 6.0), then three more fields
                    per beta in FP64 (four per beta, as in Table 3); heatbath and
                    overrelaxation sweep times with the
                    algorithmic bytes of a sweep (every link read and each
@@ -235,7 +237,8 @@ def time_to_theta_32(L, fields, torch):
     from paper_1206_0675_amd import lgf
     modes = (("fp64_12real", dict(storage=12)), ("fp64_18real", dict(storage=18)),
              ("mixed_12real", dict(storage=12, precision=lgf.MIXED)),
-             ("mixed_18real", dict(storage=18, precision=lgf.MIXED)))
+             ("mixed_18real", dict(storage=18, precision=lgf.MIXED)),
+             ("mixed_12real_switch_1e-12", dict(storage=12, precision=lgf.MIXED, theta_switch=1e-12)))
     out = {label: [] for label, _ in modes}
     for seed, U in fields:
         for label, kw in modes:
@@ -379,6 +382,15 @@ def wilson_32(L, blob, torch):
                               "theta": s.theta, "F": s.F}
                 if "step" in kw:
                     rec[label]["fallbacks"] = s.fallbacks
+            # the mixed run's switch to FP64 taken later than the default theta = 1e-6
+            for ts in (1e-10, 1e-12):
+                with lgf.Context(HEADLINE_DIMS, lib=L, max_iter=100000, storage=12, precision=lgf.MIXED,
+                                 theta_switch=ts) as ctx:
+                    ctx.load_device(g.device_links)
+                    torch.cuda.synchronize()
+                    s = ctx.fix(raise_on_error=False)
+                rec[f"mixed_12real_switch_{ts:g}"] = {"status": s.status, "iters": s.iter, "iters_fp32": s.iter_fp32,
+                                                      "seconds": round(s.seconds, 4), "F": s.F}
             if i == 1:
                 sweep = []
                 for alpha in (0.06, 0.07, 0.075, 0.08):

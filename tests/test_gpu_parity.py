@@ -145,17 +145,22 @@ def test_step_zero_is_measure(L, oracle_lib):
 # ---------------------------------------------------------------------------
 # precision
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("dims, seed", [((16, 16, 16, 16), 1), ((16, 16, 16, 16), 4)])
-def test_mixed_precision_final_F(L, oracle_lib, dims, seed):
+@pytest.mark.parametrize("dims, seed, switch", [((16, 16, 16, 16), 1, 1e-6), ((16, 16, 16, 16), 4, 1e-6),
+                                                ((16, 16, 16, 16), 2, 1e-12)])
+def test_mixed_precision_final_F(L, oracle_lib, dims, seed, switch):
+    """FP32 bulk, FP64 finish: the FP64 oracle's F to 1e-9, also when the
+    FP32 phase runs down to theta = 1e-12, a few decades above where FP32
+    rounding of the links stops it."""
     U = links(dims, seed)
-    announce(f"mixed {dims} seed {seed}")
-    with lgf.Context(dims, lib=L, precision=lgf.MIXED, storage=12, poll_every=4) as ctx:
+    announce(f"mixed {dims} seed {seed} switch {switch:g}")
+    with lgf.Context(dims, lib=L, precision=lgf.MIXED, storage=12, poll_every=4, theta_switch=switch) as ctx:
         ctx.load(U)
         s = ctx.fix()
         Ug, G = ctx.store(), ctx.store_gauge()
     _, it, F, th, ok, _ = oracle.fix(dims, U)
     assert s.theta < 1e-15 and s.iter_fp32 > 0 and s.iter_fp64 > 0
     assert abs(s.F - F) <= 1e-9
+    assert abs(s.iter - it) <= 2
     assert abs(oracle.plaquette(dims, Ug) - oracle.plaquette(dims, U)) <= 1e-12
     assert rel(oracle.transform(dims, U, G), Ug) <= 1e-12
 
