@@ -177,7 +177,11 @@ int32_t lgf_step(lgf_ctx ctx, int64_t n, lgf_stats *trace);
 /* Algorithm 1: iterate until theta < theta_stop (LGF_OK) or max_iter
  * (LGF_E_NOT_CONVERGED).  theta is read back every poll_every iterations;
  * iterations queued after convergence do nothing.  In LGF_MIXED the FP32
- * phase ends at theta < theta_switch and the run finishes in FP64. */
+ * phase ends at theta < theta_switch, or once theta has not halved for 512
+ * iterations (read at the polls: FP32 rounding of the links stops theta,
+ * near 1e-14 at 32^4, so a theta_switch below that still ends the phase),
+ * and the run finishes in FP64.  lgf_fix_batch and lgf_batch_fix switch at
+ * theta_switch only. */
 int32_t lgf_fix(lgf_ctx ctx, lgf_stats *out);
 
 /* ---------------------------------------------------------------------------

@@ -118,6 +118,12 @@ struct lgf_context : Runner {
 
 namespace {
 
+// lgf_fix in LGF_MIXED: updates without theta halving after which the FP32
+// phase ends even above theta_switch (FP32 rounding of the links stops theta
+// near 1e-14 at 32^4; a switch set below that would otherwise run the FP32
+// phase to max_iter).
+constexpr int64_t kFp32StallIters = 512;
+
 template <typename T>
 Bufs<T>& bufs(lgf_context* c);
 template <>
@@ -1093,10 +1099,25 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
         TRY(set_stop(c, stop));
         if (!c->delta_valid) TRY(measure_any(c, nullptr));
         TRY(sync_state(c));
+        // FP32 phase: theta_switch may lie below where FP32 rounding of the
+        // links stops theta; the phase also ends once theta has not halved
+        // for kFp32StallIters updates, and the run goes on in FP64
+        double best = c->st_host->theta;
+        int64_t best_iter = c->st_host->iter;
+        bool stalled = false;
         while (!c->st_host->done && c->st_host->iter < c->p.max_iter) {
             const int64_t chunk = std::min<int64_t>(c->p.poll_every, c->p.max_iter - c->st_host->iter);
             TRY(enqueue_chunk(c, chunk));
             TRY(sync_state(c));
+            if (fp32_mixed && !c->st_host->done) {
+                if (c->st_host->theta < 0.5 * best) {
+                    best = c->st_host->theta;
+                    best_iter = c->st_host->iter;
+                } else if (c->st_host->iter - best_iter >= kFp32StallIters) {
+                    stalled = true;
+                    break;
+                }
+            }
         }
         // a captured chunk that ended done has transformed D after the last
         // reduction (k_zt_reduce), so D no longer holds the current Delta
@@ -1105,7 +1126,7 @@ int32_t lgf_fix(lgf_ctx c, lgf_stats* out)
             fill_stats(c, out, LGF_E_NONFINITE, t0);
             return fail(c, LGF_E_NONFINITE, "theta became non-finite");
         }
-        if (!c->st_host->done) {
+        if (!c->st_host->done && !stalled) {
             fill_stats(c, out, LGF_E_NOT_CONVERGED, t0);
             return fail(c, LGF_E_NOT_CONVERGED, "max_iter reached");
         }

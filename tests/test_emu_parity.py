@@ -92,6 +92,20 @@ def test_emulated_fix_and_mixed(E, oracle_lib):
     assert np.max(np.abs(oracle.transform(dims, U, G) - m.store())) < 1e-12
 
 
+def test_emulated_mixed_switch_below_the_fp32_floor(E, oracle_lib):
+    """theta_switch below anything FP32 can reach: the FP32 phase ends after
+    512 updates without theta halving, and FP64 finishes on the oracle's F."""
+    dims = (4, 4, 4, 8)
+    U = synth.random_links(dims, 3)
+    _, it, F, th, ok, _ = oracle.fix(dims, U)
+    with lgf.Context(dims, lib=E, precision=lgf.MIXED, storage=12, theta_switch=1e-18) as m:
+        m.load(U)
+        s = m.fix()
+    assert s.status == 0 and s.theta < 1e-15 and s.iter == s.iter_fp32 + s.iter_fp64
+    assert s.iter_fp32 >= 512 and 0 < s.iter_fp64 < it
+    assert abs(s.F - F) <= 1e-9
+
+
 def test_emulated_checkpoint_resume(E, oracle_lib):
     """A checkpoint is the loaded links and G: loading both resumes the run
     bit for bit, and the links are G U0 G^dag(x+mu) from the moment G is

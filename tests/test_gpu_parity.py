@@ -165,6 +165,22 @@ def test_mixed_precision_final_F(L, oracle_lib, dims, seed, switch):
     assert rel(oracle.transform(dims, U, G), Ug) <= 1e-12
 
 
+def test_mixed_switch_below_the_fp32_floor(L, oracle_lib):
+    """A switch point FP32 arithmetic cannot reach: the FP32 phase ends once
+    theta has stopped halving for 512 updates, and the FP64 phase converges
+    to the oracle's maximum."""
+    dims = (16, 16, 16, 16)
+    U = links(dims, 3)
+    announce(f"mixed {dims} switch below the FP32 floor")
+    with lgf.Context(dims, lib=L, precision=lgf.MIXED, storage=12, theta_switch=1e-18) as ctx:
+        ctx.load(U)
+        s = ctx.fix()
+    _, it, F, th, ok, _ = oracle.fix(dims, U)
+    assert ok and s.status == 0 and s.theta < 1e-15
+    assert s.iter_fp32 >= 512 and 0 < s.iter_fp64 < it
+    assert abs(s.F - F) <= 1e-9
+
+
 def test_fp32_error_bound(L, oracle_lib):
     dims = (16, 16, 16, 16)
     U = links(dims)
